@@ -1,0 +1,288 @@
+"""Seeded synthetic inputs shaped like the paper's 640x480 RGB-D workloads.
+
+The paper evaluates on TUM RGB-D fr3/walking and BONN (Sec. V-A); neither is
+available here, so scenes are drawn from fixed distributions instead: static
+Gaussians uniform in the camera frustum volume (depth 0.5-4 m), plus
+axis-aligned boxes that move between frames (the dynamic objects).
+
+This module holds none of the method's arithmetic (no projection, rendering,
+loss or MP update). It only draws parameters, camera poses, masks and
+per-pixel fields with numpy's PCG64, so the oracle and the GPU path can be fed
+bit-identical inputs. Every array it returns is float32/int32/uint32.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+Z_NEAR = 0.2
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def intrinsics(width: int, height: int):
+    """Pinhole intrinsics with the same field of view at every resolution:
+    fx = fy = W / 1.28, principal point at the image centre (64x48 gives 50, 32, 24)."""
+    f = width / 1.28
+    return f, f, width / 2.0, height / 2.0
+
+
+def camera(width: int, height: int, T_cw=None) -> dict:
+    fx, fy, cx, cy = intrinsics(width, height)
+    if T_cw is None:
+        T_cw = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
+    return dict(width=int(width), height=int(height), fx=fx, fy=fy, cx=cx, cy=cy,
+                z_near=Z_NEAR, T_cw=np.asarray(T_cw, dtype=np.float32).reshape(3, 4))
+
+
+def _axis_angle_matrix(axis, angle):
+    axis = np.asarray(axis, dtype=np.float64)
+    axis = axis / np.linalg.norm(axis)
+    x, y, z = axis
+    K = np.array([[0, -z, y], [z, 0, -x], [-y, x, 0]])
+    return np.eye(3) + np.sin(angle) * K + (1 - np.cos(angle)) * (K @ K)
+
+
+def perturbed_pose(rng, deg=1.0, trans=0.02, base=None):
+    """A pose offset from `base` by `deg` degrees about a random axis and `trans`
+    metres along a random direction (both applied on the world->camera side)."""
+    if base is None:
+        base = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
+    base = np.asarray(base, dtype=np.float64)
+    axis = rng.normal(size=3)
+    R = _axis_angle_matrix(axis, np.deg2rad(deg))
+    d = rng.normal(size=3)
+    d = trans * d / np.linalg.norm(d)
+    Rn = R @ base[:, :3]
+    tn = R @ base[:, 3] + d
+    return np.concatenate([Rn, tn[:, None]], axis=1).astype(np.float32)
+
+
+def _depth_volume_uniform(rng, n, zmin, zmax):
+    # density proportional to z^2 on [zmin, zmax]: uniform in frustum volume
+    u = rng.random(n)
+    return np.cbrt(zmin ** 3 + u * (zmax ** 3 - zmin ** 3))
+
+
+def static_gaussians(rng, n, width, height, zmin=0.5, zmax=4.0, mp=None) -> dict:
+    """n Gaussians seen by an identity-pose camera: pixel position uniform in the
+    image, depth uniform in volume, log-scale N(-3, 0.5^2) per axis, random unit
+    quaternion (w,x,y,z), opacity logit N(0,1), RGB U[0,1], MP U[0,1]."""
+    fx, fy, cx, cy = intrinsics(width, height)
+    px = rng.random(n) * width
+    py = rng.random(n) * height
+    z = _depth_volume_uniform(rng, n, zmin, zmax)
+    mean = np.stack([z * (px - cx) / fx, z * (py - cy) / fy, z])
+    log_scale = rng.normal(-3.0, 0.5, size=(3, n))
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    opl = rng.normal(0.0, 1.0, size=n)
+    color = rng.random((3, n))
+    m = rng.random(n) if mp is None else np.full(n, mp)
+    return _pack(mean, log_scale, q, opl, color, m)
+
+
+def _pack(mean, log_scale, quat, opl, color, mp):
+    f = np.float32
+    return dict(mean=np.ascontiguousarray(mean, f), log_scale=np.ascontiguousarray(log_scale, f),
+                quat=np.ascontiguousarray(quat, f), opacity_logit=np.ascontiguousarray(opl, f),
+                color=np.ascontiguousarray(color, f), mp=np.ascontiguousarray(mp, f))
+
+
+def concat_gaussians(parts) -> dict:
+    keys = ["mean", "log_scale", "quat", "opacity_logit", "color", "mp"]
+    return {k: np.ascontiguousarray(np.concatenate([p[k] for p in parts], axis=-1)) for k in keys}
+
+
+def n_gaussians(g) -> int:
+    return int(g["opacity_logit"].shape[0])
+
+
+# ---------------------------------------------------------------- moving boxes
+def random_boxes(rng, n_boxes, width, height):
+    """Axis-aligned boxes, sides U[0.2, 0.5] m, centre depth U[1, 3] m, centre
+    pixel uniform in the inner 80% of the image (identity-pose camera)."""
+    fx, fy, cx, cy = intrinsics(width, height)
+    boxes = []
+    for _ in range(n_boxes):
+        z = rng.uniform(1.0, 3.0)
+        px = rng.uniform(0.1, 0.9) * width
+        py = rng.uniform(0.1, 0.9) * height
+        centre = np.array([z * (px - cx) / fx, z * (py - cy) / fy, z])
+        sides = rng.uniform(0.2, 0.5, size=3)
+        base = rng.random(3)
+        boxes.append(dict(centre=centre, sides=sides, color=base))
+    return boxes
+
+
+def box_gaussians(rng, box, n) -> dict:
+    """n Gaussians with means uniform on the box faces, log-scale N(-4, 0.3^2),
+    opacity logit N(4, 0.5^2), colour = box base colour + N(0, 0.02^2), MP = 1."""
+    c, s = box["centre"], box["sides"]
+    face = rng.integers(0, 6, size=n)
+    axis = face // 2
+    sign = np.where(face % 2 == 0, -1.0, 1.0)
+    local = (rng.random((3, n)) - 0.5) * s[:, None]
+    local[axis, np.arange(n)] = sign * s[axis] / 2
+    mean = c[:, None] + local
+    log_scale = rng.normal(-4.0, 0.3, size=(3, n))
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    opl = rng.normal(4.0, 0.5, size=n)
+    color = np.clip(box["color"][:, None] + rng.normal(0, 0.02, size=(3, n)), 0, 1)
+    return _pack(mean, log_scale, q, opl, color, np.ones(n))
+
+
+def move_boxes(rng, boxes):
+    """Each box moves U[0.05, 0.20] m along a random signed coordinate axis."""
+    out = []
+    for b in boxes:
+        d = np.zeros(3)
+        d[rng.integers(0, 3)] = rng.choice([-1.0, 1.0]) * rng.uniform(0.05, 0.20)
+        nb = dict(b)
+        nb["centre"] = b["centre"] + d
+        out.append(nb)
+    return out
+
+
+def translate_gaussians(g, sl, delta) -> dict:
+    out = {k: v.copy() for k, v in g.items()}
+    out["mean"][:, sl] += np.asarray(delta, dtype=np.float32)[:, None]
+    return out
+
+
+# ---------------------------------------------------------------- configurations
+def tiny_scene(seed=1, n=2000, width=64, height=48):
+    """64x48 pinhole (fx=fy=50, cx=32, cy=24), 2,000 Gaussians; the target view
+    is 1 degree about a random axis and 2 cm away from the rendered view."""
+    rng = rng_for(seed)
+    g = static_gaussians(rng, n, width, height)
+    cam = camera(width, height)
+    target_cam = camera(width, height, perturbed_pose(rng))
+    return g, cam, target_cam
+
+
+def moving_box_scene(seed, n, width, height, n_boxes=3, box_frac=0.05):
+    """Static Gaussians plus `n_boxes` boxes that hold `box_frac` of the
+    Gaussians. Returns (gaussians, camera, target camera, target gaussians,
+    box slices); the target copy has the boxes moved, as in a new frame."""
+    rng = rng_for(seed)
+    nb_total = int(round(n * box_frac)) if n_boxes > 0 else 0
+    g_static = static_gaussians(rng, n - nb_total, width, height)
+    parts, slices, start = [g_static], [], n - nb_total
+    boxes = random_boxes(rng, n_boxes, width, height)
+    per = [nb_total // max(n_boxes, 1)] * n_boxes
+    if n_boxes:
+        per[-1] += nb_total - sum(per)
+    for b, k in zip(boxes, per):
+        parts.append(box_gaussians(rng, b, k))
+        slices.append(slice(start, start + k))
+        start += k
+    g = concat_gaussians(parts)
+    g["mp"][: n - nb_total] = rng.random(n - nb_total).astype(np.float32)
+    moved = move_boxes(rng, boxes)
+    g_target = g
+    for b0, b1, sl in zip(boxes, moved, slices):
+        g_target = translate_gaussians(g_target, sl, b1["centre"] - b0["centre"])
+    cam = camera(width, height)
+    # camera motion per frame: 1 cm and 0.5 degree in random directions
+    target_cam = camera(width, height, perturbed_pose(rng, deg=0.5, trans=0.01))
+    return g, cam, target_cam, g_target, slices
+
+
+def window_cameras(seed, n_views, width, height, spacing=5):
+    """Keyframe poses along a random walk of 1 cm / 0.5 degree per frame,
+    one keyframe every `spacing` frames."""
+    rng = rng_for(seed)
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
+    cams = []
+    for v in range(n_views):
+        cams.append(camera(width, height, pose))
+        for _ in range(spacing):
+            pose = perturbed_pose(rng, deg=0.5, trans=0.01, base=pose)
+    return cams
+
+
+# ---------------------------------------------------------------- MP-update inputs
+def mp_frame_inputs(seed, n, width, height, n_inst=3, invalid_frac=0.05, cull_frac=0.05):
+    """Per-pixel and per-Gaussian inputs of one MP update, drawn directly:
+    rendered depth/colour, observed depth (with holes = 0), an instance-id map of
+    `n_inst` rectangles, per-instance prior/confidence tables, projected means
+    (some outside the image), a culled flag and the previous MP state."""
+    rng = rng_for(seed)
+    P = width * height
+    yy, xx = np.mgrid[0:height, 0:width]
+    depth = (1.0 + 2.0 * rng.random()) + 0.3 * np.sin(xx / 7.0 + rng.random() * 6) * np.cos(yy / 5.0)
+    depth = depth + rng.normal(0, 0.01, size=depth.shape)
+    inst = np.zeros((height, width), np.int32)
+    obs = depth + rng.normal(0, 0.01, size=depth.shape)
+    for k in range(1, n_inst + 1):
+        w = rng.integers(max(2, width // 8), max(3, width // 3))
+        h = rng.integers(max(2, height // 8), max(3, height // 3))
+        x0 = rng.integers(0, width - w)
+        y0 = rng.integers(0, height - h)
+        inst[y0:y0 + h, x0:x0 + w] = k
+        # a moving object: the observation differs from the render inside it
+        obs[y0:y0 + h, x0:x0 + w] += rng.uniform(0.05, 0.2) * (1 + 0.5 * rng.random((h, w)))
+    holes = rng.random(depth.shape) < invalid_frac
+    obs[holes] = 0.0
+    color = rng.random((3, height, width))
+    tcolor = np.clip(color + rng.normal(0, 0.05, size=color.shape), 0, 1)
+    prior = np.concatenate([[0.05], rng.uniform(0.6, 0.95, size=n_inst)])
+    conf = np.concatenate([[0.1], rng.uniform(0.5, 0.95, size=n_inst)])
+    mean2d = np.stack([rng.uniform(-3, width + 3, size=n), rng.uniform(-3, height + 3, size=n)])
+    culled = rng.random(n) < cull_frac
+    mp_prev = rng.random(n)
+    f = np.float32
+    return dict(width=width, height=height,
+                depth=np.ascontiguousarray(depth.reshape(P), f),
+                color=np.ascontiguousarray(color.reshape(3, P), f),
+                target_depth=np.ascontiguousarray(obs.reshape(P), f),
+                target_color=np.ascontiguousarray(tcolor.reshape(3, P), f),
+                instance_id=np.ascontiguousarray(inst.reshape(P), np.int32),
+                inst_prior=prior.astype(f), inst_conf=conf.astype(f),
+                mean2d=np.ascontiguousarray(mean2d, f),
+                culled=culled, mp=mp_prev.astype(f))
+
+
+def bin_inputs(seed, m, width, height, tile=16, cull_frac=0.1, max_tiles=6):
+    """Synthetic per-Gaussian binning inputs: an inclusive tile rectangle and a
+    depth key (IEEE bits of a positive float depth, 0xFFFFFFFF when culled).
+    Depths are drawn on a coarse grid so equal keys (ties) occur."""
+    rng = rng_for(seed)
+    gx = (width + tile - 1) // tile
+    gy = (height + tile - 1) // tile
+    x0 = rng.integers(-2, gx + 1, size=m)
+    y0 = rng.integers(-2, gy + 1, size=m)
+    x1 = x0 + rng.integers(0, max_tiles, size=m)
+    y1 = y0 + rng.integers(0, max_tiles, size=m)
+    x0c, y0c = np.maximum(x0, 0), np.maximum(y0, 0)
+    x1c, y1c = np.minimum(x1, gx - 1), np.minimum(y1, gy - 1)
+    z = (0.5 + np.floor(rng.random(m) * 512) / 128.0).astype(np.float32)
+    key = z.view(np.uint32).copy()
+    culled = rng.random(m) < cull_frac
+    empty = (x0c > x1c) | (y0c > y1c) | culled
+    key[empty] = 0xFFFFFFFF
+    rect = np.stack([x0c, y0c, x1c, y1c]).astype(np.int16)
+    rect[0, empty] = 1
+    rect[2, empty] = 0
+    rect[1, empty] = 1
+    rect[3, empty] = 0
+    return np.ascontiguousarray(rect.T), key
+
+
+def mlp_inputs(seed, P, hidden=32, n_in=8):
+    """Per-pixel MLP features and labels in plausible ranges, plus FP32 master
+    weights drawn with a He-style scale."""
+    rng = rng_for(seed)
+    x = rng.normal(0, 1, size=(n_in, P)).astype(np.float32)
+    label = rng.random(P).astype(np.float32)
+    W1 = (rng.normal(0, 1, (hidden, n_in)) * np.sqrt(2.0 / n_in)).astype(np.float32)
+    b1 = (rng.normal(0, 0.1, hidden)).astype(np.float32)
+    W2 = (rng.normal(0, 1, (hidden, hidden)) * np.sqrt(2.0 / hidden)).astype(np.float32)
+    b2 = (rng.normal(0, 0.1, hidden)).astype(np.float32)
+    W3 = (rng.normal(0, 1, (1, hidden)) * np.sqrt(1.0 / hidden)).astype(np.float32)
+    b3 = np.zeros(1, np.float32)
+    return x, label, dict(W1=W1, b1=b1, W2=W2, b2=b2, W3=W3, b3=b3)
