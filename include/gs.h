@@ -1,0 +1,319 @@
+/*
+ * gs.h - C ABI of the MI355X (gfx950) MP-weighted Gaussian-splatting library.
+ *
+ * The method (DAGS-SLAM, arXiv 2602.21644) renders colour and depth from a
+ * Gaussian map and a camera pose, weights the photometric and depth L1 losses
+ * by a per-pixel static weight built from per-Gaussian motion probabilities
+ * (Sec. IV-D, Eq. (20)-(22), (27)), optimises Gaussians and poses jointly
+ * (Sec. IV-D, "Overall objective"), and keeps the motion probabilities as a
+ * temporally updated state (Sec. IV-A/B, Eq. (1)-(13), (17)).
+ *
+ * The calls, in the order one optimisation iteration uses them:
+ *   gs_project    -> gs_bin_sort -> gs_render_fwd -> gs_loss -> gs_render_bwd
+ * and once per frame gs_mp_update. The learned MP surrogate (not in the paper)
+ * adds gs_mlp_features / gs_mlp_fwd / gs_mlp_train_step.
+ *
+ * Conventions shared by every call
+ *  - Pointers are DEVICE pointers unless marked [host]. The caller owns every
+ *    buffer; the library never allocates, frees or retains caller memory in a
+ *    hot call. Scratch memory is the caller's `ws` of gs_workspace_size bytes.
+ *  - Every hot call only enqueues work on `stream` (a hipStream_t passed as
+ *    void*) and does not synchronise, so it can be captured in a hip graph.
+ *    gs_bins_check is the only call that synchronises.
+ *  - Return codes: GS_OK, or GS_E_ARG (bad argument, checked on the host
+ *    before anything is enqueued), GS_E_UNSUPPORTED (a size beyond the
+ *    library's limits), GS_E_HIP (a launch failed; text in gs_last_error).
+ *    Device-side capacity overflow is reported by the overflow flag of
+ *    gs_bins (kernels after it early-exit) and by gs_bins_check.
+ *  - Layouts: planar float32 structure-of-arrays. A Gaussian attribute with c
+ *    components is stored as c planes of length n: element (c, k) at c*n + k.
+ *    Images are planar per channel over all views: channel c, view v, pixel
+ *    (x, y) at c*P + pix_off(v) + y*W_v + x, with pix_off(v) = sum of W*H of
+ *    earlier views and P the total.
+ *  - Per-view projection records: view v owns records rec_off(v) .. +n_v,
+ *    where n_v is the size of the view's scene and rec_off(v) is the sum of
+ *    earlier views' n rounded up to multiples of 64 (gs_rec_offset).
+ *  - Tiles are 16x16 pixels. View v's tiles are numbered
+ *    tile_base(v) + ty*gx_v + tx (gx_v = ceil(W_v/16)), after all earlier views.
+ *  - Pose convention: T_cw maps world to camera, row-major [R | t]. The pose
+ *    gradient is w.r.t. the twist xi = (rho, phi) of a left perturbation
+ *    T <- Exp(xi) T.
+ *  - Not thread-safe per context; concurrent calls on one context race.
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gs_status;
+enum {
+  GS_OK = 0,
+  GS_E_ARG = 1,
+  GS_E_CAPACITY = 2,
+  GS_E_HIP = 3,
+  GS_E_UNSUPPORTED = 4
+};
+
+#define GS_MAX_VIEWS 32
+#define GS_TILE 16
+
+/* Pinhole camera. 80 bytes, the same layout on host and device. */
+typedef struct gs_camera {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float z_near; /* Gaussians with camera z <= z_near are culled */
+  float pad_;
+  float T_cw[12]; /* world -> camera, row-major 3x4 */
+} gs_camera;
+
+/* A batch of V views over S scenes. All Gaussians of all scenes are packed in
+ * one gs_gaussians; scene s owns [scene_begin[s], scene_begin[s+1]). */
+typedef struct gs_views {
+  int32_t n_views;              /* 1 .. GS_MAX_VIEWS */
+  int32_t n_scenes;             /* >= 1 */
+  int64_t n_gaussians;          /* total Gaussians of all scenes (= gs_gaussians.n) */
+  const gs_camera* cams_host;   /* [host] V cameras: sizes (and values) */
+  const gs_camera* cams_dev;    /* V cameras read by the kernels; poses may be
+                                   updated in place between graph replays */
+  const int32_t* view_scene;    /* [host] V scene ids; NULL = all scene 0 */
+  const int64_t* scene_begin;   /* [host] S+1 offsets; NULL = {0, n_gaussians} */
+} gs_views;
+
+/* Gaussian parameters (planar). Quaternions (w,x,y,z) need not be unit. */
+typedef struct gs_gaussians {
+  int64_t n;                    /* total over all scenes */
+  const float* mean;            /* [3][n] world position */
+  const float* log_scale;       /* [3][n] */
+  const float* quat;            /* [4][n] w, x, y, z */
+  const float* opacity_logit;   /* [n] opacity = sigmoid(logit) */
+  const float* color;           /* [3][n] RGB */
+  const float* mp;              /* [n] motion probability in [0, 1] */
+} gs_gaussians;
+
+/* Projection output, m = gs_rec_count records. `rec`, `rect` and `depth_key`
+ * are required; the planar fields are optional (NULL skips them). */
+typedef struct gs_proj {
+  int64_t m;
+  float* rec;        /* [m][12]: ux, uy, depth, opacity, k1, k2, k3, mp, r, g, b, 0 */
+  int16_t* rect;     /* [m][4] inclusive tile rect x0, y0, x1, y1; empty: x0 > x1 */
+  uint32_t* depth_key; /* [m] IEEE bits of camera z; 0xFFFFFFFF if culled/empty */
+  float* mean2d;     /* [2][m] optional */
+  float* conic;      /* [3][m] optional: inverse 2D covariance (xx, xy, yy) */
+  float* depth;      /* [m] optional */
+  float* opacity;    /* [m] optional */
+  int32_t* radius;   /* [m] optional: opacity-aware support radius in pixels,
+                        0 for culled records */
+} gs_proj;
+
+/* Per-tile lists. Entries are scene-local Gaussian ids; tile t's list is
+ * gauss_id[tile_start[t] .. tile_start[t+1]), ordered by (depth bits, id). */
+typedef struct gs_bins {
+  int64_t capacity;       /* entries gauss_id can hold */
+  uint32_t* gauss_id;     /* [capacity] */
+  uint32_t* tile_start;   /* [T + 1] */
+  uint32_t* sorted_ids;   /* [m] per view, record ids in (depth bits, id) order */
+  int64_t* n_instances;   /* [1] total entries (also when above capacity) */
+  int32_t* overflow;      /* [1] 1 when n_instances > capacity, else 0 */
+  int32_t* incomplete;    /* [1] set by gs_render_fwd when a tile ran out of a
+                             truncated list with unsaturated pixels (see max_rank) */
+  int64_t max_rank;       /* bin only the max_rank nearest records of each view
+                             (<= 0: all). The lists are then exact prefixes of the
+                             full lists. */
+} gs_bins;
+
+/* Rendered maps (planar, see layouts). */
+typedef struct gs_image {
+  float* color;      /* [3][P] C + T * bg */
+  float* depth;      /* [P]  sum alpha T z */
+  float* mp;         /* [P]  sum alpha T m (MP channel) */
+  float* T;          /* [P]  final transmittance */
+  uint32_t* n_last;  /* [P]  list position after the last contributing entry */
+} gs_image;
+
+typedef struct gs_target {
+  const float* color; /* [3][P] */
+  const float* depth; /* [P], 0 = missing observation */
+} gs_target;
+
+typedef struct gs_loss_params {
+  float lambda_pho;    /* 0.9 (Sec. V-A) */
+  float lambda_depth;  /* 0.1 */
+  float eps_A;         /* w = 0 where 1 - T <= eps_A (1e-6) */
+  int32_t weight_mode; /* 0: w = 1 - M/(1-T) (normalised omega); 1: w = (1-T) - M */
+  int32_t grad_through_weight; /* 0: w detached; 1: also emit dmp, dT */
+} gs_loss_params;
+
+typedef struct gs_pixel_grads {
+  float* dcolor; /* [3][P] */
+  float* ddepth; /* [P] */
+  float* dmp;    /* [P] or NULL (treated as 0) */
+  float* dT;     /* [P] or NULL (treated as 0) */
+} gs_pixel_grads;
+
+/* Gradients w.r.t. gs_gaussians fields (same layout) and the pose twists. */
+typedef struct gs_grads {
+  float* mean;          /* [3][n] */
+  float* log_scale;     /* [3][n] */
+  float* quat;          /* [4][n] */
+  float* opacity_logit; /* [n] */
+  float* color;         /* [3][n] */
+  float* pose;          /* [V][6] (rho, phi) */
+  int32_t pose_only;    /* 1: only `pose` is written; the others may be NULL */
+  int32_t accumulate;   /* 1: add to the outputs instead of overwriting */
+} gs_grads;
+
+/* ---------------------------------------------------------------- context */
+typedef struct gs_ctx gs_ctx;
+const char* gs_status_str(gs_status s);
+/* Creates a context on `device` (must be current when calling any op). */
+gs_status gs_ctx_create(int device, gs_ctx** out);
+gs_status gs_ctx_destroy(gs_ctx* ctx);
+const char* gs_last_error(const gs_ctx* ctx);
+/* Tuning knobs (see gs_param_names): render batch, backward batch, binning
+ * chunk. Values outside the supported set return GS_E_ARG. */
+gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
+gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value /*[host]*/);
+
+/* Host-side layout helpers. */
+int64_t gs_rec_offset(const gs_views* views, int32_t view);
+int64_t gs_rec_count(const gs_views* views);
+int64_t gs_tile_count(const gs_views* views);
+int64_t gs_pixel_count(const gs_views* views);
+
+enum { GS_OP_BIN_SORT = 1, GS_OP_RENDER_BWD = 2, GS_OP_LOSS = 3, GS_OP_MP_UPDATE = 4, GS_OP_MLP_TRAIN = 5 };
+/* Scratch bytes needed by `op` for this batch. For
+ * GS_OP_RENDER_BWD the scratch must be zero-filled before its first use; each
+ * call leaves it zero-filled again. */
+gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, size_t* bytes);
+
+/* ---------------------------------------------------------------- the path */
+
+/* EWA projection (the renderer implied by Sec. IV-D, "Pixel-wise static
+ * confidence"): camera mean p = R mu + t, 3D covariance from log-scale and
+ * quaternion, 2D covariance J R Sigma R^T J^T + 0.3 I, conic, pixel mean,
+ * sigmoid opacity, opacity-aware radius ceil(sqrt(2 ln(255 o) lambda_max)),
+ * tile rect of pixels floor(u) -/+ r. Culls non-finite inputs, z <= z_near,
+ * det <= 0, opacity < 1/255. */
+gs_status gs_project(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, gs_proj* proj, void* stream);
+
+/* Tile binning: per-tile lists equal to a stable ascending sort of the keys
+ * (tile << 32 | depth bits) with value id, i.e. lists in (depth, id) order.
+ * Sorts each view's records by depth key (LSD radix), then counts, scans and
+ * scatters tile instances chunk by chunk in that order. */
+gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, gs_bins* bins, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Front-to-back compositing per 16x16 tile: alpha = min(0.99, o exp(p)),
+ * entries with alpha < 1/255 skipped, stop before an entry that drops T below
+ * 1e-4. Writes C + T bg, D, the MP channel M, T and n_last. bg is [host] RGB. */
+gs_status gs_render_fwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                        const gs_bins* bins, const float* bg, gs_image* img, void* stream);
+
+/* MP-weighted loss, Eq. (20)-(22) and the lambda1/lambda2 terms of Eq. (27):
+ * w = 1 - M/(1-T) (0 where 1-T <= eps_A), L_v = lambda_pho sum_u w |C - C_gt|_1
+ * + lambda_depth sum_u w [D_gt>0] |D - D_gt| (sums over pixels). Writes loss[V]
+ * (device, deterministic) and the per-pixel adjoints (sign(0) = 0). */
+gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
+                  const gs_loss_params* params /*[host]*/, float* loss, gs_pixel_grads* pg, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Adjoint of render + projection for the objective sum_v L_v, to all Gaussian
+ * parameters and one pose twist per view (Sec. IV-D: Gaussians and poses are
+ * optimised jointly). Transmittance is recomputed back from T_final. `ws` of
+ * gs_workspace_size(GS_OP_RENDER_BWD), zero-filled before first use. */
+gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                        const gs_bins* bins, const gs_image* img, const gs_pixel_grads* pg, const float* bg,
+                        gs_grads* grads, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream` and reports GS_E_CAPACITY with *required = n_instances
+ * when the lists overflowed; *incomplete = the gs_render_fwd flag. */
+gs_status gs_bins_check(gs_ctx* ctx, const gs_bins* bins, int64_t* required /*[host]*/,
+                        int32_t* incomplete /*[host], nullable*/, void* stream);
+
+/* ---------------------------------------------------------------- MP update */
+typedef struct gs_mp_frame {
+  const int32_t* instance_id; /* [P] 0 = background, 1..K = instance mask id */
+  int32_t n_inst;             /* K, 0 .. 15 */
+  const float* inst_prior;    /* [K+1] mu(cls_k); [0] = mu(bg)   (Eq. 2) */
+  const float* inst_conf;     /* [K+1] c_k; [0] = c_bg           (Eq. 2, 7) */
+  int32_t seg_updated;        /* 1 if the prior was refreshed at this frame (Eq. 17) */
+  const float* mlp_mp;        /* [P] nullable: per-pixel M_p from the surrogate */
+} gs_mp_frame;
+
+typedef struct gs_mp_params {
+  float lambda_e;    /* Eq. (4) */
+  float sigma_small; /* region mean replaces e when sigma_e < sigma_small (Eq. 5 note) */
+  float e_floor;     /* lower bound of e_ub */
+  float sigma_g;     /* Eq. (7) */
+  float sigma_c;     /* Eq. (11) */
+  float lambda_u;    /* Eq. (10) */
+  float eps;         /* Eq. (10) */
+  float alpha_min, alpha_max; /* Eq. (11) */
+  float rho;         /* Eq. (17) */
+  float radius_px;   /* association radius (Eq. 1), <= 4 */
+  float sigma_w;     /* soft association kernel width */
+  float beta_color;  /* photometric share of the residual cue */
+  float prune_above; /* prune flag M > prune_above */
+  float logodds_eps, logodds_max; /* log-odds variant */
+  int32_t mode;      /* 0: exponential smoothing (Eq. 9); 1: log-odds variant */
+  int32_t u_norm;    /* 0: min-max over observed Gaussians; 1: / (ln 2 + lambda_u/4) */
+} gs_mp_params;
+
+typedef struct gs_mp_out {
+  float* U_tilde;    /* [n] normalised uncertainty (0 when unobserved) */
+  float* alpha;      /* [n] rate alpha' used (0 when unobserved) */
+  uint8_t* dynamic;  /* [n] M^t > tau (Eq. 12) */
+  uint8_t* prune;    /* [n] M^t > prune_above */
+  float* M_p;        /* [P] nullable: fused per-pixel MP (Eq. 6) */
+  float* e;          /* [P] nullable: residual cue */
+  float* stats;      /* [8]: U_bar, tau, n_obs, n_dyn, n_prune, U_min, U_max, median */
+} gs_mp_out;
+
+/* One frame of the temporal MP update for a single view (views->n_views = 1).
+ * Region statistics of the residual e = |D - D_gt| + beta |C - C_gt|_1 (Eq. 4),
+ * MP_geo (Eq. 5), fusion with the instance prior (Eq. 2, 6, 7), per-Gaussian
+ * aggregation over valid pixels within radius_px of the projected mean (Eq. 1,
+ * 8), uncertainty and rate (Eq. 10, 11, 17), the state update (Eq. 9 or the
+ * log-odds variant) applied in place to `mp` of the view's scene, then the
+ * lower-median threshold tau = max(median, 0.5) and labels (Eq. 12) and the
+ * frame uncertainty (Eq. 13). `proj` must carry mean2d. */
+gs_status gs_mp_update(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, const gs_image* img,
+                       const gs_target* tgt, const gs_mp_frame* frame, const gs_mp_params* params /*[host]*/,
+                       float* mp, gs_mp_out* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- learned MP surrogate
+ * Not in the paper: a per-pixel MLP 8 -> 32 -> 32 -> 1 (ReLU, sigmoid) that
+ * stands in for the geometric cue. Weights are used as bfloat16 copies of
+ * float32 masters; biases and accumulation are float32. */
+typedef struct gs_mlp {
+  float* master;   /* [1377] float32: W1[32][8], b1[32], W2[32][32], b2[32], W3[32], b3[1] */
+  uint16_t* w_bf16;/* [1312] bfloat16 copies of W1, W2, W3 (round to nearest even) */
+  float* adam_m;   /* [1377] */
+  float* adam_v;   /* [1377] */
+} gs_mlp;
+#define GS_MLP_PARAMS 1377
+#define GS_MLP_WEIGHTS 1312
+
+/* x[8][P] = [C - C_gt (3), (D - D_gt)[D_gt > 0] / 0.1, M, T, D / 4, MP_ins]. */
+gs_status gs_mlp_features(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
+                          const gs_mp_frame* frame, float* x, void* stream);
+/* Refreshes w_bf16 from master (round to nearest even). */
+gs_status gs_mlp_sync(gs_ctx* ctx, gs_mlp* mlp, void* stream);
+/* y[P] = sigmoid(W3 relu(W2 relu(W1 x + b1) + b2) + b3). */
+gs_status gs_mlp_fwd(gs_ctx* ctx, const gs_mlp* mlp, const float* x, float* y, int64_t P, void* stream);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) on the mean binary cross-entropy
+ * against label[P]; `step` is the 1-based step count; loss[1] (device) gets
+ * the loss before the step; grad[1377] (device, nullable) gets the gradient. */
+gs_status gs_mlp_train_step(gs_ctx* ctx, gs_mlp* mlp, const float* x, const float* label, int64_t P,
+                            float lr, int32_t step, float* loss, float* grad, void* ws, size_t ws_bytes,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H_ */

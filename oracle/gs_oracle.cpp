@@ -212,7 +212,10 @@ double composite_pixel(int i, int j, const std::vector<int64_t>& ord, const doub
     if (alpha < 1.0 / 255.0) continue;
     const double Tn = T * (1.0 - alpha);
     margin = std::min(margin, std::fabs(std::log(Tn / 1e-4)));
-    if (prev_z > 0) margin = std::min(margin, std::fabs(depth[k] - prev_z) / depth[k]);
+    // an order swap needs two contributors closer in depth than float32
+    // rounding of z (~1e-7 relative): the gap enters scaled by 10, so pairs
+    // closer than 1e-6 relative fall under the 1e-5 margin
+    if (prev_z > 0) margin = std::min(margin, 10.0 * std::fabs(depth[k] - prev_z) / depth[k]);
     prev_z = depth[k];
     if (Tn < 1e-4) break;
     if (steps) steps->push_back(Step{k, alpha, T, G, araw > 0.99, dx, dy});

@@ -90,31 +90,47 @@ def pixel_mp(e, valid, inst, prior, conf, p):
     return dict(M_p=Mp, mp_geo=mp_geo, mp_ins=mp_ins, gain=gain, mu=mu, sd=sd, cnt=cnt, e_ub=e_ub)
 
 
-def window(mean2d_f32, kept, width, height, valid, radius_px):
-    """Eq. (1) at one scale: for each visible Gaussian, the valid pixels whose
-    centre lies within radius_px of its projected mean. Membership is decided in
-    float32 without fused multiply-add (dx = i - u_x rounded, then dx*dx + dy*dy
-    rounded), the precision the GPU kernel decides it in. Yields (k, pixel
-    indices, float64 squared distances)."""
+def window_aggregate(mean2d_f32, kept, width, height, valid, radius_px, sigma_w, Mp, e):
+    """Eq. (1) and (8) at one scale, for every visible Gaussian at once.
+
+    N(G) = valid pixels whose centre lies within radius_px of the projected
+    mean; membership is decided in float32 without fused multiply-add
+    (dx = i - u_x rounded, then dx*dx + dy*dy rounded), the precision the GPU
+    kernel decides it in. Returns per Gaussian: |N(G)|, the kernel-weighted
+    mean of M_p (weights exp(-d^2 / (2 sigma_w^2)) with float64 distances),
+    the population variance of M_p and the population std of e over N(G)."""
     u = np.asarray(mean2d_f32, np.float32)
+    N = u.shape[1]
     r = np.float32(radius_px)
     r2 = np.float32(r * r)
     vis = np.asarray(kept, bool) & (u[0] >= 0) & (u[0] <= width - 1) & (u[1] >= 0) & (u[1] <= height - 1)
     rr = int(np.ceil(radius_px)) + 1
-    for kk in np.nonzero(vis)[0]:
-        ux, uy = u[0, kk], u[1, kk]
-        cx, cy = int(np.floor(ux)), int(np.floor(uy))
-        xs = np.arange(max(0, cx - rr), min(width - 1, cx + rr) + 1)
-        ys = np.arange(max(0, cy - rr), min(height - 1, cy + rr) + 1)
-        X, Y = np.meshgrid(xs, ys)
-        dx = (X.astype(np.float32) - ux).astype(np.float32)
-        dy = (Y.astype(np.float32) - uy).astype(np.float32)
-        d2 = (dx * dx).astype(np.float32) + (dy * dy).astype(np.float32)
-        idx = (Y * width + X).ravel()
-        sel = (d2.ravel() <= r2) & valid[idx]
-        d2_64 = (X.astype(np.float64) - np.float64(ux)) ** 2 + (Y.astype(np.float64) - np.float64(uy)) ** 2
-        yield kk, idx[sel], d2_64.ravel()[sel], True
-    return
+    cx = np.floor(u[0]).astype(np.int64)
+    cy = np.floor(u[1]).astype(np.int64)
+    offs = [(ox, oy) for oy in range(-rr, rr + 1) for ox in range(-rr, rr + 1)]
+    X = np.stack([cx + ox for ox, oy in offs], axis=1)          # [N, S]
+    Y = np.stack([cy + oy for ox, oy in offs], axis=1)
+    inside = (X >= 0) & (X <= width - 1) & (Y >= 0) & (Y <= height - 1)
+    Xc = np.clip(X, 0, width - 1)
+    Yc = np.clip(Y, 0, height - 1)
+    idx = Yc * width + Xc
+    dx = (Xc.astype(np.float32) - u[0][:, None]).astype(np.float32)
+    dy = (Yc.astype(np.float32) - u[1][:, None]).astype(np.float32)
+    d2 = ((dx * dx).astype(np.float32) + (dy * dy).astype(np.float32)).astype(np.float32)
+    member = inside & (d2 <= r2) & valid[idx] & vis[:, None]
+    n = member.sum(axis=1)
+    d2_64 = (Xc - u[0][:, None].astype(np.float64)) ** 2 + (Yc - u[1][:, None].astype(np.float64)) ** 2
+    w = np.where(member, np.exp(-d2_64 / (2.0 * sigma_w ** 2)), 0.0)
+    m = np.where(member, Mp[idx], 0.0)
+    ev = np.where(member, e[idx], 0.0)
+    nn = np.maximum(n, 1)
+    sw = w.sum(axis=1)
+    M_hat = np.where(n > 0, (w * m).sum(axis=1) / np.where(sw > 0, sw, 1.0), 0.0)
+    mm = m.sum(axis=1) / nn
+    var = np.where(member, (m - mm[:, None]) ** 2, 0.0).sum(axis=1) / nn
+    me = ev.sum(axis=1) / nn
+    sd_e = np.sqrt(np.where(member, (ev - me[:, None]) ** 2, 0.0).sum(axis=1) / nn)
+    return n, M_hat, var, sd_e
 
 
 def mp_update(inp: dict, params: dict | None = None, seg_updated: bool = True, mlp_mp=None) -> dict:
@@ -137,20 +153,8 @@ def mp_update(inp: dict, params: dict | None = None, seg_updated: bool = True, m
     mprev = np.asarray(inp["mp"], np.float64)
     N = mprev.shape[0]
     kept = ~np.asarray(inp["culled"], bool)
-    M_hat = np.zeros(N)
-    var = np.zeros(N)
-    sd_e = np.zeros(N)
-    nobs = np.zeros(N, np.int64)
-    for k, idx, d2, _ in window(inp["mean2d"], kept, W, H, valid, p["radius_px"]):
-        if idx.size == 0:
-            continue
-        w = np.exp(-d2 / (2.0 * p["sigma_w"] ** 2))
-        m = Mp[idx]
-        M_hat[k] = (w * m).sum() / w.sum()               # Eq. (8)
-        var[k] = ((m - m.mean()) ** 2).mean()             # Var{M_p} over N(G)
-        ee = e[idx]
-        sd_e[k] = np.sqrt(((ee - ee.mean()) ** 2).mean())  # sigma_e,G
-        nobs[k] = idx.size
+    nobs, M_hat, var, sd_e = window_aggregate(inp["mean2d"], kept, W, H, valid, p["radius_px"], p["sigma_w"],
+                                              Mp, e)                # Eq. (1), (8)
     observed = nobs > 0
 
     eps = p["eps"]

@@ -1,0 +1,350 @@
+// Host side of the C ABI: argument validation, batch tables, workspace
+// layout and kernel dispatch. Nothing here allocates device memory.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gs_internal.h"
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+gs_status gs_fail(gs_ctx* ctx, gs_status s, const char* fmt, ...) {
+  if (ctx) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+gs_status gs_check_launch(gs_ctx* ctx, const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return gs_fail(ctx, GS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  return GS_OK;
+}
+
+extern "C" {
+
+const char* gs_status_str(gs_status s) {
+  switch (s) {
+    case GS_OK: return "ok";
+    case GS_E_ARG: return "invalid argument";
+    case GS_E_CAPACITY: return "instance capacity exceeded";
+    case GS_E_HIP: return "HIP error";
+    case GS_E_UNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+gs_status gs_ctx_create(int device, gs_ctx** out) {
+  if (!out) return GS_E_ARG;
+  gs_ctx* c = new gs_ctx;
+  c->device = device;
+  c->render_batch = 128;
+  c->bwd_batch = 64;
+  c->bin_chunk = 1024;
+  c->err[0] = 0;
+  *out = c;
+  return GS_OK;
+}
+
+gs_status gs_ctx_destroy(gs_ctx* ctx) {
+  delete ctx;
+  return GS_OK;
+}
+
+const char* gs_last_error(const gs_ctx* ctx) { return ctx ? ctx->err : "null context"; }
+
+gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value) {
+  if (!ctx || !name) return GS_E_ARG;
+  if (!strcmp(name, "render_batch")) {
+    if (value != 64 && value != 128 && value != 256) return gs_fail(ctx, GS_E_ARG, "render_batch: 64|128|256");
+    ctx->render_batch = (int)value;
+  } else if (!strcmp(name, "bwd_batch")) {
+    if (value != 32 && value != 64 && value != 128) return gs_fail(ctx, GS_E_ARG, "bwd_batch: 32|64|128");
+    ctx->bwd_batch = (int)value;
+  } else if (!strcmp(name, "bin_chunk")) {
+    if (value != 256 && value != 512 && value != 1024 && value != 2048)
+      return gs_fail(ctx, GS_E_ARG, "bin_chunk: 256|512|1024|2048");
+    ctx->bin_chunk = (int)value;
+  } else {
+    return gs_fail(ctx, GS_E_ARG, "unknown parameter %s", name);
+  }
+  return GS_OK;
+}
+
+gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) {
+  if (!ctx || !name || !value) return GS_E_ARG;
+  if (!strcmp(name, "render_batch")) *value = ctx->render_batch;
+  else if (!strcmp(name, "bwd_batch")) *value = ctx->bwd_batch;
+  else if (!strcmp(name, "bin_chunk")) *value = ctx->bin_chunk;
+  else return GS_E_ARG;
+  return GS_OK;
+}
+
+}  // extern "C"
+
+// Builds the per-batch table; validates the views.
+static gs_status make_tab(gs_ctx* ctx, const gs_views* vw, ViewTab& tab) {
+  std::memset(&tab, 0, sizeof(tab));
+  if (!vw) return gs_fail(ctx, GS_E_ARG, "views is NULL");
+  const int64_t n_total = vw->n_gaussians;
+  if (vw->n_views < 1 || vw->n_views > GS_MAX_VIEWS)
+    return gs_fail(ctx, GS_E_ARG, "n_views must be in [1, %d]", GS_MAX_VIEWS);
+  if (!vw->cams_host || !vw->cams_dev) return gs_fail(ctx, GS_E_ARG, "cameras are NULL");
+  const int S = vw->n_scenes < 1 ? 1 : vw->n_scenes;
+  if (n_total < 0) return gs_fail(ctx, GS_E_ARG, "n < 0");
+  if (!vw->scene_begin && S != 1) return gs_fail(ctx, GS_E_ARG, "scene_begin required for n_scenes > 1");
+  if (vw->scene_begin) {
+    if (vw->scene_begin[0] != 0 || vw->scene_begin[S] != n_total)
+      return gs_fail(ctx, GS_E_ARG, "scene_begin must run from 0 to n");
+    for (int s = 0; s < S; ++s)
+      if (vw->scene_begin[s + 1] < vw->scene_begin[s]) return gs_fail(ctx, GS_E_ARG, "scene_begin not monotone");
+  }
+  tab.nv = vw->n_views;
+  tab.ng = n_total;
+  int64_t roff = 0, poff = 0;
+  int32_t tb = 0;
+  for (int v = 0; v < tab.nv; ++v) {
+    const int s = vw->view_scene ? vw->view_scene[v] : 0;
+    if (s < 0 || s >= S) return gs_fail(ctx, GS_E_ARG, "view %d: scene %d out of range", v, s);
+    const gs_camera& c = vw->cams_host[v];
+    if (c.width <= 0 || c.height <= 0) return gs_fail(ctx, GS_E_ARG, "view %d: empty image", v);
+    const int gx = (c.width + GS_TILE - 1) / GS_TILE, gy = (c.height + GS_TILE - 1) / GS_TILE;
+    if ((gx + 1) * (gy + 1) > 4096) return gs_fail(ctx, GS_E_UNSUPPORTED, "view %d: image too large", v);
+    const int64_t b = vw->scene_begin ? vw->scene_begin[s] : 0;
+    const int64_t e = vw->scene_begin ? vw->scene_begin[s + 1] : n_total;
+    tab.W[v] = c.width;
+    tab.H[v] = c.height;
+    tab.gx[v] = gx;
+    tab.gy[v] = gy;
+    tab.scene[v] = s;
+    tab.tile_base[v] = tb;
+    tab.n[v] = e - b;
+    tab.npad[v] = (e - b + 63) / 64 * 64;
+    tab.g_off[v] = b;
+    tab.r_off[v] = roff;
+    tab.px_off[v] = poff;
+    roff += tab.npad[v];
+    poff += (int64_t)c.width * c.height;
+    tb += gx * gy;
+  }
+  tab.tile_base[tab.nv] = tb;
+  tab.ntiles = tb;
+  tab.nrec = roff;
+  tab.npix = poff;
+  if (roff >= (int64_t)1 << 32) return gs_fail(ctx, GS_E_UNSUPPORTED, "more than 2^32 records");
+  return GS_OK;
+}
+
+struct BwdWs {
+  size_t g2d, touched, pose, bytes;
+};
+static BwdWs bwd_ws_layout(const ViewTab& tab) {
+  BwdWs L;
+  size_t o = 0;
+  L.g2d = o; o += al256((size_t)tab.nrec * 10 * 4);
+  L.touched = o; o += al256((size_t)tab.nrec);
+  L.pose = o; o += al256((size_t)tab.nv * bwd_pose_blocks(tab) * 6 * 4 + 4);
+  L.bytes = o;
+  return L;
+}
+
+#define GS_TRY(x)                 \
+  do {                            \
+    const gs_status st_ = (x);    \
+    if (st_ != GS_OK) return st_; \
+  } while (0)
+
+extern "C" {
+
+int64_t gs_rec_offset(const gs_views* views, int32_t view) {
+  ViewTab tab;
+  if (make_tab(nullptr, views, tab) != GS_OK || view < 0 || view >= tab.nv) return -1;
+  return tab.r_off[view];
+}
+
+int64_t gs_rec_count(const gs_views* views) {
+  ViewTab tab;
+  if (make_tab(nullptr, views, tab) != GS_OK) return -1;
+  return tab.nrec;
+}
+
+int64_t gs_tile_count(const gs_views* views) {
+  ViewTab tab;
+  if (make_tab(nullptr, views, tab) != GS_OK) return -1;
+  return tab.ntiles;
+}
+
+int64_t gs_pixel_count(const gs_views* views) {
+  if (!views || !views->cams_host || views->n_views < 1) return -1;
+  int64_t p = 0;
+  for (int v = 0; v < views->n_views; ++v) p += (int64_t)views->cams_host[v].width * views->cams_host[v].height;
+  return p;
+}
+
+gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, size_t* bytes) {
+  if (!ctx || !bytes) return GS_E_ARG;
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  switch (op) {
+    case GS_OP_BIN_SORT: {
+      BinTab bt;
+      bin_tab_fill(tab, ctx->bin_chunk, 0, bt);
+      // the smallest chunk gives the largest count matrix
+      BinTab bt2;
+      bin_tab_fill(tab, 256, 0, bt2);
+      const size_t a = bin_ws_layout(tab, bt).bytes, b = bin_ws_layout(tab, bt2).bytes;
+      *bytes = a > b ? a : b;
+      return GS_OK;
+    }
+    case GS_OP_RENDER_BWD: *bytes = bwd_ws_layout(tab).bytes; return GS_OK;
+    case GS_OP_LOSS: *bytes = al256((size_t)tab.nv * loss_blocks(tab) * 8); return GS_OK;
+    case GS_OP_MP_UPDATE:
+      if (tab.nv != 1) return gs_fail(ctx, GS_E_ARG, "mp_update takes one view");
+      *bytes = mp_ws_bytes(tab, tab.npix);
+      return GS_OK;
+    case GS_OP_MLP_TRAIN: *bytes = mlp_ws_bytes(tab.npix); return GS_OK;
+    default: return gs_fail(ctx, GS_E_ARG, "unknown op %d", op);
+  }
+}
+
+gs_status gs_project(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, gs_proj* proj, void* stream) {
+  if (!ctx || !g || !proj) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
+  if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->color || !g->mp))
+    return gs_fail(ctx, GS_E_ARG, "gaussian arrays are NULL");
+  if (!proj->rec || !proj->rect || !proj->depth_key) return gs_fail(ctx, GS_E_ARG, "proj.rec/rect/depth_key NULL");
+  if (proj->m < tab.nrec) return gs_fail(ctx, GS_E_ARG, "proj.m %lld < %lld records", (long long)proj->m,
+                                         (long long)tab.nrec);
+  return launch_project(ctx, tab, views->cams_dev, g, proj, (hipStream_t)stream);
+}
+
+gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, gs_bins* bins, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!ctx || !proj || !bins) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!bins->gauss_id || !bins->tile_start || !bins->sorted_ids || !bins->n_instances || !bins->overflow ||
+      !bins->incomplete)
+    return gs_fail(ctx, GS_E_ARG, "bins arrays NULL");
+  if (bins->capacity < 0 || bins->capacity > ((int64_t)1 << 32)) return gs_fail(ctx, GS_E_ARG, "bad capacity");
+  BinTab bt;
+  bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
+  const BinWs L = bin_ws_layout(tab, bt);
+  if (!ws || ws_bytes < L.bytes)
+    return gs_fail(ctx, GS_E_ARG, "bin_sort workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  return launch_bin_sort(ctx, tab, bt, proj, bins, (char*)ws, (hipStream_t)stream);
+}
+
+gs_status gs_render_fwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                        const gs_bins* bins, const float* bg, gs_image* img, void* stream) {
+  if (!ctx || !g || !proj || !bins || !bg || !img) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!img->color || !img->depth || !img->mp || !img->T || !img->n_last) return gs_fail(ctx, GS_E_ARG, "image NULL");
+  BinTab bt;
+  bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
+  int bits = 0;
+  for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
+  return launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, (hipStream_t)stream);
+}
+
+gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
+                  const gs_loss_params* lp, float* loss, gs_pixel_grads* pg, void* ws, size_t ws_bytes,
+                  void* stream) {
+  if (!ctx || !img || !tgt || !lp || !loss || !pg) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!pg->dcolor || !pg->ddepth) return gs_fail(ctx, GS_E_ARG, "pixel grads NULL");
+  if (lp->weight_mode != 0 && lp->weight_mode != 1) return gs_fail(ctx, GS_E_ARG, "weight_mode 0|1");
+  const size_t need = al256((size_t)tab.nv * loss_blocks(tab) * 8);
+  if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "loss workspace %zu < %zu", ws_bytes, need);
+  return launch_loss(ctx, tab, img, tgt, lp, loss, pg, (double*)ws, (hipStream_t)stream);
+}
+
+gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                        const gs_bins* bins, const gs_image* img, const gs_pixel_grads* pg, const float* bg,
+                        gs_grads* gr, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !g || !proj || !bins || !img || !pg || !bg || !gr) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!gr->pose_only && (!gr->mean || !gr->log_scale || !gr->quat || !gr->opacity_logit || !gr->color))
+    return gs_fail(ctx, GS_E_ARG, "gradient arrays NULL");
+  const BwdWs L = bwd_ws_layout(tab);
+  if (!ws || ws_bytes < L.bytes) return gs_fail(ctx, GS_E_ARG, "render_bwd workspace %zu < %zu", ws_bytes, L.bytes);
+  char* w = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  GS_TRY(launch_render_bwd_tiles(ctx, tab, proj, bins, img, pg, bg, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
+                                 s));
+  return launch_bwd_project(ctx, tab, views->cams_dev, g, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
+                            (float*)(w + L.pose), gr, s);
+}
+
+gs_status gs_bins_check(gs_ctx* ctx, const gs_bins* bins, int64_t* required, int32_t* incomplete, void* stream) {
+  if (!ctx || !bins || !required) return GS_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t n = 0;
+  int32_t of = 0, inc = 0;
+  if (hipStreamSynchronize(s) != hipSuccess) return gs_fail(ctx, GS_E_HIP, "stream sync failed");
+  if (hipMemcpy(&n, bins->n_instances, 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&of, bins->overflow, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&inc, bins->incomplete, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return gs_fail(ctx, GS_E_HIP, "reading bin counters failed");
+  *required = n;
+  if (incomplete) *incomplete = inc;
+  return of ? GS_E_CAPACITY : GS_OK;
+}
+
+gs_status gs_mp_update(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, const gs_image* img,
+                       const gs_target* tgt, const gs_mp_frame* fr, const gs_mp_params* mp_params, float* mp,
+                       gs_mp_out* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !proj || !img || !tgt || !fr || !mp_params || !mp || !out) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (tab.nv != 1) return gs_fail(ctx, GS_E_ARG, "gs_mp_update takes exactly one view");
+  if (!proj->mean2d) return gs_fail(ctx, GS_E_ARG, "proj.mean2d is required");
+  if (fr->n_inst < 0 || fr->n_inst > 15) return gs_fail(ctx, GS_E_UNSUPPORTED, "n_inst must be in [0, 15]");
+  if (!fr->instance_id || !fr->inst_prior || !fr->inst_conf) return gs_fail(ctx, GS_E_ARG, "frame arrays NULL");
+  if (!(mp_params->radius_px >= 0.f && mp_params->radius_px <= 4.f))
+    return gs_fail(ctx, GS_E_UNSUPPORTED, "radius_px must be in [0, 4]");
+  if (!out->U_tilde || !out->alpha || !out->dynamic || !out->prune || !out->stats)
+    return gs_fail(ctx, GS_E_ARG, "mp outputs NULL");
+  const size_t need = mp_ws_bytes(tab, tab.npix);
+  if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "mp_update workspace %zu < %zu", ws_bytes, need);
+  return launch_mp_update(ctx, tab, proj, img, tgt, fr, mp_params, mp, out, (char*)ws, (hipStream_t)stream);
+}
+
+gs_status gs_mlp_features(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
+                          const gs_mp_frame* fr, float* x, void* stream) {
+  if (!ctx || !img || !tgt || !fr || !x) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!fr->instance_id || !fr->inst_prior) return gs_fail(ctx, GS_E_ARG, "frame arrays NULL");
+  return launch_mlp_features(ctx, tab, img, tgt, fr, x, (hipStream_t)stream);
+}
+
+gs_status gs_mlp_sync(gs_ctx* ctx, gs_mlp* mlp, void* stream) {
+  if (!ctx || !mlp || !mlp->master || !mlp->w_bf16) return gs_fail(ctx, GS_E_ARG, "null argument");
+  return launch_mlp_sync(ctx, mlp, (hipStream_t)stream);
+}
+
+gs_status gs_mlp_fwd(gs_ctx* ctx, const gs_mlp* mlp, const float* x, float* y, int64_t P, void* stream) {
+  if (!ctx || !mlp || !mlp->master || !mlp->w_bf16 || !x || !y || P < 0) return gs_fail(ctx, GS_E_ARG, "bad argument");
+  return launch_mlp_fwd(ctx, mlp, x, y, P, (hipStream_t)stream);
+}
+
+gs_status gs_mlp_train_step(gs_ctx* ctx, gs_mlp* mlp, const float* x, const float* label, int64_t P, float lr,
+                            int32_t step, float* loss, float* grad, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !mlp || !mlp->master || !mlp->w_bf16 || !mlp->adam_m || !mlp->adam_v || !x || !label || !loss ||
+      P <= 0 || step < 1)
+    return gs_fail(ctx, GS_E_ARG, "bad argument");
+  const size_t need = mlp_ws_bytes(P);
+  if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "mlp workspace %zu < %zu", ws_bytes, need);
+  return launch_mlp_train(ctx, mlp, x, label, P, lr, step, loss, grad, (char*)ws, (hipStream_t)stream);
+}
+
+}  // extern "C"

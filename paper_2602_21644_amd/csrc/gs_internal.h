@@ -1,0 +1,135 @@
+// Internal definitions shared by the gfx950 kernels and the host dispatch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gs.h"
+
+#define GS_BLOCK 256
+
+// Per-batch view table, passed by value to every kernel (fits the kernel
+// argument segment). Record offsets are multiples of 64 so a wave of records
+// never straddles two views.
+struct ViewTab {
+  int32_t nv;
+  int32_t ntiles;   // total tiles over views
+  int64_t nrec;     // total records (padded)
+  int64_t npix;     // total pixels
+  int64_t ng;       // total Gaussians (all scenes)
+  int32_t W[GS_MAX_VIEWS], H[GS_MAX_VIEWS], gx[GS_MAX_VIEWS], gy[GS_MAX_VIEWS];
+  int32_t tile_base[GS_MAX_VIEWS + 1];
+  int32_t scene[GS_MAX_VIEWS];
+  int64_t n[GS_MAX_VIEWS];      // Gaussians of the view's scene
+  int64_t npad[GS_MAX_VIEWS];   // n rounded up to 64
+  int64_t g_off[GS_MAX_VIEWS];  // first Gaussian of the view's scene
+  int64_t r_off[GS_MAX_VIEWS];  // first record of the view
+  int64_t px_off[GS_MAX_VIEWS]; // first pixel of the view
+};
+
+// Binning layout (per view), also by value.
+struct BinTab {
+  int32_t chunk;                  // records per chunk (4 waves x chunk/4)
+  int32_t nchunk[GS_MAX_VIEWS];   // chunks of the view (>= 1)
+  int64_t nlim[GS_MAX_VIEWS];     // records binned: min(max_rank, npad)
+  int64_t cm_off[GS_MAX_VIEWS];   // offset of the view in the count matrix
+  int32_t sblk[GS_MAX_VIEWS];     // radix blocks of the view
+  int64_t h_off[GS_MAX_VIEWS];    // offset of the view in the radix histogram
+  int32_t truncated[GS_MAX_VIEWS];
+};
+
+__device__ __forceinline__ int view_of_tile(const ViewTab& tab, int t) {
+  int v = 0;
+  for (int i = 1; i < tab.nv; ++i)
+    if (t >= tab.tile_base[i]) v = i;
+  return v;
+}
+
+// Exponent of the Gaussian at offset (dx, dy) = u - pixel, with every rounding
+// spelled out (explicit fma, no contractible mul+add) so the forward and the
+// backward kernels evaluate bit-identical alphas and take identical skips.
+__device__ __forceinline__ float gs_power(float k1, float k2, float k3, float dx, float dy) {
+  const float ax = k1 * dx;
+  const float cy = k3 * dy;
+  const float bx = k2 * dx;
+  const float q = __builtin_fmaf(ax, dx, cy * dy);
+  return __builtin_fmaf(-0.5f, q, -(bx * dy));
+}
+
+#define GS_ALPHA_MIN (1.0f / 255.0f)
+#define GS_ALPHA_MAX 0.99f
+#define GS_T_MIN 1e-4f
+
+// DPP wave64 reduction: returns the sum over all 64 lanes in lane 63.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf, bool BOUND = true>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, BOUND));
+}
+
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x += dpp_mov<0x111>(x);               // row_shr:1
+  x += dpp_mov<0x112>(x);               // row_shr:2
+  x += dpp_mov<0x114>(x);               // row_shr:4 -> lane i holds the sum of lanes i-7..i
+  x += dpp_mov<0x118>(x);               // row_shr:8 -> lane 15 of each row holds the row sum
+  x += dpp_mov<0x142, 0xa>(x);          // row_bcast:15 -> rows 1, 3 add the previous row's lane 15
+  x += dpp_mov<0x143, 0xc>(x);          // row_bcast:31 -> rows 2, 3 add lane 31
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum_to_lane63_d(double x) {
+  // exact-order-independent enough for FP64 partials: butterfly via shuffles
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// Host helpers
+struct gs_ctx {
+  int device;
+  int render_batch;
+  int bwd_batch;
+  int bin_chunk;
+  char err[512];
+};
+
+gs_status gs_fail(gs_ctx* ctx, gs_status s, const char* fmt, ...);
+gs_status gs_check_launch(gs_ctx* ctx, const char* what);
+
+// Workspace layout of gs_bin_sort (byte offsets, 256-aligned).
+struct BinWs {
+  size_t keys_a, keys_b, vals_a, vals_b, hist, part, total, cm, bytes;
+  int64_t hist_n, cm_n;
+};
+
+// Launchers (one translation unit each).
+gs_status launch_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, gs_proj*, hipStream_t);
+void bin_tab_fill(const ViewTab&, int, int64_t, BinTab&);
+BinWs bin_ws_layout(const ViewTab&, const BinTab&);
+gs_status launch_bin_sort(gs_ctx*, const ViewTab&, const BinTab&, const gs_proj*, gs_bins*, char*, hipStream_t);
+gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const float*, int, gs_image*,
+                            hipStream_t);
+gs_status launch_render_bwd_tiles(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const gs_image*,
+                                  const gs_pixel_grads*, const float*, float*, uint8_t*, hipStream_t);
+gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, float*, uint8_t*,
+                             float*, gs_grads*, hipStream_t);
+int bwd_pose_blocks(const ViewTab&);
+int loss_blocks(const ViewTab&);
+gs_status launch_loss(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_loss_params*, float*,
+                      gs_pixel_grads*, double*, hipStream_t);
+size_t mp_ws_bytes(const ViewTab&, int64_t npix);
+gs_status launch_mp_update(gs_ctx*, const ViewTab&, const gs_proj*, const gs_image*, const gs_target*,
+                           const gs_mp_frame*, const gs_mp_params*, float*, gs_mp_out*, char*, hipStream_t);
+size_t mlp_ws_bytes(int64_t P);
+gs_status launch_mlp_features(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_mp_frame*, float*,
+                              hipStream_t);
+gs_status launch_mlp_sync(gs_ctx*, gs_mlp*, hipStream_t);
+gs_status launch_mlp_fwd(gs_ctx*, const gs_mlp*, const float*, float*, int64_t, hipStream_t);
+gs_status launch_mlp_train(gs_ctx*, gs_mlp*, const float*, const float*, int64_t, float, int, float*, float*, char*,
+                           hipStream_t);

@@ -1,0 +1,210 @@
+// Second part of gs_render_bwd: per-Gaussian adjoint of the projection.
+//
+// One thread per Gaussian (all scenes); it visits every view of its scene,
+// reads the 2D adjoint the tile pass accumulated for that (view, Gaussian)
+// record only when the record was touched, chains it through the projection
+// in float32 and sums the parameter gradients over views in registers. Read
+// records are reset to zero so the scratch stays zero-filled between calls.
+// Pose-twist partials are reduced per block and summed in a fixed order by a
+// second kernel (deterministic).
+//
+// The chain works with the camera-space square root T1 = R Rq diag(S) of the
+// covariance (cov2D = (J T1)(J T1)^T + 0.3 I), a different route from the
+// covariance-space derivation of the CPU reference.
+#include "gs_project_dev.h"
+
+namespace {
+
+__device__ __forceinline__ void block_sum6(float (&x)[6], float* s_tmp /*[4][6]*/, float* out) {
+  const int w = threadIdx.x >> 6, lane = __lane_id();
+#pragma unroll
+  for (int c = 0; c < 6; ++c) x[c] = wave_sum_to_lane63(x[c]);
+  if (lane == 63)
+    for (int c = 0; c < 6; ++c) s_tmp[w * 6 + c] = x[c];
+  __syncthreads();
+  if (threadIdx.x < 6) out[threadIdx.x] = s_tmp[threadIdx.x] + s_tmp[6 + threadIdx.x] + s_tmp[12 + threadIdx.x] +
+                                          s_tmp[18 + threadIdx.x];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
+    ViewTab tab, const gs_camera* __restrict__ cams, const float* __restrict__ mean,
+    const float* __restrict__ log_scale, const float* __restrict__ quat, const float* __restrict__ opl,
+    float* __restrict__ g2d, uint8_t* __restrict__ touched, float* __restrict__ d_mean,
+    float* __restrict__ d_ls, float* __restrict__ d_quat, float* __restrict__ d_opl, float* __restrict__ d_color,
+    float* __restrict__ pose_part, int pose_only, int accumulate) {
+  __shared__ float s_tmp[24];
+  const int64_t gk = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+  const int64_t N = tab.ng;
+  const int64_t M = tab.nrec;
+  const bool valid = gk < N;
+  float gm[3] = {0, 0, 0}, gl[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
+  float m[3], ls[3], q[4], op = 0.f;
+  bool loaded = false;
+  for (int v = 0; v < tab.nv; ++v) {
+    float pv[6] = {0, 0, 0, 0, 0, 0};
+    bool has = false;
+    const int64_t k = gk - tab.g_off[v];
+    if (valid && k >= 0 && k < tab.n[v]) {
+      const int64_t r = tab.r_off[v] + k;
+      if (touched[r]) {
+        has = true;
+        touched[r] = 0;
+        float a[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+          a[c] = g2d[c * M + r];
+          g2d[c * M + r] = 0.f;
+        }
+        if (!loaded) {
+          for (int c = 0; c < 3; ++c) {
+            m[c] = mean[c * N + gk];
+            ls[c] = log_scale[c * N + gk];
+          }
+          for (int c = 0; c < 4; ++c) q[c] = quat[c * N + gk];
+          op = opl[gk];
+          loaded = true;
+        }
+        const gs_camera cam = cams[v];
+        const ProjF P = project_f(cam, m, ls, q, op);
+        gc[0] += a[6];
+        gc[1] += a[7];
+        gc[2] += a[8];
+        if (P.kept) {
+          const float k1 = P.k1, k2 = P.k2, k3 = P.k3;
+          // conic -> 2D covariance
+          const float G00 = a[2], G01 = 0.5f * a[3], G11 = a[4];
+          const float QG00 = k1 * G00 + k2 * G01, QG01 = k1 * G01 + k2 * G11;
+          const float QG10 = k2 * G00 + k3 * G01, QG11 = k2 * G01 + k3 * G11;
+          const float cb00 = -(QG00 * k1 + QG01 * k2);
+          const float cb01 = -(QG00 * k2 + QG01 * k3);
+          const float cb11 = -(QG10 * k2 + QG11 * k3);
+          // cov = JT JT^T + 0.3 I -> JTbar = 2 cb JT
+          float JTb[2][3];
+          for (int j = 0; j < 3; ++j) {
+            JTb[0][j] = 2.f * (cb00 * P.JT[0][j] + cb01 * P.JT[1][j]);
+            JTb[1][j] = 2.f * (cb01 * P.JT[0][j] + cb11 * P.JT[1][j]);
+          }
+          // JT = J T1
+          const float Jb00 = JTb[0][0] * P.T1[0][0] + JTb[0][1] * P.T1[0][1] + JTb[0][2] * P.T1[0][2];
+          const float Jb02 = JTb[0][0] * P.T1[2][0] + JTb[0][1] * P.T1[2][1] + JTb[0][2] * P.T1[2][2];
+          const float Jb11 = JTb[1][0] * P.T1[1][0] + JTb[1][1] * P.T1[1][1] + JTb[1][2] * P.T1[1][2];
+          const float Jb12 = JTb[1][0] * P.T1[2][0] + JTb[1][1] * P.T1[2][1] + JTb[1][2] * P.T1[2][2];
+          float T1b[3][3];
+          for (int j = 0; j < 3; ++j) {
+            T1b[0][j] = P.j00 * JTb[0][j];
+            T1b[1][j] = P.j11 * JTb[1][j];
+            T1b[2][j] = P.j02 * JTb[0][j] + P.j12 * JTb[1][j];
+          }
+          const float x = P.px, y = P.py, iz = 1.0f / P.pz;
+          const float iz2 = iz * iz, iz3 = iz2 * iz;
+          const float fx = cam.fx, fy = cam.fy;
+          float pb0 = Jb02 * (-fx * iz2) + a[0] * fx * iz;
+          float pb1 = Jb12 * (-fy * iz2) + a[1] * fy * iz;
+          float pb2 = Jb00 * (-fx * iz2) + Jb02 * (2.f * fx * x * iz3) + Jb11 * (-fy * iz2) +
+                      Jb12 * (2.f * fy * y * iz3) - a[0] * fx * x * iz2 - a[1] * fy * y * iz2 + a[9];
+          // pose: p' = Exp(xi) p and T1' = Exp(phi) T1
+          float B[3][3];
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              B[i][j] = P.T1[i][0] * T1b[j][0] + P.T1[i][1] * T1b[j][1] + P.T1[i][2] * T1b[j][2];
+          pv[0] = pb0;
+          pv[1] = pb1;
+          pv[2] = pb2;
+          pv[3] = y * pb2 - P.pz * pb1 + (B[1][2] - B[2][1]);
+          pv[4] = P.pz * pb0 - x * pb2 + (B[2][0] - B[0][2]);
+          pv[5] = x * pb1 - y * pb0 + (B[0][1] - B[1][0]);
+          if (!pose_only) {
+            const float* R = cam.T_cw;  // rows R[0..2], R[4..6], R[8..10]
+            for (int c = 0; c < 3; ++c) gm[c] += R[c] * pb0 + R[4 + c] * pb1 + R[8 + c] * pb2;
+            // T1 = R Mw, Mw = Rq diag(S): Mwbar = R^T T1bar
+            float Mb[3][3];
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j) Mb[i][j] = R[i] * T1b[0][j] + R[4 + i] * T1b[1][j] + R[8 + i] * T1b[2][j];
+            float Rb[3][3];
+            for (int j = 0; j < 3; ++j) {
+              const float sb = Mb[0][j] * P.Rq[0][j] + Mb[1][j] * P.Rq[1][j] + Mb[2][j] * P.Rq[2][j];
+              gl[j] += sb * P.S[j];
+              for (int i = 0; i < 3; ++i) Rb[i][j] = Mb[i][j] * P.S[j];
+            }
+            const float w = P.qn[0], qx = P.qn[1], qy = P.qn[2], qz = P.qn[3];
+            float nb[4];
+            nb[0] = 2.f * (-qz * Rb[0][1] + qy * Rb[0][2] + qz * Rb[1][0] - qx * Rb[1][2] - qy * Rb[2][0] + qx * Rb[2][1]);
+            nb[1] = 2.f * (qy * Rb[0][1] + qz * Rb[0][2] + qy * Rb[1][0] - 2.f * qx * Rb[1][1] - w * Rb[1][2] +
+                           qz * Rb[2][0] + w * Rb[2][1] - 2.f * qx * Rb[2][2]);
+            nb[2] = 2.f * (-2.f * qy * Rb[0][0] + qx * Rb[0][1] + w * Rb[0][2] + qx * Rb[1][0] + qz * Rb[1][2] -
+                           w * Rb[2][0] + qz * Rb[2][1] - 2.f * qy * Rb[2][2]);
+            nb[3] = 2.f * (-2.f * qz * Rb[0][0] - w * Rb[0][1] + qx * Rb[0][2] + w * Rb[1][0] - 2.f * qz * Rb[1][1] +
+                           qy * Rb[1][2] + qx * Rb[2][0] + qy * Rb[2][1]);
+            const float dot = nb[0] * P.qn[0] + nb[1] * P.qn[1] + nb[2] * P.qn[2] + nb[3] * P.qn[3];
+            for (int c = 0; c < 4; ++c) gq[c] += (nb[c] - P.qn[c] * dot) * P.qinv;
+            go += a[5] * P.o * (1.f - P.o);
+          }
+        }
+      }
+    }
+    if (__syncthreads_or(has)) {
+      float out6[6];
+      block_sum6(pv, s_tmp, pose_part + ((int64_t)v * gridDim.x + blockIdx.x) * 6);
+      (void)out6;
+    } else if (threadIdx.x < 6) {
+      pose_part[((int64_t)v * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = 0.f;
+    }
+  }
+  if (!valid || pose_only) return;
+  if (accumulate) {
+    for (int c = 0; c < 3; ++c) {
+      d_mean[c * N + gk] += gm[c];
+      d_ls[c * N + gk] += gl[c];
+      d_color[c * N + gk] += gc[c];
+    }
+    for (int c = 0; c < 4; ++c) d_quat[c * N + gk] += gq[c];
+    d_opl[gk] += go;
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      d_mean[c * N + gk] = gm[c];
+      d_ls[c * N + gk] = gl[c];
+      d_color[c * N + gk] = gc[c];
+    }
+    for (int c = 0; c < 4; ++c) d_quat[c * N + gk] = gq[c];
+    d_opl[gk] = go;
+  }
+}
+
+// Sums the per-block pose partials of view blockIdx.x in a fixed order.
+__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(const float* __restrict__ part, int nblk,
+                                                              float* __restrict__ pose, int accumulate) {
+  __shared__ double s[GS_BLOCK];
+  const int v = blockIdx.x;
+  for (int c = 0; c < 6; ++c) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) acc += (double)part[((int64_t)v * nblk + b) * 6 + c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = GS_BLOCK / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + s[0] : s[0]);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams, const gs_gaussians* g,
+                             float* g2d, uint8_t* touched, float* pose_part, gs_grads* gr, hipStream_t s) {
+  const int nblk = (int)((tab.ng + GS_BLOCK - 1) / GS_BLOCK);
+  if (nblk > 0) {
+    hipLaunchKernelGGL(bwd_project_kernel, dim3(nblk), dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale,
+                       g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
+                       gr->color, pose_part, gr->pose_only, gr->accumulate);
+  }
+  if (gr->pose) {
+    hipLaunchKernelGGL(pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, nblk, gr->pose,
+                       gr->accumulate);
+  }
+  return gs_check_launch(ctx, "render_bwd_project");
+}
+
+int bwd_pose_blocks(const ViewTab& tab) { return (int)((tab.ng + GS_BLOCK - 1) / GS_BLOCK); }

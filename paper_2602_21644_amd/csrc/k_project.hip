@@ -1,0 +1,89 @@
+// gs_project: one thread per (view, Gaussian) record, coalesced planar reads.
+#include "gs_project_dev.h"
+
+namespace {
+
+__global__ __launch_bounds__(GS_BLOCK) void project_kernel(ViewTab tab, const gs_camera* __restrict__ cams,
+                                                           const float* __restrict__ mean,
+                                                           const float* __restrict__ log_scale,
+                                                           const float* __restrict__ quat,
+                                                           const float* __restrict__ opl,
+                                                           const float* __restrict__ color,
+                                                           const float* __restrict__ mp, float4* __restrict__ rec,
+                                                           int2* __restrict__ rect, uint32_t* __restrict__ key,
+                                                           float* __restrict__ mean2d, float* __restrict__ conic,
+                                                           float* __restrict__ depth, float* __restrict__ opacity,
+                                                           int32_t* __restrict__ radius) {
+  const int v = blockIdx.y;
+  const int64_t k = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+  if (k >= tab.npad[v]) return;
+  const int64_t r = tab.r_off[v] + k;
+  const int64_t M = tab.nrec;
+  const int64_t N = tab.ng;
+  // empty rect: x0 = 1 > x1 = 0
+  const int2 empty_rect = make_int2((int)(uint16_t)1 | ((int)(uint16_t)1 << 16), 0);
+  if (k >= tab.n[v]) {
+    rect[r] = empty_rect;
+    key[r] = 0xFFFFFFFFu;
+    if (radius) radius[r] = 0;
+    return;
+  }
+  const gs_camera cam = cams[v];
+  const int64_t gk = tab.g_off[v] + k;
+  const float m[3] = {mean[gk], mean[N + gk], mean[2 * N + gk]};
+  const float ls[3] = {log_scale[gk], log_scale[N + gk], log_scale[2 * N + gk]};
+  const float q[4] = {quat[gk], quat[N + gk], quat[2 * N + gk], quat[3 * N + gk]};
+  const ProjF P = project_f(cam, m, ls, q, opl[gk]);
+  int rr = 0;
+  bool nonempty = false;
+  int2 rc = empty_rect;
+  if (P.kept) {
+    const float rf = ceilf(P.extent);
+    // Gaussians whose projected mean or radius exceed 1e7 px are treated as
+    // off-screen (integer pixel arithmetic below needs exact floats).
+    if (fabsf(P.ux) < 1e7f && fabsf(P.uy) < 1e7f && rf < 1e7f) {
+      rr = (int)rf;
+      const int ix = (int)floorf(P.ux), iy = (int)floorf(P.uy);
+      const int gx = tab.gx[v], gy = tab.gy[v];
+      const int x0 = max(0, (ix - rr) >> 4), x1 = min(gx - 1, (ix + rr) >> 4);
+      const int y0 = max(0, (iy - rr) >> 4), y1 = min(gy - 1, (iy + rr) >> 4);
+      if (x0 <= x1 && y0 <= y1) {
+        nonempty = true;
+        rc = make_int2((x0 & 0xFFFF) | (y0 << 16), (x1 & 0xFFFF) | (y1 << 16));
+      }
+    }
+  }
+  rect[r] = rc;
+  key[r] = nonempty ? __float_as_uint(P.pz) : 0xFFFFFFFFu;
+  if (P.kept) {
+    rec[3 * r + 0] = make_float4(P.ux, P.uy, P.pz, P.o);
+    rec[3 * r + 1] = make_float4(P.k1, P.k2, P.k3, mp[gk]);
+    rec[3 * r + 2] = make_float4(color[gk], color[N + gk], color[2 * N + gk], 0.f);
+  }
+  if (mean2d) {
+    mean2d[r] = P.ux;
+    mean2d[M + r] = P.uy;
+  }
+  if (conic) {
+    conic[r] = P.k1;
+    conic[M + r] = P.k2;
+    conic[2 * M + r] = P.k3;
+  }
+  if (depth) depth[r] = P.pz;
+  if (opacity) opacity[r] = P.o;
+  if (radius) radius[r] = P.kept ? rr : 0;
+}
+
+}  // namespace
+
+gs_status launch_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams, const gs_gaussians* g,
+                         gs_proj* p, hipStream_t s) {
+  int64_t maxn = 0;
+  for (int v = 0; v < tab.nv; ++v) maxn = tab.npad[v] > maxn ? tab.npad[v] : maxn;
+  if (maxn == 0) return GS_OK;
+  dim3 grid((unsigned)((maxn + GS_BLOCK - 1) / GS_BLOCK), tab.nv);
+  hipLaunchKernelGGL(project_kernel, grid, dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale, g->quat,
+                     g->opacity_logit, g->color, g->mp, (float4*)p->rec, (int2*)p->rect, p->depth_key, p->mean2d,
+                     p->conic, p->depth, p->opacity, p->radius);
+  return gs_check_launch(ctx, "project");
+}

@@ -1,0 +1,456 @@
+"""ctypes binding of libgs.so (include/gs.h), argument marshalling only.
+
+The C structures are mirrored one to one; the functions gs_project,
+gs_bin_sort, gs_render_fwd, gs_loss, gs_render_bwd, gs_mp_update (and the
+helpers) keep their C names and take those structures. Device memory comes
+from torch tensors; every call is enqueued on torch's current HIP stream
+unless a stream handle is given. `Pipeline` allocates the buffers of one view
+batch and chains the calls of one optimisation iteration.
+
+There is no fallback: if libgs.so is missing or fails to load, lib() raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_int64, c_size_t, c_uint16, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs.so")
+_lib = None
+
+GS_OK, GS_E_ARG, GS_E_CAPACITY, GS_E_HIP, GS_E_UNSUPPORTED = 0, 1, 2, 3, 4
+GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_LOSS, GS_OP_MP_UPDATE, GS_OP_MLP_TRAIN = 1, 2, 3, 4, 5
+GS_MAX_VIEWS = 32
+GS_MLP_PARAMS = 1377
+GS_MLP_WEIGHTS = 1312
+
+
+class GSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("fx", c_float), ("fy", c_float), ("cx", c_float),
+                ("cy", c_float), ("z_near", c_float), ("pad_", c_float), ("T_cw", c_float * 12)]
+
+
+class Views(ctypes.Structure):
+    _fields_ = [("n_views", c_int32), ("n_scenes", c_int32), ("n_gaussians", c_int64),
+                ("cams_host", POINTER(Camera)), ("cams_dev", c_void_p), ("view_scene", POINTER(c_int32)),
+                ("scene_begin", POINTER(c_int64))]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", c_int64)] + [(k, c_void_p) for k in ("mean", "log_scale", "quat", "opacity_logit", "color",
+                                                          "mp")]
+
+
+class Proj(ctypes.Structure):
+    _fields_ = [("m", c_int64)] + [(k, c_void_p) for k in ("rec", "rect", "depth_key", "mean2d", "conic", "depth",
+                                                          "opacity", "radius")]
+
+
+class Bins(ctypes.Structure):
+    _fields_ = [("capacity", c_int64)] + [(k, c_void_p) for k in ("gauss_id", "tile_start", "sorted_ids",
+                                                                 "n_instances", "overflow", "incomplete")] + [
+        ("max_rank", c_int64)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [(k, c_void_p) for k in ("color", "depth", "mp", "T", "n_last")]
+
+
+class Target(ctypes.Structure):
+    _fields_ = [("color", c_void_p), ("depth", c_void_p)]
+
+
+class LossParams(ctypes.Structure):
+    _fields_ = [("lambda_pho", c_float), ("lambda_depth", c_float), ("eps_A", c_float), ("weight_mode", c_int32),
+                ("grad_through_weight", c_int32)]
+
+
+class PixelGrads(ctypes.Structure):
+    _fields_ = [(k, c_void_p) for k in ("dcolor", "ddepth", "dmp", "dT")]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [(k, c_void_p) for k in ("mean", "log_scale", "quat", "opacity_logit", "color", "pose")] + [
+        ("pose_only", c_int32), ("accumulate", c_int32)]
+
+
+class MPFrame(ctypes.Structure):
+    _fields_ = [("instance_id", c_void_p), ("n_inst", c_int32), ("inst_prior", c_void_p), ("inst_conf", c_void_p),
+                ("seg_updated", c_int32), ("mlp_mp", c_void_p)]
+
+
+MP_PARAM_NAMES = ("lambda_e", "sigma_small", "e_floor", "sigma_g", "sigma_c", "lambda_u", "eps", "alpha_min",
+                  "alpha_max", "rho", "radius_px", "sigma_w", "beta_color", "prune_above", "logodds_eps",
+                  "logodds_max")
+
+
+class MPParams(ctypes.Structure):
+    _fields_ = [(k, c_float) for k in MP_PARAM_NAMES] + [("mode", c_int32), ("u_norm", c_int32)]
+
+
+class MPOut(ctypes.Structure):
+    _fields_ = [(k, c_void_p) for k in ("U_tilde", "alpha", "dynamic", "prune", "M_p", "e", "stats")]
+
+
+class MLP(ctypes.Structure):
+    _fields_ = [(k, c_void_p) for k in ("master", "w_bf16", "adam_m", "adam_v")]
+
+
+MP_DEFAULTS = dict(lambda_e=2.0, sigma_small=1e-3, e_floor=0.0, sigma_g=0.05, sigma_c=0.05, lambda_u=1.0, eps=1e-6,
+                   alpha_min=0.1, alpha_max=0.8, rho=0.5, radius_px=2.0, sigma_w=1.0, beta_color=0.0,
+                   prune_above=2.0, logodds_eps=0.01, logodds_max=float(np.log(99.0)), mode=0, u_norm=0)
+
+
+def lib():
+    """Load libgs.so (built by __graft_entry__.build / paper_2602_21644_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = c_void_p
+        sig = {
+            "gs_status_str": ([c_int32], ctypes.c_char_p),
+            "gs_ctx_create": ([ctypes.c_int, POINTER(c_void_p)], c_int32),
+            "gs_ctx_destroy": ([P], c_int32),
+            "gs_last_error": ([P], ctypes.c_char_p),
+            "gs_ctx_set_param": ([P, ctypes.c_char_p, c_int64], c_int32),
+            "gs_ctx_get_param": ([P, ctypes.c_char_p, POINTER(c_int64)], c_int32),
+            "gs_rec_offset": ([POINTER(Views), c_int32], c_int64),
+            "gs_rec_count": ([POINTER(Views)], c_int64),
+            "gs_tile_count": ([POINTER(Views)], c_int64),
+            "gs_pixel_count": ([POINTER(Views)], c_int64),
+            "gs_workspace_size": ([P, POINTER(Views), c_int32, POINTER(c_size_t)], c_int32),
+            "gs_project": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), P], c_int32),
+            "gs_bin_sort": ([P, POINTER(Views), POINTER(Proj), POINTER(Bins), P, c_size_t, P], c_int32),
+            "gs_render_fwd": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins), POINTER(c_float),
+                               POINTER(Image), P], c_int32),
+            "gs_loss": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(LossParams), P,
+                         POINTER(PixelGrads), P, c_size_t, P], c_int32),
+            "gs_render_bwd": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins), POINTER(Image),
+                               POINTER(PixelGrads), POINTER(c_float), POINTER(Grads), P, c_size_t, P], c_int32),
+            "gs_bins_check": ([P, POINTER(Bins), POINTER(c_int64), POINTER(c_int32), P], c_int32),
+            "gs_mp_update": ([P, POINTER(Views), POINTER(Proj), POINTER(Image), POINTER(Target), POINTER(MPFrame),
+                              POINTER(MPParams), P, POINTER(MPOut), P, c_size_t, P], c_int32),
+            "gs_mlp_features": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(MPFrame), P, P],
+                                c_int32),
+            "gs_mlp_sync": ([P, POINTER(MLP), P], c_int32),
+            "gs_mlp_fwd": ([P, POINTER(MLP), P, P, c_int64, P], c_int32),
+            "gs_mlp_train_step": ([P, POINTER(MLP), P, P, c_int64, c_float, c_int32, P, P, P, c_size_t, P],
+                                  c_int32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error", "gs_ctx_set_param",
+            "gs_ctx_get_param", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
+            "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_bwd",
+            "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step")
+
+
+def ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.h = c_void_p()
+        st = lib().gs_ctx_create(device, ctypes.byref(self.h))
+        if st != GS_OK:
+            raise GSError(st, "gs_ctx_create failed")
+
+    def check(self, st, what):
+        if st != GS_OK:
+            msg = lib().gs_last_error(self.h).decode()
+            raise GSError(st, f"{what}: {lib().gs_status_str(st).decode()}: {msg}")
+
+    def set_param(self, name, value):
+        self.check(lib().gs_ctx_set_param(self.h, name.encode(), int(value)), "set_param " + name)
+
+    def get_param(self, name):
+        v = c_int64()
+        self.check(lib().gs_ctx_get_param(self.h, name.encode(), ctypes.byref(v)), "get_param " + name)
+        return v.value
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().gs_ctx_destroy(self.h)
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- the six calls (C names)
+def gs_project(ctx, views, g, proj, stream=None):
+    ctx.check(lib().gs_project(ctx.h, ctypes.byref(views), ctypes.byref(g), ctypes.byref(proj), _stream(stream)),
+              "gs_project")
+
+
+def gs_bin_sort(ctx, views, proj, bins, ws, stream=None):
+    ctx.check(lib().gs_bin_sort(ctx.h, ctypes.byref(views), ctypes.byref(proj), ctypes.byref(bins), ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)), "gs_bin_sort")
+
+
+def gs_render_fwd(ctx, views, g, proj, bins, bg, img, stream=None):
+    bgv = (c_float * 3)(*[float(x) for x in bg])
+    ctx.check(lib().gs_render_fwd(ctx.h, ctypes.byref(views), ctypes.byref(g), ctypes.byref(proj),
+                                  ctypes.byref(bins), bgv, ctypes.byref(img), _stream(stream)), "gs_render_fwd")
+
+
+def gs_loss(ctx, views, img, tgt, params, loss, pg, ws, stream=None):
+    ctx.check(lib().gs_loss(ctx.h, ctypes.byref(views), ctypes.byref(img), ctypes.byref(tgt), ctypes.byref(params),
+                            ptr(loss), ctypes.byref(pg), ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+              "gs_loss")
+
+
+def gs_render_bwd(ctx, views, g, proj, bins, img, pg, bg, grads, ws, stream=None):
+    bgv = (c_float * 3)(*[float(x) for x in bg])
+    ctx.check(lib().gs_render_bwd(ctx.h, ctypes.byref(views), ctypes.byref(g), ctypes.byref(proj),
+                                  ctypes.byref(bins), ctypes.byref(img), ctypes.byref(pg), bgv, ctypes.byref(grads),
+                                  ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "gs_render_bwd")
+
+
+def gs_mp_update(ctx, views, proj, img, tgt, frame, params, mp, out, ws, stream=None):
+    ctx.check(lib().gs_mp_update(ctx.h, ctypes.byref(views), ctypes.byref(proj), ctypes.byref(img),
+                                 ctypes.byref(tgt), ctypes.byref(frame), ctypes.byref(params), ptr(mp),
+                                 ctypes.byref(out), ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+              "gs_mp_update")
+
+
+def gs_bins_check(ctx, bins, stream=None):
+    req = c_int64()
+    inc = c_int32()
+    st = lib().gs_bins_check(ctx.h, ctypes.byref(bins), ctypes.byref(req), ctypes.byref(inc), _stream(stream))
+    if st not in (GS_OK, GS_E_CAPACITY):
+        ctx.check(st, "gs_bins_check")
+    return st == GS_E_CAPACITY, int(req.value), int(inc.value)
+
+
+def gs_workspace_size(ctx, views, op):
+    b = c_size_t()
+    ctx.check(lib().gs_workspace_size(ctx.h, ctypes.byref(views), op, ctypes.byref(b)), "gs_workspace_size")
+    return int(b.value)
+
+
+def gs_mlp_features(ctx, views, img, tgt, frame, x, stream=None):
+    ctx.check(lib().gs_mlp_features(ctx.h, ctypes.byref(views), ctypes.byref(img), ctypes.byref(tgt),
+                                    ctypes.byref(frame), ptr(x), _stream(stream)), "gs_mlp_features")
+
+
+def gs_mlp_sync(ctx, mlp, stream=None):
+    ctx.check(lib().gs_mlp_sync(ctx.h, ctypes.byref(mlp), _stream(stream)), "gs_mlp_sync")
+
+
+def gs_mlp_fwd(ctx, mlp, x, y, P, stream=None):
+    ctx.check(lib().gs_mlp_fwd(ctx.h, ctypes.byref(mlp), ptr(x), ptr(y), int(P), _stream(stream)), "gs_mlp_fwd")
+
+
+def gs_mlp_train_step(ctx, mlp, x, label, P, lr, step, loss, grad, ws, stream=None):
+    ctx.check(lib().gs_mlp_train_step(ctx.h, ctypes.byref(mlp), ptr(x), ptr(label), int(P), float(lr), int(step),
+                                      ptr(loss), ptr(grad), ptr(ws), ws.numel() * ws.element_size(),
+                                      _stream(stream)), "gs_mlp_train_step")
+
+
+# ---------------------------------------------------------------- host-side helpers
+def camera_struct(cam: dict) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.fx, c.fy, c.cx, c.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    c.z_near = float(cam["z_near"])
+    c.T_cw[:] = [float(x) for x in np.asarray(cam["T_cw"], np.float64).reshape(12)]
+    return c
+
+
+class ViewBatch:
+    """V cameras over S scenes (packed Gaussians). Holds the host arrays the
+    C struct points to and the device copy of the cameras."""
+
+    def __init__(self, cams, n_gaussians, view_scene=None, scene_begin=None, device="cuda"):
+        V = len(cams)
+        self.V = V
+        self.cams = list(cams)
+        self._host = (Camera * V)(*[camera_struct(c) for c in cams])
+        raw = np.frombuffer(bytes(self._host), dtype=np.uint8).copy()
+        self.cams_dev = torch.from_numpy(raw).to(device)
+        self._vs = None
+        self._sb = None
+        S = 1
+        if view_scene is not None:
+            self._vs = (c_int32 * V)(*[int(s) for s in view_scene])
+        if scene_begin is not None:
+            S = len(scene_begin) - 1
+            self._sb = (c_int64 * (S + 1))(*[int(s) for s in scene_begin])
+        self.n_scenes = S
+        self.n_gaussians = int(n_gaussians)
+        self.s = Views()
+        self.s.n_views = V
+        self.s.n_scenes = S
+        self.s.n_gaussians = self.n_gaussians
+        self.s.cams_host = ctypes.cast(self._host, POINTER(Camera))
+        self.s.cams_dev = c_void_p(self.cams_dev.data_ptr())
+        self.s.view_scene = ctypes.cast(self._vs, POINTER(c_int32)) if self._vs is not None else None
+        self.s.scene_begin = ctypes.cast(self._sb, POINTER(c_int64)) if self._sb is not None else None
+
+    def set_pose(self, v, T_cw, stream=None):
+        """Update view v's pose in the device camera table (in place, on the stream)."""
+        T = torch.as_tensor(np.asarray(T_cw, np.float32).reshape(12))
+        off = ctypes.sizeof(Camera) * v + Camera.T_cw.offset
+        self.cams_dev[off:off + 48].copy_(T.view(torch.uint8).to(self.cams_dev.device), non_blocking=False)
+        self._host[v].T_cw[:] = [float(x) for x in T.tolist()]
+
+    def set_pose_tensor(self, v, T_dev):
+        """Copy a float32 [12] device tensor into view v's pose (graph-capturable)."""
+        off = ctypes.sizeof(Camera) * v + Camera.T_cw.offset
+        self.cams_dev[off:off + 48].view(torch.float32).copy_(T_dev.reshape(12))
+
+    @property
+    def rec_count(self):
+        return int(lib().gs_rec_count(ctypes.byref(self.s)))
+
+    def rec_offset(self, v):
+        return int(lib().gs_rec_offset(ctypes.byref(self.s), v))
+
+    @property
+    def tile_count(self):
+        return int(lib().gs_tile_count(ctypes.byref(self.s)))
+
+    @property
+    def pixel_count(self):
+        return int(lib().gs_pixel_count(ctypes.byref(self.s)))
+
+
+def gaussians_struct(t: dict) -> Gaussians:
+    g = Gaussians()
+    g.n = int(t["opacity_logit"].shape[0])
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "color", "mp"):
+        setattr(g, k, c_void_p(t[k].data_ptr()))
+    return g
+
+
+def to_device(g: dict, device="cuda") -> dict:
+    return {k: torch.as_tensor(np.ascontiguousarray(v)).to(device) for k, v in g.items()}
+
+
+class Pipeline:
+    """Buffers and calls of one render + loss + backward iteration for a view
+    batch. All buffers are torch tensors on `device`; every kernel runs in
+    libgs.so."""
+
+    def __init__(self, ctx: Context, views: ViewBatch, capacity: int, max_rank: int = 0, full_proj=False,
+                 device="cuda", bg=(0.0, 0.0, 0.0)):
+        self.ctx, self.views, self.device = ctx, views, device
+        self.bg = tuple(float(x) for x in bg)
+        M, T, P = views.rec_count, views.tile_count, views.pixel_count
+        self.M, self.T, self.P = M, T, P
+        f32, i32, dev = torch.float32, torch.int32, device
+        self.rec = torch.empty(M * 12, dtype=f32, device=dev)
+        self.rect = torch.empty(M * 4, dtype=torch.int16, device=dev)
+        self.key = torch.empty(M, dtype=i32, device=dev)
+        self.full_proj = full_proj
+        if full_proj:
+            self.mean2d = torch.empty(2 * M, dtype=f32, device=dev)
+            self.conic = torch.empty(3 * M, dtype=f32, device=dev)
+            self.depth = torch.empty(M, dtype=f32, device=dev)
+            self.opacity = torch.empty(M, dtype=f32, device=dev)
+            self.radius = torch.empty(M, dtype=i32, device=dev)
+        self.proj = Proj()
+        self.proj.m = M
+        self.proj.rec, self.proj.rect, self.proj.depth_key = ptr(self.rec), ptr(self.rect), ptr(self.key)
+        if full_proj:
+            for k in ("mean2d", "conic", "depth", "opacity", "radius"):
+                setattr(self.proj, k, ptr(getattr(self, k)))
+        self.capacity = int(capacity)
+        self.ids = torch.empty(max(1, self.capacity), dtype=i32, device=dev)
+        self.tile_start = torch.empty(T + 1, dtype=i32, device=dev)
+        self.sorted_ids = torch.empty(M, dtype=i32, device=dev)
+        self.counters = torch.zeros(4, dtype=torch.int64, device=dev)  # n_inst, overflow|incomplete
+        self.bins = Bins()
+        self.bins.capacity = self.capacity
+        self.bins.gauss_id, self.bins.tile_start, self.bins.sorted_ids = ptr(self.ids), ptr(self.tile_start), ptr(
+            self.sorted_ids)
+        base = self.counters.data_ptr()
+        self.bins.n_instances = c_void_p(base)
+        self.bins.overflow = c_void_p(base + 8)
+        self.bins.incomplete = c_void_p(base + 16)
+        self.bins.max_rank = int(max_rank)
+        self.img_color = torch.empty(3 * P, dtype=f32, device=dev)
+        self.img_depth = torch.empty(P, dtype=f32, device=dev)
+        self.img_mp = torch.empty(P, dtype=f32, device=dev)
+        self.img_T = torch.empty(P, dtype=f32, device=dev)
+        self.img_nlast = torch.empty(P, dtype=i32, device=dev)
+        self.img = Image(ptr(self.img_color), ptr(self.img_depth), ptr(self.img_mp), ptr(self.img_T),
+                         ptr(self.img_nlast))
+        self.dC = torch.empty(3 * P, dtype=f32, device=dev)
+        self.dD = torch.empty(P, dtype=f32, device=dev)
+        self.dM = torch.zeros(P, dtype=f32, device=dev)
+        self.dT = torch.zeros(P, dtype=f32, device=dev)
+        self.pg = PixelGrads(ptr(self.dC), ptr(self.dD), ptr(self.dM), ptr(self.dT))
+        self.loss = torch.zeros(views.V, dtype=f32, device=dev)
+        self.ws_bin = torch.empty(gs_workspace_size(ctx, views.s, GS_OP_BIN_SORT), dtype=torch.uint8, device=dev)
+        self.ws_bwd = torch.zeros(gs_workspace_size(ctx, views.s, GS_OP_RENDER_BWD), dtype=torch.uint8, device=dev)
+        self.ws_loss = torch.empty(gs_workspace_size(ctx, views.s, GS_OP_LOSS), dtype=torch.uint8, device=dev)
+        self.lp = LossParams(0.9, 0.1, 1e-6, 0, 0)
+
+    def set_loss_params(self, lambda_pho=0.9, lambda_depth=0.1, eps_A=1e-6, weight_mode=0, grad_through_weight=0):
+        self.lp = LossParams(lambda_pho, lambda_depth, eps_A, weight_mode, grad_through_weight)
+
+    def forward(self, g: Gaussians, stream=None):
+        gs_project(self.ctx, self.views.s, g, self.proj, stream)
+        gs_bin_sort(self.ctx, self.views.s, self.proj, self.bins, self.ws_bin, stream)
+        gs_render_fwd(self.ctx, self.views.s, g, self.proj, self.bins, self.bg, self.img, stream)
+
+    def loss_and_grads(self, target_color, target_depth, stream=None):
+        self._tgt_keep = (target_color, target_depth)
+        tgt = Target(ptr(target_color), ptr(target_depth))
+        gs_loss(self.ctx, self.views.s, self.img, tgt, self.lp, self.loss, self.pg, self.ws_loss, stream)
+
+    def backward(self, g: Gaussians, grads: Grads, stream=None):
+        gs_render_bwd(self.ctx, self.views.s, g, self.proj, self.bins, self.img, self.pg, self.bg, grads,
+                      self.ws_bwd, stream)
+
+    def check(self, stream=None):
+        return gs_bins_check(self.ctx, self.bins, stream)
+
+    def image(self):
+        P = self.P
+        return dict(C=self.img_color.view(3, P), D=self.img_depth, M=self.img_mp, T=self.img_T,
+                    n_last=self.img_nlast)
+
+
+def grads_struct(gr: dict, pose: torch.Tensor, pose_only=False, accumulate=False) -> Grads:
+    s = Grads()
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "color"):
+        setattr(s, k, ptr(gr[k]) if gr is not None and k in gr else None)
+    s.pose = ptr(pose)
+    s.pose_only = int(pose_only)
+    s.accumulate = int(accumulate)
+    return s
+
+
+def alloc_grads(n, device="cuda"):
+    f = torch.float32
+    return dict(mean=torch.zeros(3, n, dtype=f, device=device), log_scale=torch.zeros(3, n, dtype=f, device=device),
+                quat=torch.zeros(4, n, dtype=f, device=device), opacity_logit=torch.zeros(n, dtype=f, device=device),
+                color=torch.zeros(3, n, dtype=f, device=device))

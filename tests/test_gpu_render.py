@@ -1,0 +1,239 @@
+"""GPU parity of the render path (gs_project, gs_bin_sort, gs_render_fwd,
+gs_loss, gs_render_bwd) against the FP64 oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_21644_amd import gs, synth
+from tests.gpu_util import (assert_grads_close, assert_image_close, image_view, make_pipeline, oracle_target,
+                            proj_view, torch_np)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return gs.Context(0)
+
+
+def _near_int(x, tol):
+    return np.abs(x - np.round(x)) < tol
+
+
+def test_project_parity(ctx, orc):
+    g, cam, tcam = synth.tiny_scene()
+    n = synth.n_gaussians(g)
+    for c in (cam, tcam):
+        views, pipe, gt, gst = make_pipeline(ctx, g, [c])
+        gs.gs_project(ctx, views.s, gst, pipe.proj)
+        torch.cuda.synchronize()
+        got = proj_view(pipe, views, 0, n)
+        ref = orc.project(g, c)
+        kept = ref["kept"]
+        gkept = got["key"] != 0xFFFFFFFF
+        assert kept.sum() > 1900
+        assert np.array_equal(gkept, kept)  # every kept one of this scene is on screen
+        np.testing.assert_allclose(got["mean2d"][:, kept], ref["mean2d"][:, kept], rtol=1e-5, atol=1e-4)
+        np.testing.assert_allclose(got["depth"][kept], ref["depth"][kept], rtol=1e-5)
+        np.testing.assert_allclose(got["opacity"][kept], ref["opacity"][kept], rtol=1e-5)
+        for i in range(3):
+            sc = np.abs(ref["conic"][i, kept]).max()
+            np.testing.assert_allclose(got["conic"][i, kept], ref["conic"][i, kept], rtol=1e-4, atol=1e-6 * sc)
+        # integer radius: equal unless the FP64 extent sits within 1e-4 of an integer
+        amb = _near_int(ref["extent"], 1e-4)
+        assert np.all((got["radius"][kept] == ref["radius"][kept]) | amb[kept])
+        x0, y0, x1, y1, empty = orc.tile_rect(ref["mean2d"], ref["radius"], kept, c["width"], c["height"])
+        ambr = amb | _near_int(ref["mean2d"][0], 1e-4) | _near_int(ref["mean2d"][1], 1e-4)
+        same = (got["rect"][:, 0] == x0) & (got["rect"][:, 1] == y0) & (got["rect"][:, 2] == x1) & (
+            got["rect"][:, 3] == y1)
+        assert np.all(same[kept] | ambr[kept])
+
+
+def _bin_case(ctx, orc, seed, m, W, H, chunk, max_tiles=6):
+    rect, key = synth.bin_inputs(seed, m, W, H, max_tiles=max_tiles)
+    g = synth.static_gaussians(synth.rng_for(seed), m, W, H)
+    cam = synth.camera(W, H)
+    ctx.set_param("bin_chunk", chunk)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], capacity=max(1024, m * max_tiles * max_tiles))
+    M = pipe.M
+    rect_full = np.zeros((M, 4), np.int16)
+    rect_full[:, 0] = 1
+    rect_full[:, 1] = 1
+    key_full = np.full(M, 0xFFFFFFFF, np.uint32)
+    rect_full[:m] = rect
+    key_full[:m] = key
+    pipe.rect.copy_(torch.from_numpy(rect_full.reshape(-1)))
+    pipe.key.copy_(torch.from_numpy(key_full.view(np.int32)))
+    gs.gs_bin_sort(ctx, views.s, pipe.proj, pipe.bins, pipe.ws_bin)
+    over, n_inst, _ = pipe.check()
+    ids_ref, ranges = orc.bin_reference(rect, key, ((W + 15) // 16, (H + 15) // 16))
+    assert not over
+    assert n_inst == ids_ref.size
+    ts = torch_np(pipe.tile_start).view(np.uint32).astype(np.int64)
+    np.testing.assert_array_equal(ts[:-1], ranges[:, 0])
+    np.testing.assert_array_equal(ts[1:], ranges[:, 1])
+    got = torch_np(pipe.ids[:n_inst]).view(np.uint32)
+    np.testing.assert_array_equal(got, ids_ref)
+
+
+@pytest.mark.parametrize("seed,m,W,H,chunk", [(1, 3000, 64, 48, 256), (2, 20011, 200, 150, 1024),
+                                              (3, 70000, 640, 480, 1024), (4, 5000, 640, 480, 2048),
+                                              (5, 1, 64, 48, 512)])
+def test_bin_sort_bitexact(ctx, orc, seed, m, W, H, chunk):
+    _bin_case(ctx, orc, seed, m, W, H, chunk)
+    ctx.set_param("bin_chunk", 1024)
+
+
+def test_bin_sort_all_culled_and_overflow(ctx, orc):
+    g = synth.static_gaussians(synth.rng_for(9), 500, 64, 48)
+    g["mean"][2] = -1.0  # everything behind the camera
+    views, pipe, gt, gst = make_pipeline(ctx, g, [synth.camera(64, 48)], capacity=16)
+    pipe.forward(gst)
+    over, n_inst, _ = pipe.check()
+    assert not over and n_inst == 0
+    im = image_view(pipe, views, 0)
+    assert np.all(im["T"] == 1.0) and np.all(im["C"] == 0.0)
+    g, cam, tcam = synth.tiny_scene()
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], capacity=100)
+    pipe.forward(gst)
+    over, n_inst, _ = pipe.check()
+    assert over and n_inst > 100
+
+
+def test_render_fwd_parity_tiny(ctx, orc):
+    g, cam, tcam = synth.tiny_scene()
+    for c, bg in ((cam, (0, 0, 0)), (tcam, (0.2, 0.5, 0.9))):
+        views, pipe, gt, gst = make_pipeline(ctx, g, [c], bg=bg)
+        pipe.forward(gst)
+        torch.cuda.synchronize()
+        got = image_view(pipe, views, 0)
+        ref = orc.render(orc.project(g, c), g, c, bg=bg)
+        assert_image_close(got, ref, ref["margin"])
+
+
+def test_render_fwd_deterministic(ctx):
+    g, cam, tcam = synth.moving_box_scene(2, 20000, 320, 240)[:3]
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam])
+    pipe.forward(gst)
+    a = [t.clone() for t in (pipe.img_color, pipe.img_depth, pipe.img_T, pipe.ids)]
+    pipe.forward(gst)
+    b = [pipe.img_color, pipe.img_depth, pipe.img_T, pipe.ids]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_render_fwd_parity_640(ctx, orc):
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(2, 30000, 640, 480)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [tcam])
+    pipe.forward(gst)
+    torch.cuda.synchronize()
+    got = image_view(pipe, views, 0)
+    ref = orc.render(orc.project(g, tcam), g, tcam)
+    assert_image_close(got, ref, ref["margin"])
+
+
+def _loss_bwd_case(ctx, orc, g, cam, tcam, weight_mode=0, gtw=0, bg=(0, 0, 0)):
+    tc, td = oracle_target(orc, g, tcam)
+    n = synth.n_gaussians(g)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], bg=bg)
+    pipe.set_loss_params(weight_mode=weight_mode, grad_through_weight=gtw)
+    pipe.forward(gst)
+    tcd, tdd = torch.from_numpy(tc.reshape(-1)).cuda(), torch.from_numpy(td).cuda()
+    pipe.loss_and_grads(tcd, tdd)
+    grads = gs.alloc_grads(n)
+    pose = torch.zeros(6, device="cuda")
+    pipe.backward(gst, gs.grads_struct(grads, pose))
+    torch.cuda.synchronize()
+    L, im, rg, pr, _ = orc.full_backward(g, cam, tc, td, bg=bg, weight_mode=weight_mode,
+                                         grad_through_weight=bool(gtw))
+    return pipe, views, grads, pose, L, im, rg
+
+
+@pytest.mark.parametrize("weight_mode,gtw", [(0, 0), (1, 0), (0, 1)])
+def test_loss_and_backward_parity_tiny(ctx, orc, weight_mode, gtw):
+    g, cam, tcam = synth.tiny_scene()
+    pipe, views, grads, pose, L, im, rg = _loss_bwd_case(ctx, orc, g, cam, tcam, weight_mode, gtw)
+    assert abs(float(pipe.loss[0]) - L["loss"]) <= 1e-4 * abs(L["loss"])
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "color"):
+        assert_grads_close(torch_np(grads[k]), rg[k], name=k)
+    assert_grads_close(torch_np(pose), rg["pose"], name="pose")
+
+
+def test_backward_parity_640(ctx, orc):
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(3, 20000, 640, 480)
+    pipe, views, grads, pose, L, im, rg = _loss_bwd_case(ctx, orc, g, cam, tcam, bg=(0.1, 0.1, 0.1))
+    assert abs(float(pipe.loss[0]) - L["loss"]) <= 1e-4 * abs(L["loss"])
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "color"):
+        assert_grads_close(torch_np(grads[k]), rg[k], name=k)
+    assert_grads_close(torch_np(pose), rg["pose"], name="pose")
+
+
+def test_backward_zero_ws_invariant_and_pose_only(ctx, orc):
+    """Two backward calls in a row give identical gradients (the scratch is
+    left zero-filled); pose-only mode gives the same pose gradient."""
+    g, cam, tcam = synth.tiny_scene(seed=4)
+    tc, td = oracle_target(orc, g, tcam)
+    n = synth.n_gaussians(g)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam])
+    pipe.forward(gst)
+    pipe.loss_and_grads(torch.from_numpy(tc.reshape(-1)).cuda(), torch.from_numpy(td).cuda())
+    outs = []
+    for pose_only in (False, False, True):
+        grads = gs.alloc_grads(n)
+        pose = torch.zeros(6, device="cuda")
+        pipe.backward(gst, gs.grads_struct(None if pose_only else grads, pose, pose_only=pose_only))
+        torch.cuda.synchronize()
+        outs.append((grads, pose.clone()))
+    for k in outs[0][0]:
+        assert torch.equal(outs[0][0][k], outs[1][0][k])
+    torch.testing.assert_close(outs[0][1], outs[2][1], rtol=1e-6, atol=1e-6)
+    assert torch.count_nonzero(pipe.ws_bwd) == 0
+
+
+def test_max_rank_prefix_lists(ctx, orc):
+    """Binning only the R nearest records gives exact prefixes of the full
+    lists; when every tile saturates inside them the image is identical."""
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(5, 60000, 640, 480)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam])
+    pipe.forward(gst)
+    full_ids = torch_np(pipe.ids).view(np.uint32).copy()
+    full_ts = torch_np(pipe.tile_start).view(np.uint32).astype(np.int64)
+    full_img = [t.clone() for t in (pipe.img_color, pipe.img_depth, pipe.img_T, pipe.img_nlast)]
+    R = 8192
+    views2, pipe2, gt2, gst2 = make_pipeline(ctx, g, [cam], max_rank=R)
+    pipe2.forward(gst2)
+    over, n_inst, inc = pipe2.check()
+    ts = torch_np(pipe2.tile_start).view(np.uint32).astype(np.int64)
+    ids = torch_np(pipe2.ids).view(np.uint32)
+    sorted_ids = torch_np(pipe2.sorted_ids).view(np.uint32)
+    nearest = set(sorted_ids[:R].tolist())
+    for t in range(0, len(ts) - 1, 37):
+        mine = ids[ts[t]:ts[t + 1]]
+        full = full_ids[full_ts[t]:full_ts[t + 1]]
+        expect = [x for x in full if x in nearest]
+        np.testing.assert_array_equal(mine, expect)
+        np.testing.assert_array_equal(mine, full[:len(mine)])
+    if inc == 0:
+        for a, b in zip(full_img, (pipe2.img_color, pipe2.img_depth, pipe2.img_T, pipe2.img_nlast)):
+            assert torch.equal(a, b)
+
+
+def test_full_size_sampled_pixels(ctx, orc):
+    """1M Gaussians at 640x480 (the benchmark workload): 512 sampled pixels
+    against the oracle, the rest via invariants."""
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(7, 1_000_000, 640, 480)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], capacity=80_000_000, full_proj=False)
+    pipe.forward(gst)
+    over, n_inst, inc = pipe.check()
+    assert not over
+    got = image_view(pipe, views, 0)
+    T = got["T"]
+    assert T.min() >= 1e-4 and T.max() <= 1.0
+    assert np.all(got["M"] <= 1 - T + 1e-5)
+    rng = np.random.default_rng(0)
+    pix = rng.choice(640 * 480, size=512, replace=False)
+    ref = orc.render(orc.project(g, cam), g, cam, pixels=pix)
+    sub = {k: (got[k][:, pix] if k == "C" else got[k][pix]) for k in ("C", "D", "M", "T")}
+    assert_image_close(sub, ref, ref["margin"], max_excluded=0.02)
