@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
     """Compile the C++ oracle with g++ (-O3, OpenMP, FP64; no fast-math)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        cmd = ["g++", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c++17", "-o", tmp, _SRC]
+        cmd = ["g++", "-O3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c++17", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -53,9 +53,9 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
-        L.or_project.argtypes = [I64] + [P] * 5 + [P] * 8
-        L.or_render.argtypes = [I64] + [P] * 7 + [ctypes.c_int, ctypes.c_int, P, I64, P] + [P] * 6
-        L.or_render_backward.argtypes = [I64] + [P] * 7 + [ctypes.c_int, ctypes.c_int, P, I64, P] + [P] * 5
+        L.or_project.argtypes = [I64] + [P] * 5 + [P] * 9
+        L.or_render.argtypes = [I64] + [P] * 8 + [ctypes.c_int, ctypes.c_int, P, I64, P] + [P] * 6
+        L.or_render_backward.argtypes = [I64] + [P] * 8 + [ctypes.c_int, ctypes.c_int, P, I64, P] + [P] * 5
         L.or_project_backward.argtypes = [I64] + [P] * 5 + [P] * 7
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_threads.argtypes = [ctypes.c_int]
@@ -88,15 +88,18 @@ def cam_vector(cam: dict) -> np.ndarray:
 # ------------------------------------------------------------------ projection
 def project(g: dict, cam: dict) -> dict:
     """EWA projection of every Gaussian (FP64). Returns planar arrays and the
-    `kept` mask (culled: non-finite input, z <= z_near, det <= 0, opacity < 1/255)."""
+    `kept` mask (culled: non-finite input, z <= z_near, det <= 0, opacity < 1/255).
+    `zkey` is the float32 camera z that orders Gaussians and decides the
+    near-plane cull (computed with float32 roundings, as the GPU path does)."""
     n = g["opacity_logit"].shape[0]
     mean, ls, q, opl = _d(g["mean"]), _d(g["log_scale"]), _d(g["quat"]), _d(g["opacity_logit"])
     out = dict(mean2d=np.zeros((2, n)), conic=np.zeros((3, n)), cov2d=np.zeros((3, n)), depth=np.zeros(n),
-               opacity=np.zeros(n), extent=np.zeros(n), radius=np.zeros(n, np.int32), kept=np.zeros(n, np.uint8))
+               opacity=np.zeros(n), extent=np.zeros(n), radius=np.zeros(n, np.int32), kept=np.zeros(n, np.uint8),
+               zkey=np.zeros(n))
     cv = cam_vector(cam)
     lib().or_project(n, _p(mean), _p(ls), _p(q), _p(opl), _p(cv), _p(out["mean2d"]), _p(out["conic"]),
                      _p(out["cov2d"]), _p(out["depth"]), _p(out["opacity"]), _p(out["extent"]),
-                     _p(out["radius"]), _p(out["kept"]))
+                     _p(out["radius"]), _p(out["kept"]), _p(out["zkey"]))
     out["kept"] = out["kept"].astype(bool)
     return out
 
@@ -121,8 +124,8 @@ def tile_rect(mean2d, radius, kept, width, height, tile=16):
 
 # ------------------------------------------------------------------ render
 def render(proj: dict, g: dict, cam: dict, bg=(0.0, 0.0, 0.0), pixels=None) -> dict:
-    """Tile-free FP64 render: every kept Gaussian per pixel in (depth, id)
-    order with the alpha clamp, the 1/255 cut-off and the T < 1e-4 stop.
+    """Tile-free FP64 render: every kept Gaussian per pixel in (float32 depth
+    key, id) order with the alpha clamp, the 1/255 cut-off and the T < 1e-4 stop.
     Returns C[3,P], D, M (MP channel), T (final), margin, ncontrib."""
     n = g["opacity_logit"].shape[0]
     W, H = cam["width"], cam["height"]
@@ -135,7 +138,8 @@ def render(proj: dict, g: dict, cam: dict, bg=(0.0, 0.0, 0.0), pixels=None) -> d
                ncontrib=np.zeros(P, np.int32))
     kept = np.ascontiguousarray(proj["kept"], np.uint8)
     color, mp, bgv = _d(g["color"]), _d(g["mp"]), _d(bg)
-    lib().or_render(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(proj["opacity"]),
+    lib().or_render(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(proj["zkey"]),
+                    _p(proj["opacity"]),
                     _p(color), _p(mp), _p(kept), W, H, _p(bgv), npix, _p(pix), _p(out["C"]), _p(out["D"]),
                     _p(out["M"]), _p(out["T"]), _p(out["margin"]), _p(out["ncontrib"]))
     return out
@@ -158,7 +162,8 @@ def render_backward(proj, g, cam, gC, gD, gM=None, gT=None, bg=(0.0, 0.0, 0.0), 
     g2d = np.zeros((10, n))
     kept = np.ascontiguousarray(proj["kept"], np.uint8)
     color, mp, bgv = _d(g["color"]), _d(g["mp"]), _d(bg)
-    lib().or_render_backward(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(proj["opacity"]),
+    lib().or_render_backward(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(proj["zkey"]),
+                             _p(proj["opacity"]),
                              _p(color), _p(mp), _p(kept), W, H, _p(bgv), npix, _p(pix), _p(gC), _p(gD),
                              _p(gM), _p(gT), _p(g2d))
     return g2d

@@ -95,6 +95,7 @@ void quat_rot_derivs(double w, double x, double y, double z, M3 dR[4]) {
 struct Proj {
   bool kept;
   double p[3];         // camera-space mean
+  double zkey;         // float32 camera z that orders and culls (see project_one)
   double qn[4], qnorm; // normalised quaternion and the norm of the input
   M3 Rq;               // rotation of the Gaussian
   double S[3];         // exp(log_scale)
@@ -125,7 +126,20 @@ Proj project_one(const Cam& cam, const double mean[3], const double ls[3], const
   for (int i = 0; i < 3; ++i)
     P.p[i] = cam.R[i][0] * mean[0] + cam.R[i][1] * mean[1] + cam.R[i][2] * mean[2] + cam.t[i];
   const double x = P.p[0], y = P.p[1], z = P.p[2];
-  if (!(z > cam.znear)) return P;
+  // The depth order (a permutation) and the near-plane cull are decisions
+  // taken from a float32 camera z in the GPU path; both sides take them on
+  // the same float32 value: ((R20 m0 + R21 m1) + R22 m2) + t2, each operation
+  // rounded to float32 (inputs are float32, so they convert exactly).
+  {
+    volatile float a = (float)cam.R[2][0] * (float)mean[0];
+    volatile float b = (float)cam.R[2][1] * (float)mean[1];
+    volatile float c = (float)cam.R[2][2] * (float)mean[2];
+    volatile float ab = a + b;
+    volatile float abc = ab + c;
+    volatile float zf = abc + (float)cam.t[2];
+    P.zkey = (double)zf;
+  }
+  if (!(P.zkey > (double)(float)cam.znear)) return P;
   P.qnorm = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   if (!(P.qnorm > 0)) return P;
   for (int i = 0; i < 4; ++i) P.qn[i] = q[i] / P.qnorm;
@@ -171,13 +185,13 @@ Proj project_one(const Cam& cam, const double mean[3], const double ls[3], const
   return P;
 }
 
-// Kept Gaussians in ascending (depth, id) order.
-std::vector<int64_t> depth_order(int64_t n, const double* depth, const uint8_t* kept) {
+// Kept Gaussians in ascending (float32 depth key, id) order.
+std::vector<int64_t> depth_order(int64_t n, const double* zkey, const uint8_t* kept) {
   std::vector<int64_t> ord;
   ord.reserve(n);
   for (int64_t k = 0; k < n; ++k)
     if (kept[k]) ord.push_back(k);
-  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return depth[a] < depth[b]; });
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return zkey[a] < zkey[b]; });
   return ord;
 }
 
@@ -195,7 +209,6 @@ double composite_pixel(int i, int j, const std::vector<int64_t>& ord, const doub
                        const double* mp, double out[6], std::vector<Step>* steps, int* ncontrib) {
   double T = 1.0, C[3] = {0, 0, 0}, D = 0, M = 0;
   double margin = 1e30;
-  double prev_z = -1.0;
   int nc = 0;
   for (size_t s = 0; s < ord.size(); ++s) {
     const int64_t k = ord[s];
@@ -212,11 +225,6 @@ double composite_pixel(int i, int j, const std::vector<int64_t>& ord, const doub
     if (alpha < 1.0 / 255.0) continue;
     const double Tn = T * (1.0 - alpha);
     margin = std::min(margin, std::fabs(std::log(Tn / 1e-4)));
-    // an order swap needs two contributors closer in depth than float32
-    // rounding of z (~1e-7 relative): the gap enters scaled by 10, so pairs
-    // closer than 1e-6 relative fall under the 1e-5 margin
-    if (prev_z > 0) margin = std::min(margin, 10.0 * std::fabs(depth[k] - prev_z) / depth[k]);
-    prev_z = depth[k];
     if (Tn < 1e-4) break;
     if (steps) steps->push_back(Step{k, alpha, T, G, araw > 0.99, dx, dy});
     for (int c = 0; c < 3; ++c) C[c] += alpha * T * color[c * n + k];
@@ -254,7 +262,7 @@ void or_set_threads(int n) {
 // Outputs are planar; culled Gaussians have kept = 0 and undefined values.
 int or_project(int64_t n, const double* mean, const double* log_scale, const double* quat, const double* opl,
                const double* camv, double* mean2d, double* conic, double* cov2d, double* depth,
-               double* opacity, double* extent, int32_t* radius, uint8_t* kept) {
+               double* opacity, double* extent, int32_t* radius, uint8_t* kept, double* zkey) {
   const Cam cam = read_cam(camv);
 #pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < n; ++k) {
@@ -269,6 +277,7 @@ int or_project(int64_t n, const double* mean, const double* log_scale, const dou
       cov2d[c * n + k] = P.cov[c];
     }
     depth[k] = P.p[2];
+    zkey[k] = P.zkey;
     opacity[k] = P.o;
     extent[k] = P.extent;
     radius[k] = P.radius;
@@ -278,11 +287,12 @@ int or_project(int64_t n, const double* mean, const double* log_scale, const dou
 
 // Tile-free render. If npix >= 0, only the listed pixel indices (y*W + x) are
 // rendered and outputs are indexed by position in that list; otherwise all W*H.
-int or_render(int64_t n, const double* mean2d, const double* conic, const double* depth, const double* opacity,
-              const double* color, const double* mp, const uint8_t* kept, int W, int H, const double* bg,
+int or_render(int64_t n, const double* mean2d, const double* conic, const double* depth, const double* zkey,
+              const double* opacity, const double* color, const double* mp, const uint8_t* kept, int W, int H,
+              const double* bg,
               int64_t npix, const int64_t* pix, double* C, double* D, double* M, double* T, double* margin,
               int32_t* ncontrib) {
-  const std::vector<int64_t> ord = depth_order(n, depth, kept);
+  const std::vector<int64_t> ord = depth_order(n, zkey, kept);
   const int64_t P = npix >= 0 ? npix : (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t q = 0; q < P; ++q) {
@@ -306,10 +316,11 @@ int or_render(int64_t n, const double* mean2d, const double* conic, const double
 // term of C is added here). Output per-Gaussian 2D adjoints, planar [10][n]:
 // (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth).
 int or_render_backward(int64_t n, const double* mean2d, const double* conic, const double* depth,
-                       const double* opacity, const double* color, const double* mp, const uint8_t* kept, int W,
+                       const double* zkey, const double* opacity, const double* color, const double* mp,
+                       const uint8_t* kept, int W,
                        int H, const double* bg, int64_t npix, const int64_t* pix, const double* gC,
                        const double* gD, const double* gM, const double* gT, double* g2d) {
-  const std::vector<int64_t> ord = depth_order(n, depth, kept);
+  const std::vector<int64_t> ord = depth_order(n, zkey, kept);
   const int64_t P = npix >= 0 ? npix : (int64_t)W * H;
   std::memset(g2d, 0, sizeof(double) * 10 * n);
 #pragma omp parallel

@@ -40,7 +40,9 @@ __device__ __forceinline__ ProjF project_f(const gs_camera& cam, const float m[3
   const float* T = cam.T_cw;
   P.px = T[0] * m[0] + T[1] * m[1] + T[2] * m[2] + T[3];
   P.py = T[4] * m[0] + T[5] * m[1] + T[6] * m[2] + T[7];
-  P.pz = T[8] * m[0] + T[9] * m[1] + T[10] * m[2] + T[11];
+  // camera z with every rounding spelled out: it orders the Gaussians (the
+  // sort key is its bit pattern) and decides the near-plane cull
+  P.pz = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(T[8], m[0]), __fmul_rn(T[9], m[1])), __fmul_rn(T[10], m[2])), T[11]);
   if (!fin || !(P.pz > cam.z_near)) return P;
   const float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
   if (!(qq > 0.f)) return P;

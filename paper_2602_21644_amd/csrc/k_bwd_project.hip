@@ -172,20 +172,25 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
 }
 
 // Sums the per-block pose partials of view blockIdx.x in a fixed order.
-__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(const float* __restrict__ part, int nblk,
+// The partials are reset to zero after reading, so the scratch stays zero-filled.
+__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict__ part, int nblk,
                                                               float* __restrict__ pose, int accumulate) {
   __shared__ double s[GS_BLOCK];
   const int v = blockIdx.x;
   for (int c = 0; c < 6; ++c) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) acc += (double)part[((int64_t)v * nblk + b) * 6 + c];
+    for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) {
+      float* q = &part[((int64_t)v * nblk + b) * 6 + c];
+      acc += (double)*q;
+      *q = 0.f;
+    }
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int o = GS_BLOCK / 2; o > 0; o >>= 1) {
       if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
       __syncthreads();
     }
-    if (threadIdx.x == 0) pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + s[0] : s[0]);
+    if (threadIdx.x == 0 && pose) pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + s[0] : s[0]);
     __syncthreads();
   }
 }
@@ -200,10 +205,8 @@ gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* c
                        g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
                        gr->color, pose_part, gr->pose_only, gr->accumulate);
   }
-  if (gr->pose) {
-    hipLaunchKernelGGL(pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, nblk, gr->pose,
-                       gr->accumulate);
-  }
+  hipLaunchKernelGGL(pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, nblk, gr->pose,
+                     gr->accumulate);
   return gs_check_launch(ctx, "render_bwd_project");
 }
 

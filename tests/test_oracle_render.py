@@ -317,3 +317,19 @@ def test_bin_reference_matches_bruteforce(orc):
         mine.sort(key=lambda k: (int(key[k]), k))
         b, e = ranges[t]
         assert list(ids[b:e]) == mine
+
+
+def test_depth_key_is_float32_camera_z(orc):
+    """The ordering key is camera z evaluated with float32 roundings in the
+    order ((R20 m0 + R21 m1) + R22 m2) + t2; it agrees with the float64 depth
+    to float32 precision, and exactly equal keys keep id order."""
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(2, 3000, 64, 48)
+    pr = orc.project(g, tcam)
+    T = np.asarray(tcam["T_cw"], np.float32)
+    m = g["mean"]
+    f = np.float32
+    z32 = (((T[2, 0] * m[0]).astype(f) + (T[2, 1] * m[1]).astype(f)).astype(f) + (T[2, 2] * m[2]).astype(f)).astype(f)
+    z32 = (z32 + T[2, 3]).astype(f)
+    k = pr["kept"]
+    np.testing.assert_array_equal(pr["zkey"][k], z32[k].astype(np.float64))
+    np.testing.assert_allclose(pr["zkey"][k], pr["depth"][k], rtol=2e-7)
