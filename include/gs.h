@@ -174,10 +174,17 @@ const char* gs_status_str(gs_status s);
 gs_status gs_ctx_create(int device, gs_ctx** out);
 gs_status gs_ctx_destroy(gs_ctx* ctx);
 const char* gs_last_error(const gs_ctx* ctx);
-/* Tuning knobs (see gs_param_names): render batch, backward batch, binning
- * chunk. Values outside the supported set return GS_E_ARG. */
+/* Tuning knobs: "render_batch" (64|128|256 list entries staged per LDS batch
+ * in gs_render_fwd), "bwd_batch" (32|64|128, gs_render_bwd), "bin_chunk"
+ * (256|512|1024|2048 records per binning workgroup), and "timing" (0|1, see
+ * gs_ctx_kernel_times). Values outside the supported set return GS_E_ARG. */
 gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
 gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value /*[host]*/);
+/* Measurement aid. With "timing" = 1 every kernel launch is bracketed by HIP
+ * events on its stream (do not capture such launches in a graph). This call
+ * waits for the pending events, writes one line "kernel launches total_ms" per
+ * kernel into buf [host] (truncated to len bytes) and clears the record. */
+gs_status gs_ctx_kernel_times(gs_ctx* ctx, char* buf, size_t len);
 
 /* Host-side layout helpers. */
 int64_t gs_rec_offset(const gs_views* views, int32_t view);

@@ -44,14 +44,53 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->render_batch = 128;
   c->bwd_batch = 64;
   c->bin_chunk = 1024;
+  c->timing = 0;
   c->err[0] = 0;
   *out = c;
   return GS_OK;
 }
 
 gs_status gs_ctx_destroy(gs_ctx* ctx) {
+  if (ctx) {
+    for (auto& t : ctx->pending) {
+      hipEventDestroy(t.a);
+      hipEventDestroy(t.b);
+    }
+  }
   delete ctx;
   return GS_OK;
+}
+
+gs_status gs_ctx_kernel_times(gs_ctx* ctx, char* buf, size_t len) {
+  if (!ctx || !buf || len == 0) return GS_E_ARG;
+  struct Acc {
+    const char* name;
+    long n;
+    double ms;
+  };
+  std::vector<Acc> acc;
+  gs_status st = GS_OK;
+  for (auto& t : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
+      st = gs_fail(ctx, GS_E_HIP, "reading kernel timing events failed");
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+    size_t i = 0;
+    while (i < acc.size() && strcmp(acc[i].name, t.name) != 0) ++i;
+    if (i == acc.size()) acc.push_back(Acc{t.name, 0, 0.0});
+    acc[i].n += 1;
+    acc[i].ms += ms;
+  }
+  ctx->pending.clear();
+  size_t o = 0;
+  buf[0] = 0;
+  for (auto& a : acc) {
+    const int w = snprintf(buf + o, len - o, "%s %ld %.6f\n", a.name, a.n, a.ms);
+    if (w < 0 || (size_t)w >= len - o) break;
+    o += (size_t)w;
+  }
+  return st;
 }
 
 const char* gs_last_error(const gs_ctx* ctx) { return ctx ? ctx->err : "null context"; }
@@ -64,6 +103,8 @@ gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value) {
   } else if (!strcmp(name, "bwd_batch")) {
     if (value != 32 && value != 64 && value != 128) return gs_fail(ctx, GS_E_ARG, "bwd_batch: 32|64|128");
     ctx->bwd_batch = (int)value;
+  } else if (!strcmp(name, "timing")) {
+    ctx->timing = value ? 1 : 0;
   } else if (!strcmp(name, "bin_chunk")) {
     if (value != 256 && value != 512 && value != 1024 && value != 2048)
       return gs_fail(ctx, GS_E_ARG, "bin_chunk: 256|512|1024|2048");
@@ -79,6 +120,7 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   if (!strcmp(name, "render_batch")) *value = ctx->render_batch;
   else if (!strcmp(name, "bwd_batch")) *value = ctx->bwd_batch;
   else if (!strcmp(name, "bin_chunk")) *value = ctx->bin_chunk;
+  else if (!strcmp(name, "timing")) *value = ctx->timing;
   else return GS_E_ARG;
   return GS_OK;
 }

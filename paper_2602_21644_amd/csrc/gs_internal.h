@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/gs.h"
 
 #define GS_BLOCK 256
@@ -91,13 +93,38 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
 // Host helpers
+struct GsTimer {
+  const char* name;
+  hipEvent_t a, b;
+};
+
 struct gs_ctx {
   int device;
   int render_batch;
   int bwd_batch;
   int bin_chunk;
+  int timing;                    // 1: bracket every launch with HIP events
+  std::vector<GsTimer> pending;  // launches whose events are not read yet
   char err[512];
 };
+
+// Kernel launch; with ctx->timing set, records a start and a stop event on the
+// launch stream around it (measurement only: not for graph capture).
+#define GS_LAUNCH(ctx, kern, grid, block, shm, strm, ...)                   \
+  do {                                                                      \
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;                                \
+    const bool t_ = (ctx) && (ctx)->timing;                                 \
+    if (t_) {                                                               \
+      hipEventCreate(&e0_);                                                 \
+      hipEventCreate(&e1_);                                                 \
+      hipEventRecord(e0_, strm);                                            \
+    }                                                                       \
+    hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);          \
+    if (t_) {                                                               \
+      hipEventRecord(e1_, strm);                                            \
+      (ctx)->pending.push_back(GsTimer{#kern, e0_, e1_});                   \
+    }                                                                       \
+  } while (0)
 
 gs_status gs_fail(gs_ctx* ctx, gs_status s, const char* fmt, ...);
 gs_status gs_check_launch(gs_ctx* ctx, const char* what);

@@ -96,9 +96,9 @@ __global__ __launch_bounds__(GS_BLOCK) void scan_apply_kernel(uint32_t* __restri
 gs_status exclusive_scan(gs_ctx* ctx, uint32_t* a, int64_t n, uint32_t* part, int64_t* total, hipStream_t s) {
   const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (nb == 0) return GS_OK;
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(GS_BLOCK), 0, s, a, n, part);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(GS_BLOCK), 0, s, part, nb, total);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(GS_BLOCK), 0, s, a, n, part);
+  GS_LAUNCH(ctx, scan_reduce_kernel, dim3((unsigned)nb), dim3(GS_BLOCK), 0, s, a, n, part);
+  GS_LAUNCH(ctx, scan_partials_kernel, dim3(1), dim3(GS_BLOCK), 0, s, part, nb, total);
+  GS_LAUNCH(ctx, scan_apply_kernel, dim3((unsigned)nb), dim3(GS_BLOCK), 0, s, a, n, part);
   return gs_check_launch(ctx, "scan");
 }
 
@@ -472,23 +472,23 @@ gs_status launch_bin_sort(gs_ctx* ctx, const ViewTab& tab, const BinTab& bt, con
   if (maxblk > 0) {
     for (int pass = 0; pass < 4; ++pass) {
       const int shift = pass * RADIX_BITS;
-      hipLaunchKernelGGL(radix_hist_kernel, dim3(maxblk, tab.nv), dim3(GS_BLOCK), 0, s, tab, bt, kin, shift, hist);
+      GS_LAUNCH(ctx, radix_hist_kernel, dim3(maxblk, tab.nv), dim3(GS_BLOCK), 0, s, tab, bt, kin, shift, hist);
       gs_status st = exclusive_scan(ctx, hist, L.hist_n, part, nullptr, s);
       if (st != GS_OK) return st;
-      hipLaunchKernelGGL(radix_scatter_kernel, dim3(maxblk, tab.nv), dim3(GS_BLOCK), 0, s, tab, bt, kin, vin,
+      GS_LAUNCH(ctx, radix_scatter_kernel, dim3(maxblk, tab.nv), dim3(GS_BLOCK), 0, s, tab, bt, kin, vin,
                          kouts[pass], vouts[pass], shift, hist);
       kin = kouts[pass];
       vin = vouts[pass];
     }
   }
   const size_t lds = bin_lds_bytes(tab);
-  hipLaunchKernelGGL(bin_count_kernel, dim3(maxchunk, tab.nv), dim3(GS_BLOCK), lds / 4, s, tab, bt,
+  GS_LAUNCH(ctx, bin_count_kernel, dim3(maxchunk, tab.nv), dim3(GS_BLOCK), lds / 4, s, tab, bt,
                      bins->sorted_ids, (const int2*)proj->rect, proj->depth_key, cm);
   gs_status st = exclusive_scan(ctx, cm, L.cm_n, part, total, s);
   if (st != GS_OK) return st;
-  hipLaunchKernelGGL(bin_ranges_kernel, dim3((tab.ntiles + GS_BLOCK) / GS_BLOCK), dim3(GS_BLOCK), 0, s, tab, bt, cm,
+  GS_LAUNCH(ctx, bin_ranges_kernel, dim3((tab.ntiles + GS_BLOCK) / GS_BLOCK), dim3(GS_BLOCK), 0, s, tab, bt, cm,
                      total, bins->capacity, bins->tile_start, bins->n_instances, bins->overflow, bins->incomplete);
-  hipLaunchKernelGGL(bin_scatter_kernel, dim3(maxchunk, tab.nv), dim3(GS_BLOCK), lds, s, tab, bt,
+  GS_LAUNCH(ctx, bin_scatter_kernel, dim3(maxchunk, tab.nv), dim3(GS_BLOCK), lds, s, tab, bt,
                      bins->sorted_ids, (const int2*)proj->rect, proj->depth_key, cm, bins->overflow,
                      bins->gauss_id);
   return gs_check_launch(ctx, "bin_sort");

@@ -201,11 +201,11 @@ gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* c
                              float* g2d, uint8_t* touched, float* pose_part, gs_grads* gr, hipStream_t s) {
   const int nblk = (int)((tab.ng + GS_BLOCK - 1) / GS_BLOCK);
   if (nblk > 0) {
-    hipLaunchKernelGGL(bwd_project_kernel, dim3(nblk), dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale,
+    GS_LAUNCH(ctx, bwd_project_kernel, dim3(nblk), dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale,
                        g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
                        gr->color, pose_part, gr->pose_only, gr->accumulate);
   }
-  hipLaunchKernelGGL(pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, nblk, gr->pose,
+  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, nblk, gr->pose,
                      gr->accumulate);
   return gs_check_launch(ctx, "render_bwd_project");
 }

@@ -93,9 +93,9 @@ gs_status launch_loss(gs_ctx* ctx, const ViewTab& tab, const gs_image* img, cons
                       const gs_loss_params* lp, float* loss, gs_pixel_grads* pg, double* part, hipStream_t s) {
   const int nb = loss_blocks(tab);
   if (nb == 0) return GS_OK;
-  hipLaunchKernelGGL(loss_kernel, dim3(nb, tab.nv), dim3(GS_BLOCK), 0, s, tab, img->color, img->depth, img->mp,
+  GS_LAUNCH(ctx, loss_kernel, dim3(nb, tab.nv), dim3(GS_BLOCK), 0, s, tab, img->color, img->depth, img->mp,
                      img->T, tgt->color, tgt->depth, lp->lambda_pho, lp->lambda_depth, lp->eps_A, lp->weight_mode,
                      lp->grad_through_weight, pg->dcolor, pg->ddepth, pg->dmp, pg->dT, part);
-  hipLaunchKernelGGL(loss_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, part, nb, loss);
+  GS_LAUNCH(ctx, loss_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, part, nb, loss);
   return gs_check_launch(ctx, "loss");
 }

@@ -244,20 +244,20 @@ gs_status launch_mlp_features(gs_ctx* ctx, const ViewTab& tab, const gs_image* i
                               const gs_mp_frame* fr, float* x, hipStream_t s) {
   const int64_t P = tab.npix;
   if (P > 0)
-    hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s, P,
+    GS_LAUNCH(ctx, mlp_features_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s, P,
                        fr->n_inst, img->color, img->depth, img->mp, img->T, tgt->color, tgt->depth, fr->instance_id,
                        fr->inst_prior, x);
   return gs_check_launch(ctx, "mlp_features");
 }
 
 gs_status launch_mlp_sync(gs_ctx* ctx, gs_mlp* mlp, hipStream_t s) {
-  hipLaunchKernelGGL(mlp_sync_kernel, dim3(6), dim3(GS_BLOCK), 0, s, mlp->master, mlp->w_bf16);
+  GS_LAUNCH(ctx, mlp_sync_kernel, dim3(6), dim3(GS_BLOCK), 0, s, mlp->master, mlp->w_bf16);
   return gs_check_launch(ctx, "mlp_sync");
 }
 
 gs_status launch_mlp_fwd(gs_ctx* ctx, const gs_mlp* mlp, const float* x, float* y, int64_t P, hipStream_t s) {
   if (P > 0)
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s,
+    GS_LAUNCH(ctx, mlp_fwd_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s,
                        mlp->master, mlp->w_bf16, x, y, P);
   return gs_check_launch(ctx, "mlp_fwd");
 }
@@ -267,10 +267,10 @@ gs_status launch_mlp_train(gs_ctx* ctx, gs_mlp* mlp, const float* x, const float
   const int nb = (int)((P + GS_BLOCK - 1) / GS_BLOCK);
   float* part = (float*)ws;
   double* lpart = (double*)(ws + al((size_t)nb * NP * 4));
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(nb), dim3(GS_BLOCK), 0, s, mlp->master, mlp->w_bf16, x, label, P, part,
+  GS_LAUNCH(ctx, mlp_grad_kernel, dim3(nb), dim3(GS_BLOCK), 0, s, mlp->master, mlp->w_bf16, x, label, P, part,
                      lpart);
-  hipLaunchKernelGGL(mlp_adam_kernel, dim3((NP + GS_BLOCK - 1) / GS_BLOCK), dim3(GS_BLOCK), 0, s, part, lpart, nb, P,
+  GS_LAUNCH(ctx, mlp_adam_kernel, dim3((NP + GS_BLOCK - 1) / GS_BLOCK), dim3(GS_BLOCK), 0, s, part, lpart, nb, P,
                      lr, step, mlp->master, mlp->adam_m, mlp->adam_v, grad, loss);
-  hipLaunchKernelGGL(mlp_sync_kernel, dim3(6), dim3(GS_BLOCK), 0, s, mlp->master, mlp->w_bf16);
+  GS_LAUNCH(ctx, mlp_sync_kernel, dim3(6), dim3(GS_BLOCK), 0, s, mlp->master, mlp->w_bf16);
   return gs_check_launch(ctx, "mlp_train_step");
 }

@@ -421,32 +421,32 @@ gs_status launch_mp_update(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj,
   const int K = fr->n_inst;
   const int nb = (int)((P + REG_TILE - 1) / REG_TILE);
   if (nb > 0)
-    hipLaunchKernelGGL(mp_region_kernel, dim3(nb), dim3(GS_BLOCK), 0, s, P, P, K, img->depth, tgt->depth, img->color,
+    GS_LAUNCH(ctx, mp_region_kernel, dim3(nb), dim3(GS_BLOCK), 0, s, P, P, K, img->depth, tgt->depth, img->color,
                        tgt->color, fr->instance_id, pp->beta_color, e, part);
-  hipLaunchKernelGGL(mp_region_final_kernel, dim3(1), dim3(64), 0, s, part, nb, K, pp->lambda_e, pp->e_floor,
+  GS_LAUNCH(ctx, mp_region_final_kernel, dim3(1), dim3(64), 0, s, part, nb, K, pp->lambda_e, pp->e_floor,
                      pp->sigma_g, sc);
   if (P > 0)
-    hipLaunchKernelGGL(mp_pixel_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s, P, K,
+    GS_LAUNCH(ctx, mp_pixel_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s, P, K,
                        e, fr->instance_id, fr->inst_prior, fr->inst_conf, fr->mlp_mp, pp->sigma_small, sc, Mp,
                        out->e);
   const unsigned gb = (unsigned)((n + GS_BLOCK - 1) / GS_BLOCK);
   if (n > 0) {
-    hipLaunchKernelGGL(mp_gauss_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, proj->mean2d, proj->depth_key,
+    GS_LAUNCH(ctx, mp_gauss_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, proj->mean2d, proj->depth_key,
                        tgt->depth, Mp, e, mp, pp->radius_px, pp->sigma_w, pp->lambda_u, pp->eps, go, sc);
-    hipLaunchKernelGGL(mp_state_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, go, sc, pp->sigma_c, pp->lambda_u,
+    GS_LAUNCH(ctx, mp_state_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, go, sc, pp->sigma_c, pp->lambda_u,
                        pp->alpha_min, pp->alpha_max, pp->rho, fr->seg_updated, pp->mode, pp->u_norm, pp->logodds_eps,
                        pp->logodds_max, mp, out->U_tilde, out->alpha);
   }
-  hipLaunchKernelGGL(mp_sel_reset_kernel, dim3(1), dim3(GS_BLOCK), 0, s, sc);
+  GS_LAUNCH(ctx, mp_sel_reset_kernel, dim3(1), dim3(GS_BLOCK), 0, s, sc);
   const unsigned sb = gb < 1024 ? (gb > 0 ? gb : 1) : 1024;
   for (int pass = 0; pass < 4; ++pass) {
-    hipLaunchKernelGGL(mp_sel_hist_kernel, dim3(sb), dim3(GS_BLOCK), 0, s, n, tab.g_off[0], go.obs, mp, out->U_tilde,
+    GS_LAUNCH(ctx, mp_sel_hist_kernel, dim3(sb), dim3(GS_BLOCK), 0, s, n, tab.g_off[0], go.obs, mp, out->U_tilde,
                        pass, sc);
-    hipLaunchKernelGGL(mp_sel_pick_kernel, dim3(1), dim3(64), 0, s, pass, sc);
+    GS_LAUNCH(ctx, mp_sel_pick_kernel, dim3(1), dim3(64), 0, s, pass, sc);
   }
   if (n > 0)
-    hipLaunchKernelGGL(mp_label_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, mp, pp->prune_above, sc, out->dynamic,
+    GS_LAUNCH(ctx, mp_label_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, mp, pp->prune_above, sc, out->dynamic,
                        out->prune);
-  hipLaunchKernelGGL(mp_stats_kernel, dim3(1), dim3(64), 0, s, sc, out->stats);
+  GS_LAUNCH(ctx, mp_stats_kernel, dim3(1), dim3(64), 0, s, sc, out->stats);
   return gs_check_launch(ctx, "mp_update");
 }

@@ -82,7 +82,7 @@ gs_status launch_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams,
   for (int v = 0; v < tab.nv; ++v) maxn = tab.npad[v] > maxn ? tab.npad[v] : maxn;
   if (maxn == 0) return GS_OK;
   dim3 grid((unsigned)((maxn + GS_BLOCK - 1) / GS_BLOCK), tab.nv);
-  hipLaunchKernelGGL(project_kernel, grid, dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale, g->quat,
+  GS_LAUNCH(ctx, project_kernel, grid, dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale, g->quat,
                      g->opacity_logit, g->color, g->mp, (float4*)p->rec, (int2*)p->rect, p->depth_key, p->mean2d,
                      p->conic, p->depth, p->opacity, p->radius);
   return gs_check_launch(ctx, "project");

@@ -127,6 +127,7 @@ def lib():
             "gs_last_error": ([P], ctypes.c_char_p),
             "gs_ctx_set_param": ([P, ctypes.c_char_p, c_int64], c_int32),
             "gs_ctx_get_param": ([P, ctypes.c_char_p, POINTER(c_int64)], c_int32),
+            "gs_ctx_kernel_times": ([P, ctypes.c_char_p, c_size_t], c_int32),
             "gs_rec_offset": ([POINTER(Views), c_int32], c_int64),
             "gs_rec_count": ([POINTER(Views)], c_int64),
             "gs_tile_count": ([POINTER(Views)], c_int64),
@@ -159,7 +160,7 @@ def lib():
 
 
 EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error", "gs_ctx_set_param",
-            "gs_ctx_get_param", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
+            "gs_ctx_get_param", "gs_ctx_kernel_times", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_bwd",
             "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step")
 
@@ -193,6 +194,16 @@ class Context:
         v = c_int64()
         self.check(lib().gs_ctx_get_param(self.h, name.encode(), ctypes.byref(v)), "get_param " + name)
         return v.value
+
+    def kernel_times(self):
+        """{kernel: (launches, total_ms)} since the last call (timing mode)."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        self.check(lib().gs_ctx_kernel_times(self.h, buf, len(buf)), "gs_ctx_kernel_times")
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, n, ms = line.rsplit(" ", 2)
+            out[name] = (int(n), float(ms))
+        return out
 
     def __del__(self):
         try:
