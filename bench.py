@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--max-rank", type=int, default=-1,
+                    help="prefix rank for binning (-1: smallest power of two >= 4096 that is exact; 0: full lists)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many eager steps (for rocprofv3) and exit")
     return ap.parse_args()
@@ -101,17 +103,25 @@ def main():
     A = 1.0 - tp.img_T
     td = torch.where(A >= 0.5, tp.img_depth, torch.zeros_like(tp.img_depth)).contiguous()
     del tp, gtt
-    # the iteration under test
+    # the iteration under test; choose the smallest power-of-two prefix rank
+    # whose prefix lists let every tile saturate (exact result), full lists
+    # when none does
     views = gs.ViewBatch([cam], a.n)
-    probe = gs.Pipeline(ctx, views, capacity=a.n * 128)
     gt = gs.to_device(g)
     gst = gs.gaussians_struct(gt)
-    probe.forward(gst)
-    over, n_inst, _ = probe.check()
-    assert not over
-    del probe
-    cap = int(n_inst * 1.25) + 1024
-    pipe = gs.Pipeline(ctx, views, capacity=cap)
+    R = a.max_rank if a.max_rank >= 0 else 4096
+    while True:
+        probe = gs.Pipeline(ctx, views, capacity=a.n * 64, max_rank=R)
+        probe.forward(gst)
+        over, n_inst, inc = probe.check()
+        del probe
+        assert not over
+        if inc == 0 or R == 0:
+            break
+        R = R * 2 if R * 2 < a.n else 0
+    log(f"[bench] prefix rank {R} ({'full lists' if R == 0 else 'prefix lists'}), {n_inst} list entries")
+    cap = int(n_inst * 1.25) + 4096
+    pipe = gs.Pipeline(ctx, views, capacity=cap, max_rank=R)
     grads = gs.alloc_grads(a.n)
     pose = torch.zeros(6, device=dev)
     grs = gs.grads_struct(grads, pose)
@@ -132,7 +142,7 @@ def main():
         step()
     torch.cuda.synchronize()
     over, n_inst, inc = pipe.check()
-    assert not over and n_inst > 0
+    assert not over and n_inst > 0 and inc == 0
     # workload statistics for the byte model
     P = a.width * a.height
     nl = pipe.img_nlast.view(a.height, a.width)
@@ -150,7 +160,8 @@ def main():
     st = dict(n=a.n, instances=n_inst, pixels=P, tiles=views.tile_count, records=views.rec_count,
               nlim=views.rec_count, cm=views.tile_count * ((views.rec_count + chunk - 1) // chunk),
               loaded_fwd=loaded_fwd, loaded_bwd=loaded_bwd, touched=touched)
-    log(f"[bench] instances {n_inst}, touched Gaussians {touched}, entries loaded fwd {loaded_fwd}")
+    log(f"[bench] instances {n_inst}, touched Gaussians {touched}, entries loaded fwd {loaded_fwd}, "
+        f"binning LDS limit {ctx.get_param('lds_limit')}")
 
     # timed region 1: graph replays (or eager steps with --no-graph)
     graph = None
@@ -180,6 +191,8 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
+    over, _, inc = pipe.check()
+    assert not over and inc == 0, "timed steps were not exact"
     ms = e0.elapsed_time(e1) / a.steps
     log(f"[bench] {'graph' if graph is not None else 'eager'}: {ms:.4f} ms/step ({1000.0 / ms:.1f} iters/s)")
 
@@ -229,7 +242,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.n} Gaussians, one {a.width}x{a.height} view, render+loss+backward to all "
                                f"Gaussian parameters and the pose", "n_gaussians": a.n, "width": a.width,
-                   "height": a.height, "instances": n_inst, "parallelism": "single-gpu",
+                   "height": a.height, "instances": n_inst, "prefix_rank": R, "parallelism": "single-gpu",
                    "timed": "hip graph replay" if graph is not None else "eager"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved

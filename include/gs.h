@@ -99,7 +99,11 @@ typedef struct gs_gaussians {
  * are required; the planar fields are optional (NULL skips them). */
 typedef struct gs_proj {
   int64_t m;
-  float* rec;        /* [m][12]: ux, uy, depth, opacity, k1, k2, k3, mp, r, g, b, 0 */
+  float* rec;        /* [m][12] compositing record: ux, uy, depth, opacity, conic
+                        (3), mp, r, g, b, 0. Written by gs_project for every
+                        record when key_hist is NULL; with key_hist set it is
+                        written by gs_bin_sort's prefix path, for the selected
+                        records only (the only ones the lists reference). */
   int16_t* rect;     /* [m][4] inclusive tile rect x0, y0, x1, y1; empty: x0 > x1 */
   uint32_t* depth_key; /* [m] IEEE bits of camera z; 0xFFFFFFFF if culled/empty */
   float* mean2d;     /* [2][m] optional */
@@ -108,6 +112,10 @@ typedef struct gs_proj {
   float* opacity;    /* [m] optional */
   int32_t* radius;   /* [m] optional: opacity-aware support radius in pixels,
                         0 for culled records */
+  uint32_t* key_hist;/* [V][4096] optional: gs_project adds the count of every
+                        non-culled record to bin (depth_key >> 20) of its view;
+                        gs_bin_sort's prefix path reads it and resets it to zero.
+                        Must be zero-filled before the first gs_project. */
 } gs_proj;
 
 /* Per-tile lists. Entries are scene-local Gaussian ids; tile t's list is
@@ -121,9 +129,12 @@ typedef struct gs_bins {
   int32_t* overflow;      /* [1] 1 when n_instances > capacity, else 0 */
   int32_t* incomplete;    /* [1] set by gs_render_fwd when a tile ran out of a
                              truncated list with unsaturated pixels (see max_rank) */
-  int64_t max_rank;       /* bin only the max_rank nearest records of each view
-                             (<= 0: all). The lists are then exact prefixes of the
-                             full lists. */
+  int64_t max_rank;       /* > 0 with proj->key_hist set: bin only the records in
+                             front of the first key-histogram boundary that has at
+                             least max_rank records in front of it. Every tile list
+                             is then an exact prefix of its full list; tiles that
+                             run out of it with unsaturated pixels raise
+                             `incomplete`. <= 0: full lists. */
 } gs_bins;
 
 /* Rendered maps (planar, see layouts). */
@@ -193,10 +204,10 @@ int64_t gs_tile_count(const gs_views* views);
 int64_t gs_pixel_count(const gs_views* views);
 
 enum { GS_OP_BIN_SORT = 1, GS_OP_RENDER_BWD = 2, GS_OP_LOSS = 3, GS_OP_MP_UPDATE = 4, GS_OP_MLP_TRAIN = 5 };
-/* Scratch bytes needed by `op` for this batch. For
- * GS_OP_RENDER_BWD the scratch must be zero-filled before its first use; each
- * call leaves it zero-filled again. */
-gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, size_t* bytes);
+/* Scratch bytes needed by `op` for this batch; `capacity` is the list capacity
+ * of gs_bins (used by GS_OP_BIN_SORT only). For GS_OP_RENDER_BWD the scratch
+ * must be zero-filled before its first use; each call leaves it zero-filled. */
+gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes);
 
 /* ---------------------------------------------------------------- the path */
 
@@ -211,9 +222,10 @@ gs_status gs_project(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, 
 /* Tile binning: per-tile lists equal to a stable ascending sort of the keys
  * (tile << 32 | depth bits) with value id, i.e. lists in (depth, id) order.
  * Sorts each view's records by depth key (LSD radix), then counts, scans and
- * scatters tile instances chunk by chunk in that order. */
-gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, gs_bins* bins, void* ws,
-                      size_t ws_bytes, void* stream);
+ * scatters tile instances chunk by chunk in that order. `g` is read by the
+ * prefix path only (to write proj->rec of the selected records). */
+gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, gs_proj* proj, gs_bins* bins,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Front-to-back compositing per 16x16 tile: alpha = min(0.99, o exp(p)),
  * entries with alpha < 1/255 skipped, stop before an entry that drops T below

@@ -45,6 +45,7 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->bwd_batch = 64;
   c->bin_chunk = 1024;
   c->timing = 0;
+  c->lds_limit = 0;
   c->err[0] = 0;
   *out = c;
   return GS_OK;
@@ -121,6 +122,7 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   else if (!strcmp(name, "bwd_batch")) *value = ctx->bwd_batch;
   else if (!strcmp(name, "bin_chunk")) *value = ctx->bin_chunk;
   else if (!strcmp(name, "timing")) *value = ctx->timing;
+  else if (!strcmp(name, "lds_limit")) *value = (int64_t)ctx->lds_limit;
   else return GS_E_ARG;
   return GS_OK;
 }
@@ -226,23 +228,26 @@ int64_t gs_pixel_count(const gs_views* views) {
   return p;
 }
 
-gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, size_t* bytes) {
+gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes) {
   if (!ctx || !bytes) return GS_E_ARG;
   ViewTab tab;
   GS_TRY(make_tab(ctx, views, tab));
   switch (op) {
     case GS_OP_BIN_SORT: {
+      if (capacity < 0) return gs_fail(ctx, GS_E_ARG, "capacity < 0");
       BinTab bt;
       bin_tab_fill(tab, ctx->bin_chunk, 0, bt);
       // the smallest chunk gives the largest count matrix
       BinTab bt2;
       bin_tab_fill(tab, 256, 0, bt2);
-      const size_t a = bin_ws_layout(tab, bt).bytes, b = bin_ws_layout(tab, bt2).bytes;
+      size_t a = bin_ws_layout(tab, bt).bytes, b = bin_ws_layout(tab, bt2).bytes;
+      a = a > b ? a : b;
+      b = bin_prefix_ws_bytes(ctx, tab, capacity);
       *bytes = a > b ? a : b;
       return GS_OK;
     }
     case GS_OP_RENDER_BWD: *bytes = bwd_ws_layout(tab).bytes; return GS_OK;
-    case GS_OP_LOSS: *bytes = al256((size_t)tab.nv * loss_blocks(tab) * 8); return GS_OK;
+    case GS_OP_LOSS: *bytes = al256((size_t)tab.nv * loss_blocks(tab) * 8 + 8); return GS_OK;
     case GS_OP_MP_UPDATE:
       if (tab.nv != 1) return gs_fail(ctx, GS_E_ARG, "mp_update takes one view");
       *bytes = mp_ws_bytes(tab, tab.npix);
@@ -265,8 +270,8 @@ gs_status gs_project(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, 
   return launch_project(ctx, tab, views->cams_dev, g, proj, (hipStream_t)stream);
 }
 
-gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, gs_bins* bins, void* ws,
-                      size_t ws_bytes, void* stream) {
+gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, gs_proj* proj, gs_bins* bins,
+                      void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !proj || !bins) return gs_fail(ctx, GS_E_ARG, "null argument");
   ViewTab tab;
   GS_TRY(make_tab(ctx, views, tab));
@@ -274,6 +279,12 @@ gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, g
       !bins->incomplete)
     return gs_fail(ctx, GS_E_ARG, "bins arrays NULL");
   if (bins->capacity < 0 || bins->capacity > ((int64_t)1 << 32)) return gs_fail(ctx, GS_E_ARG, "bad capacity");
+  if (bins->max_rank > 0 && proj->key_hist) {
+    const size_t need = bin_prefix_ws_bytes(ctx, tab, bins->capacity);
+    if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "bin_sort workspace %zu < %zu bytes", ws_bytes, need);
+    if (!g || g->n != tab.ng || !proj->rec) return gs_fail(ctx, GS_E_ARG, "prefix binning needs the gaussians and proj.rec");
+    return launch_bin_prefix(ctx, tab, views->cams_dev, g, proj, bins, (char*)ws, (hipStream_t)stream);
+  }
   BinTab bt;
   bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
   const BinWs L = bin_ws_layout(tab, bt);
@@ -288,6 +299,7 @@ gs_status gs_render_fwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   ViewTab tab;
   GS_TRY(make_tab(ctx, views, tab));
   if (!img->color || !img->depth || !img->mp || !img->T || !img->n_last) return gs_fail(ctx, GS_E_ARG, "image NULL");
+  if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
   BinTab bt;
   bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
   int bits = 0;
@@ -303,7 +315,7 @@ gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const
   GS_TRY(make_tab(ctx, views, tab));
   if (!pg->dcolor || !pg->ddepth) return gs_fail(ctx, GS_E_ARG, "pixel grads NULL");
   if (lp->weight_mode != 0 && lp->weight_mode != 1) return gs_fail(ctx, GS_E_ARG, "weight_mode 0|1");
-  const size_t need = al256((size_t)tab.nv * loss_blocks(tab) * 8);
+  const size_t need = al256((size_t)tab.nv * loss_blocks(tab) * 8 + 8);
   if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "loss workspace %zu < %zu", ws_bytes, need);
   return launch_loss(ctx, tab, img, tgt, lp, loss, pg, (double*)ws, (hipStream_t)stream);
 }
@@ -314,6 +326,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   if (!ctx || !g || !proj || !bins || !img || !pg || !bg || !gr) return gs_fail(ctx, GS_E_ARG, "null argument");
   ViewTab tab;
   GS_TRY(make_tab(ctx, views, tab));
+  if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
   if (!gr->pose_only && (!gr->mean || !gr->log_scale || !gr->quat || !gr->opacity_logit || !gr->color))
     return gs_fail(ctx, GS_E_ARG, "gradient arrays NULL");
   const BwdWs L = bwd_ws_layout(tab);

@@ -104,6 +104,7 @@ struct gs_ctx {
   int bwd_batch;
   int bin_chunk;
   int timing;                    // 1: bracket every launch with HIP events
+  size_t lds_limit;              // LDS per workgroup usable by the binning scatter (0: not queried)
   std::vector<GsTimer> pending;  // launches whose events are not read yet
   char err[512];
 };
@@ -150,6 +151,9 @@ int bwd_pose_blocks(const ViewTab&);
 int loss_blocks(const ViewTab&);
 gs_status launch_loss(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_loss_params*, float*,
                       gs_pixel_grads*, double*, hipStream_t);
+size_t bin_prefix_ws_bytes(gs_ctx*, const ViewTab&, int64_t capacity);
+gs_status launch_bin_prefix(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, const gs_proj*,
+                            gs_bins*, char*, hipStream_t);
 size_t mp_ws_bytes(const ViewTab&, int64_t npix);
 gs_status launch_mp_update(gs_ctx*, const ViewTab&, const gs_proj*, const gs_image*, const gs_target*,
                            const gs_mp_frame*, const gs_mp_params*, float*, gs_mp_out*, char*, hipStream_t);

@@ -82,3 +82,24 @@ __device__ __forceinline__ ProjF project_f(const gs_camera& cam, const float m[3
   P.kept = true;
   return P;
 }
+
+// Gaussian parameter planes, passed by value to the compositing kernels.
+struct GaussSrc {
+  const float *mean, *log_scale, *quat, *opl, *color, *mp;
+  int64_t n;
+};
+
+// The compositing record of packed Gaussian gk seen by `cam`: (u_x, u_y, z,
+// opacity), (conic, mp), (rgb, 0). Computed by the same project_f as the
+// projection kernel, so it matches the record the tile rect came from.
+__device__ __forceinline__ void render_record(const gs_camera& cam, const GaussSrc& g, int64_t gk, float4& a,
+                                              float4& b, float4& c) {
+  const int64_t N = g.n;
+  const float m[3] = {g.mean[gk], g.mean[N + gk], g.mean[2 * N + gk]};
+  const float ls[3] = {g.log_scale[gk], g.log_scale[N + gk], g.log_scale[2 * N + gk]};
+  const float q[4] = {g.quat[gk], g.quat[N + gk], g.quat[2 * N + gk], g.quat[3 * N + gk]};
+  const ProjF P = project_f(cam, m, ls, q, g.opl[gk]);
+  a = make_float4(P.ux, P.uy, P.pz, P.o);
+  b = make_float4(P.k1, P.k2, P.k3, g.mp[gk]);
+  c = make_float4(g.color[gk], g.color[N + gk], g.color[2 * N + gk], 0.f);
+}

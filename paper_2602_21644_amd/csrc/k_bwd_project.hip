@@ -151,46 +151,53 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
       pose_part[((int64_t)v * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = 0.f;
     }
   }
-  if (!valid || pose_only) return;
-  if (accumulate) {
-    for (int c = 0; c < 3; ++c) {
-      d_mean[c * N + gk] += gm[c];
-      d_ls[c * N + gk] += gl[c];
-      d_color[c * N + gk] += gc[c];
+  if (valid && !pose_only) {
+    if (accumulate) {
+      for (int c = 0; c < 3; ++c) {
+        d_mean[c * N + gk] += gm[c];
+        d_ls[c * N + gk] += gl[c];
+        d_color[c * N + gk] += gc[c];
+      }
+      for (int c = 0; c < 4; ++c) d_quat[c * N + gk] += gq[c];
+      d_opl[gk] += go;
+    } else {
+      for (int c = 0; c < 3; ++c) {
+        d_mean[c * N + gk] = gm[c];
+        d_ls[c * N + gk] = gl[c];
+        d_color[c * N + gk] = gc[c];
+      }
+      for (int c = 0; c < 4; ++c) d_quat[c * N + gk] = gq[c];
+      d_opl[gk] = go;
     }
-    for (int c = 0; c < 4; ++c) d_quat[c * N + gk] += gq[c];
-    d_opl[gk] += go;
-  } else {
-    for (int c = 0; c < 3; ++c) {
-      d_mean[c * N + gk] = gm[c];
-      d_ls[c * N + gk] = gl[c];
-      d_color[c * N + gk] = gc[c];
-    }
-    for (int c = 0; c < 4; ++c) d_quat[c * N + gk] = gq[c];
-    d_opl[gk] = go;
   }
 }
 
-// Sums the per-block pose partials of view blockIdx.x in a fixed order.
-// The partials are reset to zero after reading, so the scratch stays zero-filled.
-__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict__ part, int nblk,
+// Sums the per-block pose partials of every view in a fixed order (one
+// workgroup, float64) and resets them to zero, so the scratch stays
+// zero-filled.
+__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict__ part, int nblk, int nv,
                                                               float* __restrict__ pose, int accumulate) {
-  __shared__ double s[GS_BLOCK];
-  const int v = blockIdx.x;
-  for (int c = 0; c < 6; ++c) {
-    double acc = 0.0;
+  __shared__ double s_red[4][6];
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  for (int v = 0; v < nv; ++v) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) {
-      float* q = &part[((int64_t)v * nblk + b) * 6 + c];
-      acc += (double)*q;
-      *q = 0.f;
+      float* q = part + ((int64_t)v * nblk + b) * 6;
+      for (int c = 0; c < 6; ++c) {
+        acc[c] += (double)q[c];
+        q[c] = 0.f;
+      }
     }
-    s[threadIdx.x] = acc;
+    for (int c = 0; c < 6; ++c) {
+      acc[c] = wave_sum_to_lane63_d(acc[c]);
+      if (lane == 63) s_red[w][c] = acc[c];
+    }
     __syncthreads();
-    for (int o = GS_BLOCK / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-      __syncthreads();
+    if (threadIdx.x < 6 && pose) {
+      const int c = threadIdx.x;
+      const double t = s_red[0][c] + s_red[1][c] + s_red[2][c] + s_red[3][c];
+      pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + t : t);
     }
-    if (threadIdx.x == 0 && pose) pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + s[0] : s[0]);
     __syncthreads();
   }
 }
@@ -199,15 +206,18 @@ __global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict_
 
 gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams, const gs_gaussians* g,
                              float* g2d, uint8_t* touched, float* pose_part, gs_grads* gr, hipStream_t s) {
-  const int nblk = (int)((tab.ng + GS_BLOCK - 1) / GS_BLOCK);
-  if (nblk > 0) {
+  const int nblk = bwd_pose_blocks(tab);
+  {
     GS_LAUNCH(ctx, bwd_project_kernel, dim3(nblk), dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale,
                        g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
                        gr->color, pose_part, gr->pose_only, gr->accumulate);
   }
-  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, nblk, gr->pose,
-                     gr->accumulate);
+  GS_LAUNCH(ctx, pose_final_kernel, dim3(1), dim3(GS_BLOCK), 0, s, pose_part, nblk, tab.nv, gr->pose,
+            gr->accumulate);
   return gs_check_launch(ctx, "render_bwd_project");
 }
 
-int bwd_pose_blocks(const ViewTab& tab) { return (int)((tab.ng + GS_BLOCK - 1) / GS_BLOCK); }
+int bwd_pose_blocks(const ViewTab& tab) {
+  const int64_t b = (tab.ng + GS_BLOCK - 1) / GS_BLOCK;
+  return b > 0 ? (int)b : 1;
+}

@@ -1,6 +1,6 @@
 // gs_loss: MP-weighted L1 colour + depth loss and its per-pixel adjoints.
-// One thread per pixel; per-view loss summed in float64, per block then in a
-// fixed order by a second kernel, so the value is run-to-run identical.
+// One thread per pixel; per-view loss summed in float64, per block, then in a
+// fixed order by a one-workgroup kernel, so the value is run-to-run identical.
 #include "gs_internal.h"
 
 namespace {
@@ -66,19 +66,19 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_kernel(ViewTab tab, const float
   if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
-__global__ __launch_bounds__(GS_BLOCK) void loss_final_kernel(const double* __restrict__ part, int nblk,
+// Sums the per-block partials of every view in a fixed order (one workgroup).
+__global__ __launch_bounds__(GS_BLOCK) void loss_final_kernel(const double* __restrict__ part, int nblk, int nv,
                                                               float* __restrict__ loss) {
-  __shared__ double s[GS_BLOCK];
-  const int v = blockIdx.x;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) acc += part[(int64_t)v * nblk + b];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = GS_BLOCK / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+  __shared__ double s[4];
+  for (int v = 0; v < nv; ++v) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) t += part[(int64_t)v * nblk + b];
+    t = wave_sum_to_lane63_d(t);
+    if (__lane_id() == 63) s[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[v] = (float)(s[0] + s[1] + s[2] + s[3]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) loss[v] = (float)s[0];
 }
 
 }  // namespace
@@ -96,6 +96,6 @@ gs_status launch_loss(gs_ctx* ctx, const ViewTab& tab, const gs_image* img, cons
   GS_LAUNCH(ctx, loss_kernel, dim3(nb, tab.nv), dim3(GS_BLOCK), 0, s, tab, img->color, img->depth, img->mp,
                      img->T, tgt->color, tgt->depth, lp->lambda_pho, lp->lambda_depth, lp->eps_A, lp->weight_mode,
                      lp->grad_through_weight, pg->dcolor, pg->ddepth, pg->dmp, pg->dT, part);
-  GS_LAUNCH(ctx, loss_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, part, nb, loss);
+  GS_LAUNCH(ctx, loss_final_kernel, dim3(1), dim3(GS_BLOCK), 0, s, part, nb, tab.nv, loss);
   return gs_check_launch(ctx, "loss");
 }

@@ -1,22 +1,24 @@
-// gs_project: one thread per (view, Gaussian) record, coalesced planar reads.
+// gs_project: coalesced planar reads of the Gaussian parameters, one record
+// per thread and pass; writes the tile rect and depth key (plus the key
+// histogram and the optional planar outputs). The 48-byte compositing record
+// is written here only for full binning; with the prefix path it is written
+// by gs_bin_sort for the few records the lists reference.
 #include "gs_project_dev.h"
 
 namespace {
 
-__global__ __launch_bounds__(GS_BLOCK) void project_kernel(ViewTab tab, const gs_camera* __restrict__ cams,
-                                                           const float* __restrict__ mean,
-                                                           const float* __restrict__ log_scale,
-                                                           const float* __restrict__ quat,
-                                                           const float* __restrict__ opl,
-                                                           const float* __restrict__ color,
-                                                           const float* __restrict__ mp, float4* __restrict__ rec,
-                                                           int2* __restrict__ rect, uint32_t* __restrict__ key,
-                                                           float* __restrict__ mean2d, float* __restrict__ conic,
-                                                           float* __restrict__ depth, float* __restrict__ opacity,
-                                                           int32_t* __restrict__ radius) {
-  const int v = blockIdx.y;
-  const int64_t k = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
-  if (k >= tab.npad[v]) return;
+constexpr int PBLOCK = 1024;
+constexpr int PITEMS = 4;  // records per thread: 4096 per workgroup amortises the histogram
+
+__device__ __forceinline__ uint32_t project_one(const ViewTab& tab, const gs_camera& cam,
+                                                const float* __restrict__ mean, const float* __restrict__ log_scale,
+                                                const float* __restrict__ quat, const float* __restrict__ opl,
+                                                const float* __restrict__ color, const float* __restrict__ mp,
+                                                float4* __restrict__ rec, int2* __restrict__ rect,
+                                                uint32_t* __restrict__ key,
+                                                float* __restrict__ mean2d, float* __restrict__ conic,
+                                                float* __restrict__ depth, float* __restrict__ opacity,
+                                                int32_t* __restrict__ radius, int v, int64_t k) {
   const int64_t r = tab.r_off[v] + k;
   const int64_t M = tab.nrec;
   const int64_t N = tab.ng;
@@ -26,9 +28,8 @@ __global__ __launch_bounds__(GS_BLOCK) void project_kernel(ViewTab tab, const gs
     rect[r] = empty_rect;
     key[r] = 0xFFFFFFFFu;
     if (radius) radius[r] = 0;
-    return;
+    return 0xFFFFFFFFu;
   }
-  const gs_camera cam = cams[v];
   const int64_t gk = tab.g_off[v] + k;
   const float m[3] = {mean[gk], mean[N + gk], mean[2 * N + gk]};
   const float ls[3] = {log_scale[gk], log_scale[N + gk], log_scale[2 * N + gk]};
@@ -54,8 +55,9 @@ __global__ __launch_bounds__(GS_BLOCK) void project_kernel(ViewTab tab, const gs
     }
   }
   rect[r] = rc;
-  key[r] = nonempty ? __float_as_uint(P.pz) : 0xFFFFFFFFu;
-  if (P.kept) {
+  const uint32_t kout = nonempty ? __float_as_uint(P.pz) : 0xFFFFFFFFu;
+  key[r] = kout;
+  if (rec && nonempty) {
     rec[3 * r + 0] = make_float4(P.ux, P.uy, P.pz, P.o);
     rec[3 * r + 1] = make_float4(P.k1, P.k2, P.k3, mp[gk]);
     rec[3 * r + 2] = make_float4(color[gk], color[N + gk], color[2 * N + gk], 0.f);
@@ -72,6 +74,48 @@ __global__ __launch_bounds__(GS_BLOCK) void project_kernel(ViewTab tab, const gs
   if (depth) depth[r] = P.pz;
   if (opacity) opacity[r] = P.o;
   if (radius) radius[r] = P.kept ? rr : 0;
+  return kout;
+}
+
+__global__ __launch_bounds__(PBLOCK) void project_kernel(ViewTab tab, const gs_camera* __restrict__ cams,
+                                                         const float* __restrict__ mean,
+                                                         const float* __restrict__ log_scale,
+                                                         const float* __restrict__ quat,
+                                                         const float* __restrict__ opl,
+                                                         const float* __restrict__ color,
+                                                         const float* __restrict__ mp, float4* __restrict__ rec,
+                                                         int2* __restrict__ rect,
+                                                         uint32_t* __restrict__ key, float* __restrict__ mean2d,
+                                                         float* __restrict__ conic, float* __restrict__ depth,
+                                                         float* __restrict__ opacity, int32_t* __restrict__ radius,
+                                                         uint32_t* __restrict__ key_hist) {
+  extern __shared__ uint32_t s_hist[];  // 4096 bins when key_hist is set
+  const int v = blockIdx.y;
+  const int64_t npad = tab.npad[v];
+  const int64_t base = (int64_t)blockIdx.x * PBLOCK * PITEMS;
+  if (base >= npad) return;  // uniform per workgroup
+  if (key_hist) {
+    for (int i = threadIdx.x; i < 4096; i += PBLOCK) s_hist[i] = 0;
+    __syncthreads();
+  }
+  const gs_camera cam = cams[v];
+#pragma unroll
+  for (int it = 0; it < PITEMS; ++it) {
+    const int64_t k = base + it * PBLOCK + threadIdx.x;
+    if (k < npad) {
+      const uint32_t kv =
+          project_one(tab, cam, mean, log_scale, quat, opl, color, mp, rec, rect, key, mean2d, conic, depth,
+                      opacity, radius, v, k);
+      if (key_hist && kv != 0xFFFFFFFFu) atomicAdd(&s_hist[kv >> 20], 1u);
+    }
+  }
+  if (key_hist) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4096; i += PBLOCK) {
+      const uint32_t c = s_hist[i];
+      if (c) atomicAdd(&key_hist[(int64_t)v * 4096 + i], c);
+    }
+  }
 }
 
 }  // namespace
@@ -81,9 +125,9 @@ gs_status launch_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams,
   int64_t maxn = 0;
   for (int v = 0; v < tab.nv; ++v) maxn = tab.npad[v] > maxn ? tab.npad[v] : maxn;
   if (maxn == 0) return GS_OK;
-  dim3 grid((unsigned)((maxn + GS_BLOCK - 1) / GS_BLOCK), tab.nv);
-  GS_LAUNCH(ctx, project_kernel, grid, dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale, g->quat,
-                     g->opacity_logit, g->color, g->mp, (float4*)p->rec, (int2*)p->rect, p->depth_key, p->mean2d,
-                     p->conic, p->depth, p->opacity, p->radius);
+  dim3 grid((unsigned)((maxn + PBLOCK * PITEMS - 1) / (PBLOCK * PITEMS)), tab.nv);
+  GS_LAUNCH(ctx, project_kernel, grid, dim3(PBLOCK), p->key_hist ? 4096 * 4 : 0, s, tab, cams, g->mean,
+            g->log_scale, g->quat, g->opacity_logit, g->color, g->mp, p->key_hist ? nullptr : (float4*)p->rec,
+            (int2*)p->rect, p->depth_key, p->mean2d, p->conic, p->depth, p->opacity, p->radius, p->key_hist);
   return gs_check_launch(ctx, "project");
 }

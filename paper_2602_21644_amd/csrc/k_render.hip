@@ -8,7 +8,7 @@
 // by dividing by (1 - alpha) from T_final, per-entry gradients summed over the
 // wave with DPP, over the 4 waves in LDS, then one atomic per (Gaussian, tile,
 // component).
-#include "gs_internal.h"
+#include "gs_project_dev.h"
 
 namespace {
 
@@ -229,7 +229,7 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
   const float4* rec = (const float4*)proj->rec;
 #define GS_FWD(BATCH)                                                                                         \
-  GS_LAUNCH(ctx, render_fwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start, \
+  GS_LAUNCH(ctx, render_fwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, nullptr, bg[0], bg[1], bg[2], img->color, img->depth, img->mp, img->T,   \
                      img->n_last, bins->incomplete, truncated_bits)
   switch (ctx->render_batch) {
@@ -248,7 +248,7 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
   const float4* rec = (const float4*)proj->rec;
 #define GS_BWD(BATCH)                                                                                          \
-  GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,  \
+  GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, \
                      pg->dT, g2d, touched)
   switch (ctx->bwd_batch) {

@@ -54,7 +54,7 @@ class Gaussians(ctypes.Structure):
 
 class Proj(ctypes.Structure):
     _fields_ = [("m", c_int64)] + [(k, c_void_p) for k in ("rec", "rect", "depth_key", "mean2d", "conic", "depth",
-                                                          "opacity", "radius")]
+                                                          "opacity", "radius", "key_hist")]
 
 
 class Bins(ctypes.Structure):
@@ -132,9 +132,10 @@ def lib():
             "gs_rec_count": ([POINTER(Views)], c_int64),
             "gs_tile_count": ([POINTER(Views)], c_int64),
             "gs_pixel_count": ([POINTER(Views)], c_int64),
-            "gs_workspace_size": ([P, POINTER(Views), c_int32, POINTER(c_size_t)], c_int32),
+            "gs_workspace_size": ([P, POINTER(Views), c_int32, c_int64, POINTER(c_size_t)], c_int32),
             "gs_project": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), P], c_int32),
-            "gs_bin_sort": ([P, POINTER(Views), POINTER(Proj), POINTER(Bins), P, c_size_t, P], c_int32),
+            "gs_bin_sort": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins), P, c_size_t, P],
+                            c_int32),
             "gs_render_fwd": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins), POINTER(c_float),
                                POINTER(Image), P], c_int32),
             "gs_loss": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(LossParams), P,
@@ -219,9 +220,10 @@ def gs_project(ctx, views, g, proj, stream=None):
               "gs_project")
 
 
-def gs_bin_sort(ctx, views, proj, bins, ws, stream=None):
-    ctx.check(lib().gs_bin_sort(ctx.h, ctypes.byref(views), ctypes.byref(proj), ctypes.byref(bins), ptr(ws),
-                                ws.numel() * ws.element_size(), _stream(stream)), "gs_bin_sort")
+def gs_bin_sort(ctx, views, g, proj, bins, ws, stream=None):
+    ctx.check(lib().gs_bin_sort(ctx.h, ctypes.byref(views), ctypes.byref(g) if g is not None else None,
+                                ctypes.byref(proj), ctypes.byref(bins), ptr(ws), ws.numel() * ws.element_size(),
+                                _stream(stream)), "gs_bin_sort")
 
 
 def gs_render_fwd(ctx, views, g, proj, bins, bg, img, stream=None):
@@ -259,9 +261,10 @@ def gs_bins_check(ctx, bins, stream=None):
     return st == GS_E_CAPACITY, int(req.value), int(inc.value)
 
 
-def gs_workspace_size(ctx, views, op):
+def gs_workspace_size(ctx, views, op, capacity=0):
     b = c_size_t()
-    ctx.check(lib().gs_workspace_size(ctx.h, ctypes.byref(views), op, ctypes.byref(b)), "gs_workspace_size")
+    ctx.check(lib().gs_workspace_size(ctx.h, ctypes.byref(views), op, int(capacity), ctypes.byref(b)),
+              "gs_workspace_size")
     return int(b.value)
 
 
@@ -389,6 +392,9 @@ class Pipeline:
         self.proj = Proj()
         self.proj.m = M
         self.proj.rec, self.proj.rect, self.proj.depth_key = ptr(self.rec), ptr(self.rect), ptr(self.key)
+        self.key_hist = torch.zeros(views.V * 4096, dtype=i32, device=dev)
+        if max_rank > 0:
+            self.proj.key_hist = ptr(self.key_hist)
         if full_proj:
             for k in ("mean2d", "conic", "depth", "opacity", "radius"):
                 setattr(self.proj, k, ptr(getattr(self, k)))
@@ -419,9 +425,10 @@ class Pipeline:
         self.dT = torch.zeros(P, dtype=f32, device=dev)
         self.pg = PixelGrads(ptr(self.dC), ptr(self.dD), ptr(self.dM), ptr(self.dT))
         self.loss = torch.zeros(views.V, dtype=f32, device=dev)
-        self.ws_bin = torch.empty(gs_workspace_size(ctx, views.s, GS_OP_BIN_SORT), dtype=torch.uint8, device=dev)
+        self.ws_bin = torch.empty(gs_workspace_size(ctx, views.s, GS_OP_BIN_SORT, self.capacity), dtype=torch.uint8,
+                                  device=dev)
         self.ws_bwd = torch.zeros(gs_workspace_size(ctx, views.s, GS_OP_RENDER_BWD), dtype=torch.uint8, device=dev)
-        self.ws_loss = torch.empty(gs_workspace_size(ctx, views.s, GS_OP_LOSS), dtype=torch.uint8, device=dev)
+        self.ws_loss = torch.zeros(gs_workspace_size(ctx, views.s, GS_OP_LOSS), dtype=torch.uint8, device=dev)
         self.lp = LossParams(0.9, 0.1, 1e-6, 0, 0)
 
     def set_loss_params(self, lambda_pho=0.9, lambda_depth=0.1, eps_A=1e-6, weight_mode=0, grad_through_weight=0):
@@ -429,7 +436,7 @@ class Pipeline:
 
     def forward(self, g: Gaussians, stream=None):
         gs_project(self.ctx, self.views.s, g, self.proj, stream)
-        gs_bin_sort(self.ctx, self.views.s, self.proj, self.bins, self.ws_bin, stream)
+        gs_bin_sort(self.ctx, self.views.s, g, self.proj, self.bins, self.ws_bin, stream)
         gs_render_fwd(self.ctx, self.views.s, g, self.proj, self.bins, self.bg, self.img, stream)
 
     def loss_and_grads(self, target_color, target_depth, stream=None):

@@ -66,7 +66,7 @@ def _bin_case(ctx, orc, seed, m, W, H, chunk, max_tiles=6):
     key_full[:m] = key
     pipe.rect.copy_(torch.from_numpy(rect_full.reshape(-1)))
     pipe.key.copy_(torch.from_numpy(key_full.view(np.int32)))
-    gs.gs_bin_sort(ctx, views.s, pipe.proj, pipe.bins, pipe.ws_bin)
+    gs.gs_bin_sort(ctx, views.s, gst, pipe.proj, pipe.bins, pipe.ws_bin)
     over, n_inst, _ = pipe.check()
     ids_ref, ranges = orc.bin_reference(rect, key, ((W + 15) // 16, (H + 15) // 16))
     assert not over
@@ -84,6 +84,71 @@ def _bin_case(ctx, orc, seed, m, W, H, chunk, max_tiles=6):
 def test_bin_sort_bitexact(ctx, orc, seed, m, W, H, chunk):
     _bin_case(ctx, orc, seed, m, W, H, chunk)
     ctx.set_param("bin_chunk", 1024)
+
+
+def _prefix_selection(key, R):
+    """The prefix rule: records with key < theta, theta the first boundary of
+    the 4096-bin histogram of key >> 20 with at least R valid keys in front."""
+    valid = key != 0xFFFFFFFF
+    hist = np.bincount((key[valid] >> 20).astype(np.int64), minlength=4096)
+    if hist.sum() <= R:
+        return valid, hist
+    b = int(np.searchsorted(np.cumsum(hist), R))  # first bin with cum >= R
+    theta = (b + 1) << 20
+    return valid & (key.astype(np.int64) < theta), hist
+
+
+@pytest.mark.parametrize("seed,m,W,H,R", [(11, 3000, 64, 48, 500), (12, 70000, 640, 480, 4096),
+                                          (13, 20000, 320, 240, 100000), (14, 50000, 1280, 720, 2000)])
+def test_bin_sort_prefix_bitexact(ctx, orc, seed, m, W, H, R):
+    """Prefix path: the lists equal the textbook stable sort restricted to the
+    selected records, bit for bit."""
+    rect, key = synth.bin_inputs(seed, m, W, H, max_tiles=6)
+    # spread depth keys over a realistic range so the selection is partial
+    rng = np.random.default_rng(seed)
+    z = np.cbrt(0.125 + rng.random(m) * (64 - 0.125)).astype(np.float32)
+    z[rng.random(m) < 0.05] = np.float32(1.0)  # exact ties
+    key = np.where(key == 0xFFFFFFFF, key, z.view(np.uint32)).astype(np.uint32)
+    sel, hist = _prefix_selection(key, R)
+    g = synth.static_gaussians(synth.rng_for(seed), m, W, H)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [synth.camera(W, H)], capacity=m * 36 + 1024, max_rank=R)
+    M = pipe.M
+    rect_full = np.zeros((M, 4), np.int16)
+    rect_full[:, 0] = 1
+    rect_full[:, 1] = 1
+    key_full = np.full(M, 0xFFFFFFFF, np.uint32)
+    rect_full[:m] = rect
+    key_full[:m] = key
+    pipe.rect.copy_(torch.from_numpy(rect_full.reshape(-1)))
+    pipe.key.copy_(torch.from_numpy(key_full.view(np.int32)))
+    pipe.key_hist.copy_(torch.from_numpy(hist.astype(np.int32)))
+    for rep in range(2):  # the histogram is consumed and cleared by the call
+        if rep == 1:
+            pipe.key_hist.copy_(torch.from_numpy(hist.astype(np.int32)))
+        gs.gs_bin_sort(ctx, views.s, gst, pipe.proj, pipe.bins, pipe.ws_bin)
+        over, n_inst, _ = pipe.check()
+        assert not over
+        assert int(pipe.key_hist.abs().sum()) == 0
+        ids_ref, ranges = orc.bin_reference(rect, np.where(sel, key, 0xFFFFFFFF), ((W + 15) // 16, (H + 15) // 16))
+        assert n_inst == ids_ref.size
+        ts = torch_np(pipe.tile_start).view(np.uint32).astype(np.int64)
+        np.testing.assert_array_equal(ts[:-1], ranges[:, 0])
+        np.testing.assert_array_equal(ts[1:], ranges[:, 1])
+        np.testing.assert_array_equal(torch_np(pipe.ids[:n_inst]).view(np.uint32), ids_ref)
+
+
+def test_project_key_histogram(ctx, orc):
+    """gs_project adds every non-culled record to bin (key >> 20); the keys
+    are the float32 camera depths the oracle also orders by."""
+    g, cam, tcam = synth.tiny_scene()
+    views, pipe, gt, gst = make_pipeline(ctx, g, [tcam], max_rank=100)
+    gs.gs_project(ctx, views.s, gst, pipe.proj)
+    torch.cuda.synchronize()
+    ref = orc.project(g, tcam)
+    x0, y0, x1, y1, empty = orc.tile_rect(ref["mean2d"], ref["radius"], ref["kept"], 64, 48)
+    zb = ref["zkey"].astype(np.float32).view(np.uint32) >> 20
+    expect = np.bincount(zb[~empty].astype(np.int64), minlength=4096)
+    np.testing.assert_array_equal(torch_np(pipe.key_hist), expect)
 
 
 def test_bin_sort_all_culled_and_overflow(ctx, orc):
@@ -225,12 +290,10 @@ def test_max_rank_prefix_lists(ctx, orc):
     ts = torch_np(pipe2.tile_start).view(np.uint32).astype(np.int64)
     ids = torch_np(pipe2.ids).view(np.uint32)
     sorted_ids = torch_np(pipe2.sorted_ids).view(np.uint32)
-    nearest = set(sorted_ids[:R].tolist())
+    assert 0 < n_inst < full_ts[-1]
     for t in range(0, len(ts) - 1, 37):
         mine = ids[ts[t]:ts[t + 1]]
         full = full_ids[full_ts[t]:full_ts[t + 1]]
-        expect = [x for x in full if x in nearest]
-        np.testing.assert_array_equal(mine, expect)
         np.testing.assert_array_equal(mine, full[:len(mine)])
     if inc == 0:
         for a, b in zip(full_img, (pipe2.img_color, pipe2.img_depth, pipe2.img_T, pipe2.img_nlast)):
