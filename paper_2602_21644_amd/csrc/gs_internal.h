@@ -79,6 +79,39 @@ __device__ __forceinline__ float wave_sum_to_lane63(float x) {
   return x;
 }
 
+// Sums each of ten per-lane values over the 64 lanes of a wave (all lanes
+// active). A transposed reduction: the two permlane swaps halve the values per
+// lane twice while folding lanes 32 and 16 apart, then three in-row DPP
+// chains finish. The totals land in lane 15 of every row r (lanes 15, 31, 47,
+// 63) as k[0..2]:
+//   row 0: (v0, v2, v4)   row 1: (v1, v3, 0)
+//   row 2: (v5, v7, v9)   row 3: (v6, v8, 0)
+__device__ __forceinline__ void wave_sum10(const float v[10], float k[3]) {
+  float h[6];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    // lanes 0-31 end up with v[i] folded over lanes +32, lanes 32-63 with v[i+5]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 5]), false, false);
+    h[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  h[5] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    // rows 0 and 2 take h[2i] folded over rows +1, rows 1 and 3 take h[2i+1]
+    const auto r =
+        __builtin_amdgcn_permlane16_swap(__float_as_uint(h[2 * i]), __float_as_uint(h[2 * i + 1]), false, false);
+    k[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k[i] += dpp_mov<0x111>(k[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k[i] += dpp_mov<0x112>(k[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k[i] += dpp_mov<0x114>(k[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k[i] += dpp_mov<0x118>(k[i]);
+}
+
 __device__ __forceinline__ double wave_sum_to_lane63_d(double x) {
   // exact-order-independent enough for FP64 partials: butterfly via shuffles
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);

@@ -61,29 +61,30 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
       s_c[threadIdx.x] = rec[3 * r + 2];
     }
     __syncthreads();
-    if (!done) {
+    if (__any(!done)) {  // uniform over the wave
       const int n = (int)min((uint32_t)BATCH, e - base);
+      const uint32_t idx0 = base - b + 1;
+      // branch-free per entry: every lane evaluates, the predicates select
       for (int j = 0; j < n; ++j) {
         const float4 A = s_a[j];
         const float4 B = s_b[j];
-        const float p = gs_power(B.x, B.y, B.z, A.x - fx, A.y - fy);
-        if (p > 0.f) continue;
-        const float alpha = fminf(GS_ALPHA_MAX, A.w * __expf(p));
-        if (alpha < GS_ALPHA_MIN) continue;
-        const float Tn = T * (1.0f - alpha);
-        if (Tn < GS_T_MIN) {
-          done = true;
-          break;
-        }
         const float4 Cc = s_c[j];
-        const float wgt = alpha * T;
+        const float p = gs_power(B.x, B.y, B.z, A.x - fx, A.y - fy);
+        const float alpha = fminf(GS_ALPHA_MAX, A.w * __expf(p));
+        const bool ok = !done && p <= 0.f && alpha >= GS_ALPHA_MIN;
+        const float Tn = T * (1.0f - alpha);
+        const bool stop = ok && Tn < GS_T_MIN;
+        const bool add = ok && !stop;
+        done = done || stop;
+        const float wgt = add ? alpha * T : 0.f;
         C0 += wgt * Cc.x;
         C1 += wgt * Cc.y;
         C2 += wgt * Cc.z;
         D += wgt * A.z;
         Mm += wgt * B.w;
-        T = Tn;
-        last = base - b + j + 1;
+        T = add ? Tn : T;
+        last = add ? idx0 + j : last;
+        if (__all(done)) break;
       }
     }
   }
@@ -107,6 +108,14 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
 
 // Backward over one tile. g2d is planar [10][nrec]:
 // (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth).
+//
+// Per entry every lane forms ten moment terms of its pixel, with
+// h = dL/d(alpha) * exp(power) where alpha is unclamped, else 0:
+//   h*dx, h*dy, h*dx^2, h*dx*dy, h*dy^2, h, w*gC (3), w*gD   (w = alpha*T)
+// A transposed wave reduction sums them; the cross-wave pass turns the sums
+// into the 2D gradients with the entry's opacity and conic
+// (d/du = -o * conic * (sum h*d), d/dconic = -o/2 * (sum h*d d^T) off-diagonal
+// counted twice), so the per-pixel work carries no conic products.
 template <int BATCH>
 __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
@@ -115,7 +124,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
     float* __restrict__ g2d, uint8_t* __restrict__ touched) {
   __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
-  __shared__ float s_red[BATCH][4][10];
+  __shared__ float4 s_red[BATCH][4][4];  // [entry][wave][row]: the three row totals of wave_sum10
   __shared__ uint32_t s_r[BATCH];
   __shared__ uint32_t s_max;
   if (*overflow) return;
@@ -141,8 +150,12 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     gm = dM ? dM[tc.pix] : 0.f;
     const float gt = dT ? dT[tc.pix] : 0.f;
     Tbar = gt + gc0 * bg0 + gc1 * bg1 + gc2 * bg2;
-    atomicMax(&s_max, nl);
   }
+  // longest list prefix any pixel of this wave composited
+  uint32_t wmax = nl;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, o, 64));
+  if (lane == 0) atomicMax(&s_max, wmax);
   __syncthreads();
   const uint32_t maxl = s_max;
   for (int hi = (int)maxl; hi > 0; hi -= BATCH) {
@@ -159,62 +172,74 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     __syncthreads();
     for (int jj = n - 1; jj >= 0; --jj) {
       const int j = lo + jj;
-      float g[10];
-#pragma unroll
-      for (int c = 0; c < 10; ++c) g[c] = 0.f;
-      bool contrib = false;
-      if ((uint32_t)j < nl) {
+      float k[3] = {0.f, 0.f, 0.f};
+      if ((uint32_t)j < wmax) {  // uniform over the wave
         const float4 A = s_a[jj];
         const float4 B = s_b[jj];
+        const float4 Cc = s_c[jj];
         const float dx = A.x - fx, dy = A.y - fy;
         const float p = gs_power(B.x, B.y, B.z, dx, dy);
-        if (p <= 0.f) {
-          const float G = __expf(p);
-          const float araw = A.w * G;
-          const float alpha = fminf(GS_ALPHA_MAX, araw);
-          if (alpha >= GS_ALPHA_MIN) {
-            contrib = true;
-            const float4 Cc = s_c[jj];
-            const float one_m = 1.0f - alpha;
-            const float Tj = T / one_m;
-            const float vdot = gc0 * Cc.x + gc1 * Cc.y + gc2 * Cc.z + gd * A.z + gm * B.w;
-            const float abar = Tj * (vdot - Tbar);
-            const float wgt = alpha * Tj;
-            g[6] = wgt * gc0;
-            g[7] = wgt * gc1;
-            g[8] = wgt * gc2;
-            g[9] = wgt * gd;
-            Tbar = vdot * alpha + Tbar * one_m;
-            T = Tj;
-            if (araw < GS_ALPHA_MAX) {
-              const float pbar = abar * alpha;
-              g[0] = pbar * (-B.x * dx - B.y * dy);
-              g[1] = pbar * (-B.z * dy - B.y * dx);
-              g[2] = -0.5f * pbar * dx * dx;
-              g[3] = -pbar * dx * dy;
-              g[4] = -0.5f * pbar * dy * dy;
-              g[5] = abar * G;
-            }
-          }
+        const float G = __expf(p);
+        const float araw = A.w * G;
+        const float alpha = fminf(GS_ALPHA_MAX, araw);
+        const bool valid = (uint32_t)j < nl && p <= 0.f && alpha >= GS_ALPHA_MIN;
+        if (__ballot(valid)) {  // uniform
+          const float a = valid ? alpha : 0.f;
+          const float one_m = 1.0f - a;
+          const float Tj = T * __builtin_amdgcn_rcpf(one_m);
+          const float vdot = gc0 * Cc.x + gc1 * Cc.y + gc2 * Cc.z + gd * A.z + gm * B.w;
+          const float abar = Tj * (vdot - Tbar);
+          const float wgt = a * Tj;
+          const float h = (valid && araw < GS_ALPHA_MAX) ? abar * G : 0.f;
+          Tbar = vdot * a + Tbar * one_m;
+          T = Tj;
+          float v[10];
+          v[0] = h * dx;
+          v[1] = h * dy;
+          v[2] = v[0] * dx;
+          v[3] = v[0] * dy;
+          v[4] = v[1] * dy;
+          v[5] = h;
+          v[6] = wgt * gc0;
+          v[7] = wgt * gc1;
+          v[8] = wgt * gc2;
+          v[9] = wgt * gd;
+          wave_sum10(v, k);
         }
       }
-      const uint64_t any = __ballot(contrib);
-      if (any) {
-#pragma unroll
-        for (int c = 0; c < 10; ++c) g[c] = wave_sum_to_lane63(g[c]);
-      }
-      if (lane == 63) {
-#pragma unroll
-        for (int c = 0; c < 10; ++c) s_red[jj][w][c] = any ? g[c] : 0.f;
-      }
+      if ((lane & 15) == 15) s_red[jj][w][lane >> 4] = make_float4(k[0], k[1], k[2], 0.f);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < n * 10; q += GS_BLOCK) {
       const int jj = q / 10, c = q - jj * 10;
-      const float s = s_red[jj][0][c] + s_red[jj][1][c] + s_red[jj][2][c] + s_red[jj][3][c];
-      if (s != 0.f) {
+      // moment index -> (row, slot) of wave_sum10's output
+      auto mom = [&](int m) {
+        const int row = m < 5 ? (m & 1) : 2 + ((m - 5) & 1);
+        const int sl = m < 5 ? (m >> 1) : ((m - 5) >> 1);
+        float acc = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+          const float4 x = s_red[jj][ww][row];
+          acc += sl == 0 ? x.x : (sl == 1 ? x.y : x.z);
+        }
+        return acc;
+      };
+      const float o = s_a[jj].w;
+      float gval;
+      if (c < 2) {
+        const float4 B = s_b[jj];
+        const float s0 = mom(0), s1 = mom(1);
+        gval = c == 0 ? -o * (B.x * s0 + B.y * s1) : -o * (B.y * s0 + B.z * s1);
+      } else if (c == 2 || c == 4) {
+        gval = -0.5f * o * mom(c);
+      } else if (c == 3) {
+        gval = -o * mom(3);
+      } else {
+        gval = mom(c);
+      }
+      if (gval != 0.f) {
         const uint32_t r = s_r[jj];
-        atomicAdd(&g2d[(int64_t)c * M + r], s);
+        atomicAdd(&g2d[(int64_t)c * M + r], gval);
         touched[r] = 1;
       }
     }
