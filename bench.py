@@ -109,7 +109,7 @@ def main():
     views = gs.ViewBatch([cam], a.n)
     gt = gs.to_device(g)
     gst = gs.gaussians_struct(gt)
-    R = a.max_rank if a.max_rank >= 0 else 4096
+    R = a.max_rank if a.max_rank >= 0 else 256
     while True:
         probe = gs.Pipeline(ctx, views, capacity=a.n * 64, max_rank=R)
         probe.forward(gst)

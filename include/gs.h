@@ -134,7 +134,9 @@ typedef struct gs_bins {
                              least max_rank records in front of it. Every tile list
                              is then an exact prefix of its full list; tiles that
                              run out of it with unsaturated pixels raise
-                             `incomplete`. <= 0: full lists. */
+                             `incomplete`. A view with more selected records than
+                             gs_ctx_get_param("prefix_cap") gets empty lists and
+                             raises `incomplete` at once. <= 0: full lists. */
 } gs_bins;
 
 /* Rendered maps (planar, see layouts). */
@@ -190,6 +192,9 @@ const char* gs_last_error(const gs_ctx* ctx);
  * (256|512|1024|2048 records per binning workgroup), and "timing" (0|1, see
  * gs_ctx_kernel_times). Values outside the supported set return GS_E_ARG. */
 gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
+/* Read-only names besides the above: "lds_limit" (LDS bytes per workgroup the
+ * context uses), "prefix_cap" (selected records per view the prefix binning
+ * path takes). */
 gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value /*[host]*/);
 /* Measurement aid. With "timing" = 1 every kernel launch is bracketed by HIP
  * events on its stream (do not capture such launches in a graph). This call

@@ -123,6 +123,7 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   else if (!strcmp(name, "bin_chunk")) *value = ctx->bin_chunk;
   else if (!strcmp(name, "timing")) *value = ctx->timing;
   else if (!strcmp(name, "lds_limit")) *value = (int64_t)ctx->lds_limit;
+  else if (!strcmp(name, "prefix_cap")) *value = bin_prefix_cap();
   else return GS_E_ARG;
   return GS_OK;
 }

@@ -185,6 +185,7 @@ int loss_blocks(const ViewTab&);
 gs_status launch_loss(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_loss_params*, float*,
                       gs_pixel_grads*, double*, hipStream_t);
 size_t bin_prefix_ws_bytes(gs_ctx*, const ViewTab&, int64_t capacity);
+int64_t bin_prefix_cap();
 gs_status launch_bin_prefix(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, const gs_proj*,
                             gs_bins*, char*, hipStream_t);
 size_t mp_ws_bytes(const ViewTab&, int64_t npix);

@@ -99,10 +99,12 @@ def _prefix_selection(key, R):
 
 
 @pytest.mark.parametrize("seed,m,W,H,R", [(11, 3000, 64, 48, 500), (12, 70000, 640, 480, 4096),
-                                          (13, 20000, 320, 240, 100000), (14, 50000, 1280, 720, 2000)])
+                                          (13, 12000, 320, 240, 100000), (14, 50000, 1280, 720, 2000),
+                                          (15, 20000, 320, 240, 100000), (16, 200000, 640, 480, 6000)])
 def test_bin_sort_prefix_bitexact(ctx, orc, seed, m, W, H, R):
     """Prefix path: the lists equal the textbook stable sort restricted to the
-    selected records, bit for bit."""
+    selected records, bit for bit; a selection above the path's cap gives
+    empty lists and raises `incomplete`."""
     rect, key = synth.bin_inputs(seed, m, W, H, max_tiles=6)
     # spread depth keys over a realistic range so the selection is partial
     rng = np.random.default_rng(seed)
@@ -126,9 +128,13 @@ def test_bin_sort_prefix_bitexact(ctx, orc, seed, m, W, H, R):
         if rep == 1:
             pipe.key_hist.copy_(torch.from_numpy(hist.astype(np.int32)))
         gs.gs_bin_sort(ctx, views.s, gst, pipe.proj, pipe.bins, pipe.ws_bin)
-        over, n_inst, _ = pipe.check()
+        over, n_inst, inc = pipe.check()
         assert not over
         assert int(pipe.key_hist.abs().sum()) == 0
+        if sel.sum() > ctx.get_param("prefix_cap"):
+            assert inc == 1 and n_inst == 0
+            continue
+        assert inc == 0
         ids_ref, ranges = orc.bin_reference(rect, np.where(sel, key, 0xFFFFFFFF), ((W + 15) // 16, (H + 15) // 16))
         assert n_inst == ids_ref.size
         ts = torch_np(pipe.tile_start).view(np.uint32).astype(np.int64)
