@@ -47,9 +47,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--max-rank", type=int, default=-1,
-                    help="prefix rank for binning (-1: smallest power of two >= 4096 that is exact; 0: full lists)")
+                    help="prefix rank for binning (-1: smallest power of two >= 256 that is exact; 0: full lists)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many eager steps (for rocprofv3) and exit")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="with --profile-steps: first copy this many bytes device to device once (a plain copy "
+                         "kernel of known size that calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -132,6 +135,14 @@ def main():
         pipe.backward(gst, grs)
 
     if a.profile_steps > 0:
+        if a.copy_bytes > 0:
+            src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+            log(f"[bench] calibration copy of {a.copy_bytes} bytes done")
         for _ in range(a.profile_steps):
             step()
         torch.cuda.synchronize()

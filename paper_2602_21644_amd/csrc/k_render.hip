@@ -54,18 +54,29 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
       exhausted = false;
       break;
     }
-    if (threadIdx.x < BATCH && base + threadIdx.x < e) {
-      const int64_t r = roff + ids[base + threadIdx.x];
-      s_a[threadIdx.x] = rec[3 * r + 0];
-      s_b[threadIdx.x] = rec[3 * r + 1];
-      s_c[threadIdx.x] = rec[3 * r + 2];
+    if (threadIdx.x < BATCH) {
+      if (base + threadIdx.x < e) {
+        const int64_t r = roff + ids[base + threadIdx.x];
+        s_a[threadIdx.x] = rec[3 * r + 0];
+        s_b[threadIdx.x] = rec[3 * r + 1];
+        s_c[threadIdx.x] = rec[3 * r + 2];
+      } else {
+        // padding: zero opacity never composites
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_a[threadIdx.x] = z;
+        s_b[threadIdx.x] = z;
+        s_c[threadIdx.x] = z;
+      }
     }
     __syncthreads();
     if (__any(!done)) {  // uniform over the wave
       const int n = (int)min((uint32_t)BATCH, e - base);
       const uint32_t idx0 = base - b + 1;
-      // branch-free per entry: every lane evaluates, the predicates select
-      for (int j = 0; j < n; ++j) {
+      // branch-free per entry: every lane evaluates, the predicates select;
+      // groups of four, the early exit tested once per group
+      for (int j0 = 0; j0 < n; j0 += 4) {
+#pragma unroll
+      for (int j = j0; j < j0 + 4; ++j) {
         const float4 A = s_a[j];
         const float4 B = s_b[j];
         const float4 Cc = s_c[j];
@@ -84,7 +95,8 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
         Mm += wgt * B.w;
         T = add ? Tn : T;
         last = add ? idx0 + j : last;
-        if (__all(done)) break;
+      }
+      if (__all(done)) break;
       }
     }
   }
@@ -106,6 +118,16 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
   (void)trunc;
 }
 
+// Backward over one tile. g2d is planar [10][nrec]:
+// (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth).
+//
+// Per entry every lane forms ten moment terms of its pixel, with
+// h = dL/d(alpha) * exp(power) where alpha is unclamped, else 0:
+//   h*dx, h*dy, h*dx^2, h*dx*dy, h*dy^2, h, w*gC (3), w*gD   (w = alpha*T)
+// A transposed wave reduction sums them; the cross-wave pass turns the sums
+// into the 2D gradients with the entry's opacity and conic
+// (d/du = -o * conic * (sum h*d), d/dconic = -o/2 * (sum h*d d^T) off-diagonal
+// counted twice), so the per-pixel work carries no conic products.
 // Backward over one tile. g2d is planar [10][nrec]:
 // (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth).
 //
