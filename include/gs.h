@@ -337,6 +337,41 @@ gs_status gs_mlp_train_step(gs_ctx* ctx, gs_mlp* mlp, const float* x, const floa
                             float lr, int32_t step, float* loss, float* grad, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* ---------------------------------------------------------------- optimisation steps
+ * The joint optimisation of Gaussian parameters and camera poses (Sec. IV-D)
+ * as first-order steps on the gradients of gs_render_bwd. (The paper refines
+ * poses with Levenberg-Marquardt; this library takes Adam steps on the pose
+ * twist and retracts them onto SE(3).) */
+typedef struct gs_adam_group {
+  float* param;       /* [n] updated in place */
+  const float* grad;  /* [n] */
+  float* m;           /* [n] first moment, zero before the first step */
+  float* v;           /* [n] second moment, zero before the first step */
+  int64_t n;
+  float lr;
+} gs_adam_group;
+typedef struct gs_adam_params {
+  float beta1, beta2, eps;
+  int32_t step;            /* 1-based step count of the bias correction */
+  const int32_t* step_dev; /* nullable, device: when set the step count is read
+                              from here at run time (a captured graph replays
+                              with the caller advancing it); `step` is ignored */
+} gs_adam_params;
+#define GS_ADAM_MAX_GROUPS 8
+/* Adam (Kingma and Ba 2015) on up to GS_ADAM_MAX_GROUPS device arrays in one
+ * launch: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * groups [host]; GS_E_ARG for NULL arrays, n < 0, step < 1 (without step_dev)
+ * or too many groups. A device step count below 1 is taken as 1. */
+gs_status gs_adam_step(gs_ctx* ctx, const gs_adam_group* groups, int32_t n_groups, const gs_adam_params* params,
+                       void* stream);
+/* Left retraction of the pose twist on every view: T_cw[v] <- Exp(delta_v) T_cw[v]
+ * with delta_v = (rho, phi) = delta[6v .. 6v + 6) (device), the SE(3)
+ * exponential in closed form (Rodrigues, with series near phi = 0), the
+ * rotation re-orthonormalised; delta is zeroed afterwards. `cams` is the
+ * device camera table of the views (gs_views.cams_dev), updated in place. */
+gs_status gs_pose_update(gs_ctx* ctx, int32_t n_views, gs_camera* cams, float* delta, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

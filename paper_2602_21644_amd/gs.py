@@ -103,6 +103,15 @@ class MPOut(ctypes.Structure):
     _fields_ = [(k, c_void_p) for k in ("U_tilde", "alpha", "dynamic", "prune", "M_p", "e", "stats")]
 
 
+class AdamGroup(ctypes.Structure):
+    _fields_ = [("param", c_void_p), ("grad", c_void_p), ("m", c_void_p), ("v", c_void_p), ("n", c_int64),
+                ("lr", c_float)]
+
+
+class AdamParams(ctypes.Structure):
+    _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("step", c_int32), ("step_dev", c_void_p)]
+
+
 class MLP(ctypes.Structure):
     _fields_ = [(k, c_void_p) for k in ("master", "w_bf16", "adam_m", "adam_v")]
 
@@ -149,6 +158,8 @@ def lib():
                                 c_int32),
             "gs_mlp_sync": ([P, POINTER(MLP), P], c_int32),
             "gs_mlp_fwd": ([P, POINTER(MLP), P, P, c_int64, P], c_int32),
+            "gs_adam_step": ([P, POINTER(AdamGroup), c_int32, POINTER(AdamParams), P], c_int32),
+            "gs_pose_update": ([P, c_int32, P, P, P], c_int32),
             "gs_mlp_train_step": ([P, POINTER(MLP), P, P, c_int64, c_float, c_int32, P, P, P, c_size_t, P],
                                   c_int32),
         }
@@ -163,7 +174,8 @@ def lib():
 EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error", "gs_ctx_set_param",
             "gs_ctx_get_param", "gs_ctx_kernel_times", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_bwd",
-            "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step")
+            "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
+            "gs_adam_step", "gs_pose_update")
 
 
 def ptr(t):
@@ -281,6 +293,28 @@ def gs_mlp_fwd(ctx, mlp, x, y, P, stream=None):
     ctx.check(lib().gs_mlp_fwd(ctx.h, ctypes.byref(mlp), ptr(x), ptr(y), int(P), _stream(stream)), "gs_mlp_fwd")
 
 
+ADAM_MAX_GROUPS = 8
+
+
+def gs_adam_step(ctx, groups, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """groups: list of (param, grad, m, v, lr) float32 device tensors of equal
+    size; step: the 1-based step count, or an int32 device tensor holding it."""
+    arr = (AdamGroup * len(groups))()
+    for i, (p_, g_, m_, v_, lr) in enumerate(groups):
+        arr[i] = AdamGroup(ptr(p_), ptr(g_), ptr(m_), ptr(v_), p_.numel(), float(lr))
+    if isinstance(step, torch.Tensor):
+        prm = AdamParams(beta1, beta2, eps, 0, ptr(step))
+    else:
+        prm = AdamParams(beta1, beta2, eps, int(step), None)
+    ctx.check(lib().gs_adam_step(ctx.h, arr, len(groups), ctypes.byref(prm), _stream(stream)), "gs_adam_step")
+
+
+def gs_pose_update(ctx, views, delta, stream=None):
+    """T_cw[v] <- Exp(delta[v]) T_cw[v] in the views' device camera table; delta [V*6] is zeroed."""
+    ctx.check(lib().gs_pose_update(ctx.h, views.V, c_void_p(views.cams_dev.data_ptr()), ptr(delta),
+                                   _stream(stream)), "gs_pose_update")
+
+
 def gs_mlp_train_step(ctx, mlp, x, label, P, lr, step, loss, grad, ws, stream=None):
     ctx.check(lib().gs_mlp_train_step(ctx.h, ctypes.byref(mlp), ptr(x), ptr(label), int(P), float(lr), int(step),
                                       ptr(loss), ptr(grad), ptr(ws), ws.numel() * ws.element_size(),
@@ -333,6 +367,11 @@ class ViewBatch:
         off = ctypes.sizeof(Camera) * v + Camera.T_cw.offset
         self.cams_dev[off:off + 48].copy_(T.view(torch.uint8).to(self.cams_dev.device), non_blocking=False)
         self._host[v].T_cw[:] = [float(x) for x in T.tolist()]
+
+    def pose(self, v):
+        """View v's T_cw [3, 4] as stored in the device camera table (synchronises)."""
+        off = ctypes.sizeof(Camera) * v + Camera.T_cw.offset
+        return self.cams_dev[off:off + 48].view(torch.float32).reshape(3, 4).cpu().numpy().astype(np.float64)
 
     def set_pose_tensor(self, v, T_dev):
         """Copy a float32 [12] device tensor into view v's pose (graph-capturable)."""

@@ -1,0 +1,229 @@
+"""Optimisation around the library calls: the joint optimisation of Gaussian
+parameters and camera poses (Sec. IV-D). Every kernel runs in libgs.so; torch
+holds the buffers and the stream.
+
+RenderLoss     torch.autograd.Function: forward = gs_project, gs_bin_sort,
+               gs_render_fwd and gs_loss (one loss per view); backward =
+               gs_render_bwd (the Gaussian parameter gradients, and the
+               gradient of the left pose twist of every view at its current
+               pose).
+Adam           device state of a list of tensors, stepped by gs_adam_step.
+track          pose-only tracking of one frame: Adam steps on the left twist,
+               each retracted onto SE(3) by gs_pose_update; the iteration is
+               captured once in a HIP graph and replayed.
+map_gaussians  Adam steps on the Gaussian parameters against a batch of views.
+
+(The paper refines poses with Levenberg-Marquardt; these loops take
+first-order steps on the same gradients.)
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import gs
+
+PARAMS = ("mean", "log_scale", "quat", "opacity_logit", "color")
+
+
+def _scale_pixel_grads(pipe, views, w):
+    """Multiplies view v's pixel adjoints by w[v] (the incoming gradient of
+    its loss)."""
+    sizes = [c["width"] * c["height"] for c in views.cams]
+    s = torch.repeat_interleave(w.to(torch.float32), torch.tensor(sizes, device=w.device))
+    P = pipe.P
+    pipe.dC.view(3, P).mul_(s)
+    pipe.dD.mul_(s)
+    pipe.dM.mul_(s)
+    pipe.dT.mul_(s)
+
+
+class RenderLoss(torch.autograd.Function):
+    """loss[V] = RenderLoss.apply(pipe, mp, target_color, target_depth,
+    mean, log_scale, quat, opacity_logit, color, pose)
+
+    `pipe` is a gs.Pipeline over the views; `pose` a [V, 6] zero tensor that
+    stands for the left twist (rho, phi) of every view at its current pose
+    (its gradient is the pose gradient). MP is a state, not a parameter: it
+    gets no gradient."""
+
+    @staticmethod
+    def forward(ctx, pipe, mp, target_color, target_depth, mean, log_scale, quat, opacity_logit, color, pose):
+        g = dict(mean=mean.contiguous(), log_scale=log_scale.contiguous(), quat=quat.contiguous(),
+                 opacity_logit=opacity_logit.contiguous(), color=color.contiguous(), mp=mp.contiguous())
+        gst = gs.gaussians_struct(g)
+        pipe.forward(gst)
+        pipe.loss_and_grads(target_color.contiguous(), target_depth.contiguous())
+        ctx.pipe, ctx.gst, ctx.keep = pipe, gst, g
+        ctx.n = int(opacity_logit.shape[0])
+        return pipe.loss.clone()
+
+    @staticmethod
+    def backward(ctx, gloss):
+        pipe = ctx.pipe
+        if not bool(torch.all(gloss == 1.0)):
+            _scale_pixel_grads(pipe, pipe.views, gloss)
+        grads = gs.alloc_grads(ctx.n)
+        pose = torch.zeros(6 * pipe.views.V, dtype=torch.float32, device=gloss.device)
+        pipe.backward(ctx.gst, gs.grads_struct(grads, pose))
+        return (None, None, None, None, grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"],
+                grads["color"], pose.view(-1, 6))
+
+
+class Adam:
+    """Adam state (first and second moments, device step count) for a list of
+    (tensor, lr); step() applies gs_adam_step with the given gradients."""
+
+    def __init__(self, ctx, params, betas=(0.9, 0.999), eps=1e-8):
+        self.ctx = ctx
+        self.params = [(p, float(lr)) for p, lr in params]
+        self.m = [torch.zeros_like(p) for p, _ in self.params]
+        self.v = [torch.zeros_like(p) for p, _ in self.params]
+        dev = self.params[0][0].device
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.betas, self.eps = betas, eps
+
+    def reset(self):
+        for t in self.m + self.v:
+            t.zero_()
+        self.count.zero_()
+
+    def step(self, grads, stream=None):
+        """Graph-capturable: the step count advances on the device."""
+        self.count.add_(1)
+        groups = [(p, g, m, v, lr) for (p, lr), g, m, v in zip(self.params, grads, self.m, self.v)]
+        for i in range(0, len(groups), gs.ADAM_MAX_GROUPS):
+            gs.gs_adam_step(self.ctx, groups[i:i + gs.ADAM_MAX_GROUPS], self.count, self.betas[0], self.betas[1],
+                            self.eps, stream)
+
+
+def choose_rank(ctx, views, gst, n, start=256):
+    """Smallest power-of-two prefix rank (from `start`) whose prefix lists let
+    every tile of the views saturate at their current poses, with the instance
+    count it gives; (0, count) when none does (full lists)."""
+    R = start
+    while True:
+        probe = gs.Pipeline(ctx, views, capacity=max(1 << 20, 64 * n), max_rank=R)
+        probe.forward(gst)
+        over, n_inst, inc = probe.check()
+        del probe
+        if over:
+            raise RuntimeError("binning capacity exceeded while choosing the prefix rank")
+        if inc == 0 or R == 0:
+            return R, n_inst
+        R = R * 2 if R * 2 <= ctx.get_param("prefix_cap") else 0
+
+
+class Tracker:
+    """Pose-only tracking of one view against an observed frame.
+
+    Every iteration renders at the current pose, takes the MP-weighted loss
+    and its pose gradient (gs_render_bwd in pose-only mode), one Adam step on
+    the left twist and the retraction T <- Exp(delta) T (gs_pose_update), all
+    on the device. The iteration is captured once as a HIP graph."""
+
+    def __init__(self, ctx, gaussians, cam, lr_rho=2e-3, lr_phi=2e-3, max_rank=-1, capacity=None, use_graph=True,
+                 slack=4.0):
+        self.ctx = ctx
+        self.g = gaussians
+        self.gst = gs.gaussians_struct(gaussians)
+        n = int(gaussians["opacity_logit"].shape[0])
+        self.views = gs.ViewBatch([cam], n)
+        if max_rank < 0:
+            R, n_inst = choose_rank(ctx, self.views, self.gst, n)
+            # the pose moves during tracking: keep margin on the rank
+            R = min(R * 2, ctx.get_param("prefix_cap")) if R else 0
+        else:
+            R, n_inst = max_rank, 64 * n
+        self.rank = R
+        cap = capacity or int(slack * max(n_inst, 1)) + (1 << 16)
+        self.pipe = gs.Pipeline(ctx, self.views, cap, max_rank=R)
+        dev = gaussians["mean"].device
+        self.delta = torch.zeros(6, dtype=torch.float32, device=dev)
+        self.dpose = torch.zeros(6, dtype=torch.float32, device=dev)
+        self.adam = Adam(ctx, [(self.delta[:3], lr_rho), (self.delta[3:], lr_phi)])
+        self.grs = gs.grads_struct(None, self.dpose, pose_only=True)
+        self.flags = torch.zeros(2, dtype=torch.int64, device=dev)  # sticky overflow, incomplete
+        self.use_graph = use_graph
+        self.graph = None
+        self.tc = self.td = None
+
+    def _iteration(self):
+        p = self.pipe
+        p.forward(self.gst)
+        p.loss_and_grads(self.tc, self.td)
+        torch.maximum(self.flags, p.counters[1:3], out=self.flags)
+        p.backward(self.gst, self.grs)
+        self.adam.step([self.dpose[:3], self.dpose[3:]])
+        gs.gs_pose_update(self.ctx, self.views, self.delta)
+
+    def run(self, target_color, target_depth, iters=100, T_init=None):
+        """Tracks from T_init (default: the current pose) for `iters`
+        iterations; returns (T_cw [3, 4], final loss, exact) where `exact` is
+        False when some iteration overflowed or ran out of its prefix lists."""
+        if self.tc is None:
+            self.tc = torch.empty_like(target_color)
+            self.td = torch.empty_like(target_depth)
+        self.tc.copy_(target_color)
+        self.td.copy_(target_depth)
+        if T_init is not None:
+            self.views.set_pose(0, T_init)
+        self.adam.reset()
+        self.delta.zero_()
+        self.flags.zero_()
+        if self.use_graph and self.graph is None:
+            # one eager iteration first (loads every kernel), then restore the
+            # start and capture
+            T0 = self.views.pose(0)
+            self._iteration()
+            torch.cuda.synchronize()
+            self.views.set_pose(0, T0)
+            self.adam.reset()
+            self.delta.zero_()
+            self.flags.zero_()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph, stream=s):
+                self._iteration()
+            torch.cuda.synchronize()
+        for _ in range(iters):
+            if self.graph is not None:
+                self.graph.replay()
+            else:
+                self._iteration()
+        # loss at the final pose
+        self.pipe.forward(self.gst)
+        self.pipe.loss_and_grads(self.tc, self.td)
+        torch.maximum(self.flags, self.pipe.counters[1:3], out=self.flags)
+        torch.cuda.synchronize()
+        exact = int(self.flags.sum()) == 0
+        return self.views.pose(0), float(self.pipe.loss[0]), exact
+
+
+def map_gaussians(ctx, gaussians, cams, target_color, target_depth, iters=50, lrs=None, max_rank=0,
+                  view_scene=None, scene_begin=None):
+    """Adam steps on the Gaussian parameters (in place) against a batch of
+    views at fixed poses; returns the per-iteration total loss (host)."""
+    lrs = lrs or dict(mean=1e-4, log_scale=5e-3, quat=1e-3, opacity_logit=2e-2, color=5e-3)
+    n = int(gaussians["opacity_logit"].shape[0])
+    views = gs.ViewBatch(cams, n, view_scene=view_scene, scene_begin=scene_begin)
+    gst = gs.gaussians_struct(gaussians)
+    pipe = gs.Pipeline(ctx, views, capacity=max(1 << 20, 64 * n * len(cams)), max_rank=max_rank)
+    grads = gs.alloc_grads(n)
+    pose = torch.zeros(6 * len(cams), dtype=torch.float32, device=gaussians["mean"].device)
+    grs = gs.grads_struct(grads, pose)
+    adam = Adam(ctx, [(gaussians[k], lrs[k]) for k in PARAMS])
+    losses = torch.zeros(iters, dtype=torch.float32, device=gaussians["mean"].device)
+    for it in range(iters):
+        pipe.forward(gst)
+        pipe.loss_and_grads(target_color, target_depth)
+        losses[it] = pipe.loss.sum()
+        pipe.backward(gst, grs)
+        adam.step([grads[k] for k in PARAMS])
+    over, _, _ = pipe.check()
+    if over:
+        raise RuntimeError("binning capacity exceeded during mapping")
+    return losses.cpu().numpy().astype(np.float64)

@@ -1,0 +1,170 @@
+"""GPU tests of the optimiser steps (against the FP64 oracle) and of the
+autograd function, tracking and mapping loops built on the library."""
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+from oracle import optim as oopt
+from paper_2602_21644_amd import gs, optim, synth
+from tests.gpu_util import torch_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return gs.Context(0)
+
+
+def test_adam_step_parity(ctx):
+    """Groups of ragged sizes (one misaligned), host and device step counts."""
+    rng = np.random.default_rng(0)
+    base = torch.from_numpy(rng.normal(size=5003).astype(np.float32)).cuda()
+    sizes = [(0, 4096), (4097, 4103), (4103, 5003)]  # [4097, 4103) starts off a 16-byte boundary
+    params = [base[a:b] for a, b in sizes]
+    ms = [torch.zeros_like(p) for p in params]
+    vs = [torch.zeros_like(p) for p in params]
+    lrs = [1e-3, 0.5, 2e-2]
+    ref = [(torch_np(p).astype(np.float64), np.zeros(p.numel()), np.zeros(p.numel())) for p in params]
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for k in range(1, 6):
+        grads = [torch.from_numpy((rng.normal(size=p.numel()) * 10.0 ** rng.integers(-4, 2)).astype(np.float32)).cuda()
+                 for p in params]
+        if k <= 3:
+            gs.gs_adam_step(ctx, list(zip(params, grads, ms, vs, lrs)), k)
+        else:
+            step_dev.fill_(k)
+            gs.gs_adam_step(ctx, list(zip(params, grads, ms, vs, lrs)), step_dev)
+        ref = [oopt.adam_step(p, torch_np(g), m, v, lr, k) for (p, m, v), g, lr in zip(ref, grads, lrs)]
+    torch.cuda.synchronize()
+    for p, m, v, (rp, rm, rv) in zip(params, ms, vs, ref):
+        np.testing.assert_allclose(torch_np(m), rm, rtol=2e-5, atol=1e-9)
+        np.testing.assert_allclose(torch_np(v), rv, rtol=2e-5, atol=1e-12)
+        np.testing.assert_allclose(torch_np(p), rp, rtol=1e-5, atol=1e-6)
+    assert float(base[4096]) == float(torch.from_numpy(np.random.default_rng(0).normal(size=5003).astype(np.float32))[4096])
+
+
+def test_pose_update_parity(ctx):
+    """Exp(delta) T for twists from zero to one radian; delta is cleared."""
+    rng = np.random.default_rng(1)
+    scales = [0.0, 1e-7, 1e-4, 3e-3, 0.05, 1.0]
+    cams, Ts = [], []
+    for _ in scales:
+        R = Rotation.from_rotvec(rng.normal(size=3)).as_matrix()
+        T = np.concatenate([R, rng.normal(size=(3, 1))], axis=1).astype(np.float32)
+        cams.append(synth.camera(64, 48, T))
+        Ts.append(T.astype(np.float64))
+    views = gs.ViewBatch(cams, 10)
+    xi = np.concatenate([rng.normal(size=6) * s for s in scales]).astype(np.float32)
+    delta = torch.from_numpy(xi).cuda()
+    gs.gs_pose_update(ctx, views, delta)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(delta) == 0
+    for v, T in enumerate(Ts):
+        ref = oopt.pose_update(T, xi[6 * v:6 * v + 6].astype(np.float64))
+        got = views.pose(v)
+        np.testing.assert_allclose(got, ref, atol=3e-6)
+        np.testing.assert_allclose(got[:, :3] @ got[:, :3].T, np.eye(3), atol=3e-7)
+
+
+def _scene(seed=5, n=20000, W=160, H=120):
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(seed, n, W, H, n_boxes=0)
+    return g, cam, tcam
+
+
+def _render_target(ctx, g_dev, cam):
+    views = gs.ViewBatch([cam], int(g_dev["opacity_logit"].shape[0]))
+    pipe = gs.Pipeline(ctx, views, capacity=1 << 22)
+    pipe.forward(gs.gaussians_struct(g_dev))
+    over, _, _ = pipe.check()
+    assert not over
+    A = 1.0 - pipe.img_T
+    return pipe.img_color.clone(), torch.where(A >= 0.5, pipe.img_depth, torch.zeros_like(A)).contiguous()
+
+
+def test_render_loss_autograd(ctx):
+    """RenderLoss returns the per-view losses; its backward gives the library's
+    gradients, weighted by the incoming per-view gradient."""
+    g, cam, tcam = _scene()
+    gd = gs.to_device(g)
+    targets = [_render_target(ctx, gd, c) for c in (tcam, cam)]
+    cams = [cam, tcam]
+    views = gs.ViewBatch(cams, synth.n_gaussians(g))
+    pipe = gs.Pipeline(ctx, views, capacity=1 << 22)
+    tcol = torch.cat([t[0].view(3, -1) for t in targets], dim=1).reshape(-1).contiguous()
+    tdep = torch.cat([t[1] for t in targets]).contiguous()
+    params = {k: gd[k].clone().requires_grad_(True) for k in optim.PARAMS}
+    pose = torch.zeros(2, 6, device="cuda", requires_grad=True)
+    loss = optim.RenderLoss.apply(pipe, gd["mp"], tcol, tdep, *[params[k] for k in optim.PARAMS], pose)
+    (loss[0] * 1.0 + loss[1] * 2.0).backward()
+    # reference: one view at a time through the pipeline calls
+    ref = {k: torch.zeros_like(gd[k]) for k in optim.PARAMS}
+    ref_pose = []
+    for v, w in ((0, 1.0), (1, 2.0)):
+        vb = gs.ViewBatch([cams[v]], synth.n_gaussians(g))
+        pp = gs.Pipeline(ctx, vb, capacity=1 << 22)
+        gst = gs.gaussians_struct(gd)
+        pp.forward(gst)
+        pp.loss_and_grads(targets[v][0].reshape(-1).contiguous(), targets[v][1])
+        lv = float(loss.detach()[v])
+        assert abs(float(pp.loss[0]) - lv) <= 1e-5 * abs(lv)
+        gr = gs.alloc_grads(synth.n_gaussians(g))
+        pz = torch.zeros(6, device="cuda")
+        pp.backward(gst, gs.grads_struct(gr, pz))
+        for k in optim.PARAMS:
+            ref[k] += w * gr[k]
+        ref_pose.append(w * pz)
+    torch.cuda.synchronize()
+    for k in optim.PARAMS:
+        scale = float(ref[k].abs().max())
+        torch.testing.assert_close(params[k].grad, ref[k], rtol=1e-4, atol=1e-5 * scale)
+    torch.testing.assert_close(pose.grad, torch.stack(ref_pose), rtol=1e-4, atol=1e-5 * float(torch.stack(ref_pose).abs().max()))
+
+
+def _pose_error(T, T_ref):
+    dR = T[:, :3] @ T_ref[:, :3].T
+    ang = np.degrees(np.arccos(np.clip((np.trace(dR) - 1) / 2, -1, 1)))
+    # camera centres
+    c = -T[:, :3].T @ T[:, 3]
+    c_ref = -T_ref[:, :3].T @ T_ref[:, 3]
+    return ang, np.linalg.norm(c - c_ref)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_tracking_converges(ctx, use_graph):
+    """From 0.5 degree and 1 cm off, 100 tracking iterations bring the pose
+    close to the one the frame was rendered at."""
+    g, cam, _ = _scene(seed=7, n=30000, W=320, H=240)
+    gd = gs.to_device(g)
+    true_cam = synth.camera(320, 240, synth.perturbed_pose(synth.rng_for(70), deg=0.3, trans=0.005))
+    tc, td = _render_target(ctx, gd, true_cam)
+    T0 = synth.perturbed_pose(synth.rng_for(71), deg=0.5, trans=0.01, base=true_cam["T_cw"])
+    ang0, dist0 = _pose_error(T0.astype(np.float64), true_cam["T_cw"].astype(np.float64))
+    trk = optim.Tracker(ctx, gd, synth.camera(320, 240, T0), use_graph=use_graph)
+    T, loss, exact = trk.run(tc.reshape(-1).contiguous(), td, iters=100)
+    ang, dist = _pose_error(T, true_cam["T_cw"].astype(np.float64))
+    print(f"tracking: rank {trk.rank} start {ang0:.3f} deg {dist0 * 1e3:.2f} mm -> {ang:.4f} deg {dist * 1e3:.3f} mm, "
+          f"loss {loss:.3f}, exact {exact}")
+    assert exact
+    assert ang < 0.2 * ang0 and dist < 0.2 * dist0
+
+
+def test_mapping_reduces_loss(ctx):
+    """Perturbed colours and opacities fitted back against two views."""
+    g, cam, tcam = _scene(seed=9, n=15000, W=160, H=120)
+    gd = gs.to_device(g)
+    cams = [cam, tcam]
+    targets = [_render_target(ctx, gd, c) for c in cams]
+    tcol = torch.cat([t[0].view(3, -1) for t in targets], dim=1).reshape(-1).contiguous()
+    tdep = torch.cat([t[1] for t in targets]).contiguous()
+    rng = np.random.default_rng(3)
+    gp = dict(g)
+    gp["color"] = np.clip(g["color"] + rng.normal(0, 0.1, g["color"].shape), 0, 1).astype(np.float32)
+    gp["opacity_logit"] = (g["opacity_logit"] + rng.normal(0, 0.5, g["opacity_logit"].shape)).astype(np.float32)
+    gpd = gs.to_device(gp)
+    losses = optim.map_gaussians(ctx, gpd, cams, tcol, tdep, iters=60)
+    print("mapping loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
