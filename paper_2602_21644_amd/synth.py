@@ -205,6 +205,46 @@ def window_cameras(seed, n_views, width, height, spacing=5):
     return cams
 
 
+def box_sequence(seed, n, width, height, n_frames, n_boxes=3, box_frac=0.05, spacing=1, zmin=0.5, zmax=4.0):
+    """A moving-box sequence: the map (the scene at frame 0, boxes at their
+    first positions), and per frame the camera pose (a random walk of 1 cm /
+    0.5 degree per frame) and the observed scene, whose boxes keep moving
+    U[0.05, 0.20] m along a random signed axis per frame. Returns
+    dict(map=gaussians, cams=[...], obs=[gaussians per frame], slices=[box
+    slices], dynamic=bool[n] ground-truth flags (box Gaussians)). Static
+    depths are drawn on [zmin, zmax]."""
+    rng = rng_for(seed)
+    nb_total = int(round(n * box_frac)) if n_boxes > 0 else 0
+    g_static = static_gaussians(rng, n - nb_total, width, height, zmin=zmin, zmax=zmax)
+    parts, slices, start = [g_static], [], n - nb_total
+    boxes = random_boxes(rng, n_boxes, width, height)
+    per = [nb_total // max(n_boxes, 1)] * n_boxes
+    if n_boxes:
+        per[-1] += nb_total - sum(per)
+    for b, k in zip(boxes, per):
+        parts.append(box_gaussians(rng, b, k))
+        slices.append(slice(start, start + k))
+        start += k
+    g0 = concat_gaussians(parts)
+    g0["mp"][:] = np.float32(0.5)  # no prior knowledge of the state
+    dynamic = np.zeros(n, bool)
+    for sl in slices:
+        dynamic[sl] = True
+    cams, obs = [], []
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
+    cur = boxes
+    for t in range(n_frames):
+        for _ in range(spacing):
+            pose = perturbed_pose(rng, deg=0.5, trans=0.01, base=pose)
+            cur = move_boxes(rng, cur)
+        g_t = g0
+        for b0, b1, sl in zip(boxes, cur, slices):
+            g_t = translate_gaussians(g_t, sl, b1["centre"] - b0["centre"])
+        cams.append(camera(width, height, pose))
+        obs.append(g_t)
+    return dict(map=g0, cams=cams, obs=obs, slices=slices, dynamic=dynamic)
+
+
 # ---------------------------------------------------------------- MP-update inputs
 def mp_frame_inputs(seed, n, width, height, n_inst=3, invalid_frac=0.05, cull_frac=0.05):
     """Per-pixel and per-Gaussian inputs of one MP update, drawn directly:
