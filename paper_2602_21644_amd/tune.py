@@ -1,0 +1,113 @@
+"""Autotuner of the library's launch knobs, cached in JSON.
+
+Knobs (gs_ctx_set_param): render_batch (records per LDS batch of the
+forward), bwd_batch (of the backward), bin_chunk (records per workgroup of
+the full binning path); plus the prefix rank of gs_bin_sort (the smallest
+exact one, see optim.choose_rank). Tiles stay 16 x 16, so every knob leaves
+the results unchanged: the forward image is bit-identical, the gradients
+differ only in the order of their float atomics.
+
+The cache key is (GPU architecture, image-size bucket, Gaussian-count
+bucket, number of views); an entry holds the knobs and the measured
+milliseconds per iteration.
+"""
+
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+
+import torch
+
+from . import gs
+from .optim import choose_rank
+
+KNOBS = dict(render_batch=(64, 128, 256), bwd_batch=(32, 64, 128))
+FULL_KNOBS = dict(bin_chunk=(256, 512, 1024, 2048))
+
+
+def default_cache():
+    root = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.environ.get("GS_TUNE_CACHE", os.path.join(root, "paper_2602_21644_amd", "tune.json"))
+
+
+def bucket_key(views, n):
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    px = max(1, views.pixel_count // views.V)
+    return f"{arch}|px2^{round(math.log2(px))}|n2^{round(math.log2(max(n, 1)))}|v{views.V}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time(step, iters):
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / iters
+
+
+def tune(ctx, views, gaussians, target_color, target_depth, cache=None, iters=5, force=False):
+    """Knobs for this workload: from the cache when present (unless force),
+    else measured over `iters` iterations of render, loss and backward per
+    candidate and stored. Applies them to ctx and returns the entry
+    (knobs, max_rank, ms, cached)."""
+    cache = cache or default_cache()
+    n = int(gaussians["opacity_logit"].shape[0])
+    key = bucket_key(views, n)
+    table = _load(cache)
+    gst = gs.gaussians_struct(gaussians)
+    if key in table and not force:
+        ent = dict(table[key])
+        for k, v in ent["knobs"].items():
+            ctx.set_param(k, v)
+        ent["cached"] = True
+        return ent
+    R, n_inst = choose_rank(ctx, views, gst, n)
+    pipe = gs.Pipeline(ctx, views, capacity=int(1.5 * n_inst) + (1 << 16), max_rank=R)
+    grads = gs.alloc_grads(n)
+    pose = torch.zeros(6 * views.V, device=gaussians["mean"].device)
+    grs = gs.grads_struct(grads, pose)
+
+    def step():
+        pipe.forward(gst)
+        pipe.loss_and_grads(target_color, target_depth)
+        pipe.backward(gst, grs)
+
+    space = dict(KNOBS)
+    if R == 0:
+        space.update(FULL_KNOBS)
+    names = list(space)
+    best = None
+    for combo in itertools.product(*[space[k] for k in names]):
+        for k, v in zip(names, combo):
+            ctx.set_param(k, v)
+        ms = _time(step, iters)
+        if best is None or ms < best[0]:
+            best = (ms, dict(zip(names, combo)))
+    over, _, inc = pipe.check()
+    if over:
+        raise RuntimeError("binning capacity exceeded while tuning")
+    for k, v in best[1].items():
+        ctx.set_param(k, v)
+    ent = dict(knobs=best[1], max_rank=R, ms=best[0])
+    table = _load(cache)
+    table[key] = ent
+    os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+    tmp = cache + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, cache)
+    return dict(ent, cached=False)
