@@ -7,10 +7,12 @@ Gaussian parameter and the pose twist. The target RGB-D frame is rendered by
 the same library at a camera 0.5 degree / 1 cm away with the boxes moved.
 
 A step is gs_project -> gs_bin_sort -> gs_render_fwd -> gs_loss ->
-gs_render_bwd. The timed region replays a hip graph of the step K times
-(inputs resident in HBM); a second timed region runs K eager steps with every
-kernel bracketed by HIP events, which gives per-kernel durations for the
-roofline entry. The oracle is timed on the host on a pixel sample.
+gs_render_bwd (one optimisation iteration; the per-frame MP update is timed
+beside it). The prefix rank is the smallest exact one and the launch knobs
+are autotuned first. The timed region replays a hip graph of the step K
+times (inputs resident in HBM); a second timed region runs K eager steps with
+every kernel bracketed by HIP events, which gives per-kernel durations for
+the roofline entry. The oracle is timed on the host on a pixel sample.
 
 Prints one JSON line.
 """
@@ -29,6 +31,18 @@ if ROOT not in sys.path:
 
 METRIC = "MP-weighted render+backward iters/s @640×480, 1M Gaussians; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFS = 157.3  # 256 CUs x 4 SIMDs x 2.4 GHz x 64 FP32 FLOP/clk (packed FP32)
+# FP32 FLOPs per (pixel, composited entry) pair of the compositing kernels
+FLOPS_PER_PAIR = {"render_fwd_kernel": 28, "render_bwd_kernel": 54}
+# HBM traffic per launch from rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE in KiB) at
+# this workload, valid while the kernel source hashes to the recorded value;
+# the counters are scaled by what they read for a 256 MiB device copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0)
+PMC_TRAFFIC = {
+    "render_bwd_kernel<64>": {"fetch_kib": 10399.5, "write_kib": 26228.1,
+                              "sha256": "d29d12c4e9f3bc757704abb13e8f55eeb61238d629f6539bfed742ac521612c1"},
+}
+PMC_SCALE = {"fetch": 2.0, "write": 1.0}
 
 
 def log(msg):
@@ -48,6 +62,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--max-rank", type=int, default=-1,
                     help="prefix rank for binning (-1: smallest power of two >= 256 that is exact; 0: full lists)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch knobs")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many eager steps (for rocprofv3) and exit")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -60,7 +75,13 @@ def kernel_bytes(name, st):
     """Algorithmic HBM bytes of one launch of `name` for this workload."""
     N, I, P, T, Mrec = st["n"], st["instances"], st["pixels"], st["tiles"], st["records"]
     if name.startswith("project_kernel"):
-        return N * (44 + 16) + Mrec * (48 + 8 + 4)
+        return N * 44 + Mrec * (8 + 4)
+    if name.startswith("psel_kernel"):
+        return Mrec * 4 + st["selected"] * (60 + 48 + 8 + 16)
+    if name.startswith("psort_kernel"):
+        return st["selected"] * (16 + 12)
+    if name.startswith("ptiles_kernel"):
+        return st["selected"] * 12 + I * 4
     if name.startswith("radix_hist_kernel"):
         return Mrec * 4
     if name.startswith("radix_scatter_kernel"):
@@ -112,17 +133,24 @@ def main():
     views = gs.ViewBatch([cam], a.n)
     gt = gs.to_device(g)
     gst = gs.gaussians_struct(gt)
-    R = a.max_rank if a.max_rank >= 0 else 256
-    while True:
+    from paper_2602_21644_amd import optim, tune
+    if a.max_rank >= 0:
+        R = a.max_rank
         probe = gs.Pipeline(ctx, views, capacity=a.n * 64, max_rank=R)
         probe.forward(gst)
         over, n_inst, inc = probe.check()
         del probe
-        assert not over
-        if inc == 0 or R == 0:
-            break
-        R = R * 2 if R * 2 < a.n else 0
+        assert not over and inc == 0, "the given prefix rank is not exact for this workload"
+    else:
+        R, n_inst = optim.choose_rank(ctx, views, gst, a.n)
     log(f"[bench] prefix rank {R} ({'full lists' if R == 0 else 'prefix lists'}), {n_inst} list entries")
+    knobs = None
+    if not a.no_tune:
+        import tempfile
+        ent = tune.tune(ctx, views, gt, tc, td, cache=os.path.join(tempfile.gettempdir(), "gs_bench_tune.json"),
+                        force=True)
+        knobs = ent["knobs"]
+        log(f"[bench] tuned knobs {knobs} ({ent['ms']:.4f} ms/iteration while tuning)")
     cap = int(n_inst * 1.25) + 4096
     pipe = gs.Pipeline(ctx, views, capacity=cap, max_rank=R)
     grads = gs.alloc_grads(a.n)
@@ -168,9 +196,12 @@ def main():
     loaded_bwd = int(((tile_max + bb - 1) // bb * bb).clamp(max=lens).sum())
     touched = int((grads["color"].abs().sum(0) > 0).sum())
     chunk = ctx.get_param("bin_chunk")
+    # records the prefix path binned (the distinct ids of the lists)
+    selected = int(torch.unique(pipe.ids[:n_inst]).numel()) if R > 0 else 0
+    pairs = int(pipe.img_nlast.to(torch.int64).sum())  # (pixel, composited entry) pairs
     st = dict(n=a.n, instances=n_inst, pixels=P, tiles=views.tile_count, records=views.rec_count,
               nlim=views.rec_count, cm=views.tile_count * ((views.rec_count + chunk - 1) // chunk),
-              loaded_fwd=loaded_fwd, loaded_bwd=loaded_bwd, touched=touched)
+              loaded_fwd=loaded_fwd, loaded_bwd=loaded_bwd, touched=touched, selected=selected, pairs=pairs)
     log(f"[bench] instances {n_inst}, touched Gaussians {touched}, entries loaded fwd {loaded_fwd}, "
         f"binning LDS limit {ctx.get_param('lds_limit')}")
 
@@ -224,7 +255,22 @@ def main():
     dom = max(per_step, key=per_step.get)
     dom_bytes = kernel_bytes(dom, st)
     dom_us = avg_launch_us[dom]
-    achieved = dom_bytes / (dom_us * 1e-6) / 1e9 if dom_bytes else None
+    base = dom.split("<")[0]
+    if base in FLOPS_PER_PAIR:
+        # compositing is bound by vector FP32 arithmetic, not by HBM
+        flops = FLOPS_PER_PAIR[base] * pairs
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(flops / (dom_us * 1e-6) / 1e12, 3),
+                "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s"}
+        roof["frac"] = round(roof["achieved"] / FP32_VECTOR_PEAK_TFS, 4)
+        roof["algorithmic_flops"] = flops
+        roof["hbm_algorithmic_bytes"] = dom_bytes
+    else:
+        achieved = dom_bytes / (dom_us * 1e-6) / 1e9 if dom_bytes else None
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "algorithmic_bytes": dom_bytes}
+    roof["traffic"] = pmc_traffic(dom)
+    roof["avg_launch_us"] = round(dom_us, 2)
     log("[bench] per-step kernel time (us): " + ", ".join(f"{k}={1000 * v:.1f}" for k, v in
                                                           sorted(per_step.items(), key=lambda x: -x[1])))
     # whole-iteration byte model
@@ -253,12 +299,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.n} Gaussians, one {a.width}x{a.height} view, render+loss+backward to all "
                                f"Gaussian parameters and the pose", "n_gaussians": a.n, "width": a.width,
-                   "height": a.height, "instances": n_inst, "prefix_rank": R, "parallelism": "single-gpu",
+                   "height": a.height, "instances": n_inst, "prefix_rank": R, "knobs": knobs,
+                   "composited_pairs": pairs, "parallelism": "single-gpu",
                    "timed": "hip graph replay" if graph is not None else "eager"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved
-                     else None, "traffic": None, "avg_launch_us": round(dom_us, 2),
-                     "algorithmic_bytes": dom_bytes},
+        "roofline": roof,
         "iteration_bytes_model": int(total_bytes),
         "iteration_hbm_frac": round(iter_frac, 4),
         "eager_ms_per_step": round(eager_ms, 4),
@@ -269,6 +313,27 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, cam, tc.cpu().numpy().reshape(3, -1), td.cpu().numpy())
     print(json.dumps(out), flush=True)
+
+
+def kernel_source_hash(kernel):
+    """sha256 of the HIP source that defines `kernel` (None when unknown)."""
+    import hashlib
+    src = {"render_bwd_kernel": "k_render.hip", "render_fwd_kernel": "k_render.hip",
+           "project_kernel": "k_project.hip"}.get(kernel.split("<")[0])
+    if not src:
+        return None
+    path = os.path.join(ROOT, "paper_2602_21644_amd", "csrc", src)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch from the recorded counters, None when the kernel
+    changed since they were taken."""
+    rec = PMC_TRAFFIC.get(kernel)
+    if not rec or rec["sha256"] != kernel_source_hash(kernel):
+        return None
+    return int(1024 * (rec["fetch_kib"] * PMC_SCALE["fetch"] + rec["write_kib"] * PMC_SCALE["write"]))
 
 
 def mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td):

@@ -59,7 +59,7 @@ def _time(step, iters):
     return e0.elapsed_time(e1) / iters
 
 
-def tune(ctx, views, gaussians, target_color, target_depth, cache=None, iters=5, force=False):
+def tune(ctx, views, gaussians, target_color, target_depth, cache=None, iters=5, force=False, margin=0.03):
     """Knobs for this workload: from the cache when present (unless force),
     else measured over `iters` iterations of render, loss and backward per
     candidate and stored. Applies them to ctx and returns the entry
@@ -90,12 +90,16 @@ def tune(ctx, views, gaussians, target_color, target_depth, cache=None, iters=5,
     if R == 0:
         space.update(FULL_KNOBS)
     names = list(space)
+    # the current knobs first; another candidate wins only when it is at
+    # least `margin` faster, so timing noise does not flip the choice
+    cur = tuple(ctx.get_param(k) for k in names)
+    combos = [cur] + [c for c in itertools.product(*[space[k] for k in names]) if c != cur]
     best = None
-    for combo in itertools.product(*[space[k] for k in names]):
+    for combo in combos:
         for k, v in zip(names, combo):
             ctx.set_param(k, v)
         ms = _time(step, iters)
-        if best is None or ms < best[0]:
+        if best is None or ms < (1.0 - margin) * best[0]:
             best = (ms, dict(zip(names, combo)))
     over, _, inc = pipe.check()
     if over:
