@@ -378,35 +378,25 @@ def mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td):
     return float(np.median(times))
 
 
-def cpu_baseline(g, cam, tc, td):
-    """The FP64 oracle on the host: full projection and projection adjoint,
-    render + loss + render adjoint on two pixel samples (S and 2S pixels);
-    per-pixel and fixed costs are separated and extrapolated to all pixels."""
+def cpu_baseline(g, cam, tc, td, budget_s=10.0):
+    """The FP64 oracle on the host: whole iterations of the step (projection,
+    render of every pixel, loss, render adjoint, projection adjoint) repeated
+    until about `budget_s` seconds of work, at least one."""
     import oracle
-    P = cam["width"] * cam["height"]
-    rng = np.random.default_rng(0)
+    n_it = 0
     t0 = time.perf_counter()
-    pr = oracle.project(g, cam)
-    t_proj = time.perf_counter() - t0
-    times = {}
-    S = 4096
-    for s in (S, 2 * S):
-        pix = rng.choice(P, size=s, replace=False)
-        t0 = time.perf_counter()
-        im = oracle.render(pr, g, cam, pixels=pix)
-        L = oracle.loss(im, tc[:, pix], td[pix])
-        g2d = oracle.render_backward(pr, g, cam, L["dC"], L["dD"], L["dM"], L["dT"], pixels=pix)
-        times[s] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.project_backward(g, cam, g2d)
-    t_pbwd = time.perf_counter() - t0
-    per_px = max(times[2 * S] - times[S], 0.0) / S
-    fixed = max(times[S] - S * per_px, 0.0)
-    t_iter = t_proj + t_pbwd + fixed + per_px * P
-    return {"value": round(1.0 / t_iter, 5), "unit": "iters/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"full projection and projection adjoint of all Gaussians; render+loss+render adjoint of "
-                      f"{S} and {2 * S} random pixels, per-pixel cost extrapolated to {P} pixels "
-                      f"(est. {t_iter:.2f} s per iteration)"}
+    while True:
+        pr = oracle.project(g, cam)
+        im = oracle.render(pr, g, cam)
+        L = oracle.loss(im, tc, td)
+        g2d = oracle.render_backward(pr, g, cam, L["dC"], L["dD"], L["dM"], L["dT"])
+        oracle.project_backward(g, cam, g2d)
+        n_it += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": round(n_it / el, 5), "unit": "iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n_it} whole iterations of the step (every pixel, every Gaussian) in {el:.1f} s"}
 
 
 if __name__ == "__main__":
