@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--max-rank", type=int, default=-1,
                     help="prefix rank for binning (-1: smallest power of two >= 256 that is exact; 0: full lists)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch knobs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-window, uneven-batch and learned-MP forms reported beside the step")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many eager steps (for rocprofv3) and exit")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -310,9 +312,187 @@ def main():
         "mp_update_ms": round(mp_ms, 4),
         "wall_s_timed": round(t_wall, 3),
     }
+    if not a.no_extras:
+        del pipe, grads
+        torch.cuda.empty_cache()
+        out["window_batch"] = window_batch(ctx, a, g, g_t)
+        out["uneven_batch"] = uneven_batch(ctx)
+        out["learned_mp"] = learned_mp(ctx, a, g, cam, tc, td)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, cam, tc.cpu().numpy().reshape(3, -1), td.cpu().numpy())
     print(json.dumps(out), flush=True)
+
+
+def _graph_time(torch, step, reps=20):
+    """ms per replay of a HIP graph of step()."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _render_targets(ctx, views, g_dev):
+    """Observed frames of a view batch: colour and depth (0 where A < 0.5),
+    rendered with exact prefix lists."""
+    import torch
+    from paper_2602_21644_amd import gs, optim
+    n = int(g_dev["opacity_logit"].shape[0])
+    gst = gs.gaussians_struct(g_dev)
+    R, n_inst = optim.choose_rank(ctx, views, gst, n)
+    tp = gs.Pipeline(ctx, views, capacity=int(1.25 * n_inst) + (1 << 16), max_rank=R)
+    tp.forward(gst)
+    over, _, inc = tp.check()
+    assert not over and inc == 0
+    A = 1.0 - tp.img_T
+    tc = tp.img_color.clone()
+    td = torch.where(A >= 0.5, tp.img_depth, torch.zeros_like(A)).contiguous()
+    return tc, td
+
+
+def _batch_step(ctx, views, g_dev, tc, td):
+    """Exact prefix rank, pipeline and step() of render + loss + backward."""
+    import torch
+    from paper_2602_21644_amd import gs, optim
+    n = int(g_dev["opacity_logit"].shape[0])
+    gst = gs.gaussians_struct(g_dev)
+    R, n_inst = optim.choose_rank(ctx, views, gst, n)
+    pipe = gs.Pipeline(ctx, views, capacity=int(1.25 * n_inst) + (1 << 16), max_rank=R)
+    grads = gs.alloc_grads(n)
+    pose = torch.zeros(6 * views.V, device="cuda")
+    grs = gs.grads_struct(grads, pose)
+
+    def step():
+        pipe.forward(gst)
+        pipe.loss_and_grads(tc, td)
+        pipe.backward(gst, grs)
+
+    return pipe, step, R, n_inst
+
+
+def window_batch(ctx, a, g, g_t):
+    """8 keyframes (every 5th frame of the camera walk) of the 1M scene
+    rendered and back-propagated in one call sequence, timed as a graph."""
+    import torch
+    from paper_2602_21644_amd import gs, synth
+    cams = synth.window_cameras(a.seed + 1, 8, a.width, a.height, spacing=5)
+    views = gs.ViewBatch(cams, a.n)
+    tc, td = _render_targets(ctx, views, gs.to_device(g_t))
+    torch.cuda.empty_cache()
+    gd = gs.to_device(g)
+    pipe, step, R, n_inst = _batch_step(ctx, views, gd, tc, td)
+    ms = _graph_time(torch, step)
+    over, _, inc = pipe.check()
+    assert not over and inc == 0
+    log(f"[bench] 8-view window: {ms:.3f} ms per batched iteration")
+    return {"views": 8, "n_gaussians": a.n, "width": a.width, "height": a.height, "prefix_rank": R,
+            "instances": n_inst, "ms_per_step": round(ms, 4), "frame_iters_per_s": round(8000.0 / ms, 1)}
+
+
+def uneven_batch(ctx):
+    """4 scenes (50k at 320x240, 150k at 640x480, 300k at 960x540, 600k at
+    1280x720; 1-5 moving boxes each) x 8 frames = 32 views rendered and
+    back-propagated in one captured graph."""
+    import torch
+    from paper_2602_21644_amd import gs, synth
+    specs = [(50_000, 320, 240), (150_000, 640, 480), (300_000, 960, 540), (600_000, 1280, 720)]
+    rng = np.random.default_rng(400)
+    scenes, targets, cams, vs = [], [], [], []
+    for i, (n, W, H) in enumerate(specs):
+        g, cam, tcam, g_t, sl = synth.moving_box_scene(400 + i, n, W, H, n_boxes=int(rng.integers(1, 6)))
+        scenes.append(g)
+        targets.append(g_t)
+        cams += synth.window_cameras(410 + i, 8, W, H, spacing=2)
+        vs += [i] * 8
+    begin = np.concatenate([[0], np.cumsum([s[0] for s in specs])]).tolist()
+    n_all = int(begin[-1])
+    views = gs.ViewBatch(cams, n_all, view_scene=vs, scene_begin=begin)
+    tc, td = _render_targets(ctx, views, gs.to_device(synth.concat_gaussians(targets)))
+    torch.cuda.empty_cache()
+    gd = gs.to_device(synth.concat_gaussians(scenes))
+    pipe, step, R, n_inst = _batch_step(ctx, views, gd, tc, td)
+    ms = _graph_time(torch, step)
+    over, _, inc = pipe.check()
+    assert not over and inc == 0
+    log(f"[bench] uneven 32-frame batch: {ms:.3f} ms per graph replay")
+    return {"frames": 32, "scenes": [f"{n}@{W}x{H}" for n, W, H in specs], "prefix_rank": R, "instances": n_inst,
+            "ms_per_step": round(ms, 4), "frames_per_s": round(32000.0 / ms, 1)}
+
+
+def learned_mp(ctx, a, g, cam, tc, td):
+    """The surrogate trained on plain-cue M_p of moving-box sequences; MP error
+    of plain and learned forms on held-out sequences, and the per-frame time
+    of the MP source at the headline size (plain: gs_mp_update; learned:
+    features + network + gs_mp_update with the network's M_p)."""
+    import torch
+    from paper_2602_21644_amd import gs, mp_learn, synth
+
+    def seq(seed, frames):
+        return synth.box_sequence(seed, 20000, 96, 72, frames, n_boxes=3, box_frac=0.2, zmin=3.0, zmax=6.0)
+
+    sur = mp_learn.MPSurrogate(ctx, seed=0)
+    for seed in (1000, 1001, 1002, 1003):
+        mp_learn.run_sequence(ctx, seq(seed, 12), surrogate=sur, train=True, steps_per_frame=8)
+    errs = []
+    for seed in (5000, 5001):
+        sq = seq(seed, 10)
+        mp_p, obs_p, _ = mp_learn.run_sequence(ctx, sq)
+        mp_l, obs_l, _ = mp_learn.run_sequence(ctx, sq, surrogate=sur)
+        ob = obs_p & obs_l
+        errs.append((mp_learn.mp_error(mp_p, sq["dynamic"], ob), mp_learn.mp_error(mp_l, sq["dynamic"], ob)))
+    e_plain = float(np.mean([e[0] for e in errs]))
+    e_learned = float(np.mean([e[1] for e in errs]))
+    # per-frame time at 1M Gaussians, 640x480
+    gd = gs.to_device(g)
+    mpf = mp_learn.MPFrame(ctx, gd, cam)
+    inst = torch.zeros(a.width * a.height, dtype=torch.int32, device="cuda")
+    prior, conf = mp_learn.instance_tables(0)
+    mpf.views.set_pose(0, cam["T_cw"])
+    mpf.pipe.forward(mpf.gst)
+    tgt = gs.Target(gs.ptr(tc), gs.ptr(td))
+
+    def plain():
+        fr = mpf._frame(inst, prior, conf, True)
+        gs.gs_mp_update(ctx, mpf.views.s, mpf.pipe.proj, mpf.pipe.img, tgt, fr, mpf.params, gd["mp"], mpf.out, mpf.ws)
+
+    def learned():
+        fr = mpf._frame(inst, prior, conf, True)
+        gs.gs_mlp_features(ctx, mpf.views.s, mpf.pipe.img, tgt, fr, mpf.x)
+        sur.predict(mpf.x, mpf.y)
+        fr = mpf._frame(inst, prior, conf, True, mpf.y)
+        gs.gs_mp_update(ctx, mpf.views.s, mpf.pipe.proj, mpf.pipe.img, tgt, fr, mpf.params, gd["mp"], mpf.out, mpf.ws)
+
+    t = {}
+    for name, fn in (("plain", plain), ("learned", learned)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        t[name] = e0.elapsed_time(e1) / 10
+    log(f"[bench] MP error plain {e_plain:.4f} learned {e_learned:.4f}; per-frame ms plain {t['plain']:.3f} "
+        f"learned {t['learned']:.3f}")
+    return {"mp_abs_error_plain": round(e_plain, 4), "mp_abs_error_learned": round(e_learned, 4),
+            "equal_accuracy": bool(e_learned <= e_plain + 0.01), "ms_per_frame_plain": round(t["plain"], 4),
+            "ms_per_frame_learned": round(t["learned"], 4),
+            "eval": "2 held-out 10-frame sequences, 20k Gaussians at 96x72; timing at the headline size"}
 
 
 def kernel_source_hash(kernel):

@@ -103,13 +103,18 @@ def choose_rank(ctx, views, gst, n, start=256):
     every tile of the views saturate at their current poses, with the instance
     count it gives; (0, count) when none does (full lists)."""
     R = start
+    cap = max(1 << 20, 16 * n)
     while True:
-        probe = gs.Pipeline(ctx, views, capacity=max(1 << 20, 64 * n), max_rank=R)
+        probe = gs.Pipeline(ctx, views, capacity=cap, max_rank=R)
         probe.forward(gst)
         over, n_inst, inc = probe.check()
         del probe
         if over:
-            raise RuntimeError("binning capacity exceeded while choosing the prefix rank")
+            # the library reports the count it needed: retry this rank with room for it
+            if n_inst >= (1 << 32) - 1:
+                raise RuntimeError("more list entries than 32-bit offsets hold")
+            cap = int(n_inst * 1.1) + (1 << 16)
+            continue
         if inc == 0 or R == 0:
             return R, n_inst
         R = R * 2 if R * 2 <= ctx.get_param("prefix_cap") else 0
