@@ -346,14 +346,31 @@ def _graph_time(torch, step, reps=20):
     return e0.elapsed_time(e1) / reps
 
 
-def _render_targets(ctx, views, g_dev):
+def _full_count(ctx, views, gst, n):
+    """List entries of full lists (grows the probe capacity to the reported count)."""
+    from paper_2602_21644_amd import gs
+    cap = max(1 << 20, 16 * n)
+    while True:
+        probe = gs.Pipeline(ctx, views, capacity=cap, max_rank=0)
+        probe.forward(gst)
+        over, n_inst, _ = probe.check()
+        del probe
+        if not over:
+            return n_inst
+        cap = int(n_inst * 1.1) + (1 << 16)
+
+
+def _render_targets(ctx, views, g_dev, full=False):
     """Observed frames of a view batch: colour and depth (0 where A < 0.5),
-    rendered with exact prefix lists."""
+    rendered with exact prefix lists (or full lists)."""
     import torch
     from paper_2602_21644_amd import gs, optim
     n = int(g_dev["opacity_logit"].shape[0])
     gst = gs.gaussians_struct(g_dev)
-    R, n_inst = optim.choose_rank(ctx, views, gst, n)
+    if full:
+        R, n_inst = 0, _full_count(ctx, views, gst, n)
+    else:
+        R, n_inst = optim.choose_rank(ctx, views, gst, n)
     tp = gs.Pipeline(ctx, views, capacity=int(1.25 * n_inst) + (1 << 16), max_rank=R)
     tp.forward(gst)
     over, _, inc = tp.check()
@@ -364,13 +381,17 @@ def _render_targets(ctx, views, g_dev):
     return tc, td
 
 
-def _batch_step(ctx, views, g_dev, tc, td):
-    """Exact prefix rank, pipeline and step() of render + loss + backward."""
+def _batch_step(ctx, views, g_dev, tc, td, full=False):
+    """Exact prefix rank (or full lists), pipeline and step() of render + loss
+    + backward."""
     import torch
     from paper_2602_21644_amd import gs, optim
     n = int(g_dev["opacity_logit"].shape[0])
     gst = gs.gaussians_struct(g_dev)
-    R, n_inst = optim.choose_rank(ctx, views, gst, n)
+    if full:
+        R, n_inst = 0, _full_count(ctx, views, gst, n)
+    else:
+        R, n_inst = optim.choose_rank(ctx, views, gst, n)
     pipe = gs.Pipeline(ctx, views, capacity=int(1.25 * n_inst) + (1 << 16), max_rank=R)
     grads = gs.alloc_grads(n)
     pose = torch.zeros(6 * views.V, device="cuda")
@@ -381,6 +402,8 @@ def _batch_step(ctx, views, g_dev, tc, td):
         pipe.loss_and_grads(tc, td)
         pipe.backward(gst, grs)
 
+    # the graph replays write these: they live as long as the step
+    step.outputs = (grads, pose)
     return pipe, step, R, n_inst
 
 
@@ -405,18 +428,21 @@ def window_batch(ctx, a, g, g_t):
 
 def uneven_batch(ctx):
     """4 scenes (50k at 320x240, 150k at 640x480, 300k at 960x540, 600k at
-    1280x720; 1-5 moving boxes each) x 8 frames = 32 views rendered and
-    back-propagated in one captured graph."""
+    1280x720; 1-5 moving boxes each) x 8 consecutive frames = 32 views
+    rendered and back-propagated in one captured graph."""
     import torch
     from paper_2602_21644_amd import gs, synth
     specs = [(50_000, 320, 240), (150_000, 640, 480), (300_000, 960, 540), (600_000, 1280, 720)]
     rng = np.random.default_rng(400)
     scenes, targets, cams, vs = [], [], [], []
     for i, (n, W, H) in enumerate(specs):
-        g, cam, tcam, g_t, sl = synth.moving_box_scene(400 + i, n, W, H, n_boxes=int(rng.integers(1, 6)))
+        # the scene extends 15% beyond the first view on every side: the
+        # following frames look past its edges
+        g, cam, tcam, g_t, sl = synth.moving_box_scene(400 + i, n, W, H, n_boxes=int(rng.integers(1, 6)),
+                                                       margin=0.15)
         scenes.append(g)
         targets.append(g_t)
-        cams += synth.window_cameras(410 + i, 8, W, H, spacing=2)
+        cams += synth.window_cameras(410 + i, 8, W, H, spacing=1)
         vs += [i] * 8
     begin = np.concatenate([[0], np.cumsum([s[0] for s in specs])]).tolist()
     n_all = int(begin[-1])

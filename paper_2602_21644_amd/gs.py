@@ -395,10 +395,13 @@ class ViewBatch:
 
 
 def gaussians_struct(t: dict) -> Gaussians:
+    """The C struct of the Gaussian arrays; keeps the tensors alive as long as
+    it lives."""
     g = Gaussians()
     g.n = int(t["opacity_logit"].shape[0])
     for k in ("mean", "log_scale", "quat", "opacity_logit", "color", "mp"):
         setattr(g, k, c_void_p(t[k].data_ptr()))
+    g._keep = dict(t)
     return g
 
 
@@ -497,12 +500,16 @@ class Pipeline:
 
 
 def grads_struct(gr: dict, pose: torch.Tensor, pose_only=False, accumulate=False) -> Grads:
+    """The C struct of gradient outputs. It holds raw device addresses, so it
+    keeps the tensors alive for as long as it lives (a struct that outlived
+    its tensors would let kernels write into freed, possibly unmapped memory)."""
     s = Grads()
     for k in ("mean", "log_scale", "quat", "opacity_logit", "color"):
         setattr(s, k, ptr(gr[k]) if gr is not None and k in gr else None)
     s.pose = ptr(pose)
     s.pose_only = int(pose_only)
     s.accumulate = int(accumulate)
+    s._keep = (gr, pose)
     return s
 
 

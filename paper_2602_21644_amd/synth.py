@@ -66,13 +66,15 @@ def _depth_volume_uniform(rng, n, zmin, zmax):
     return np.cbrt(zmin ** 3 + u * (zmax ** 3 - zmin ** 3))
 
 
-def static_gaussians(rng, n, width, height, zmin=0.5, zmax=4.0, mp=None) -> dict:
+def static_gaussians(rng, n, width, height, zmin=0.5, zmax=4.0, mp=None, margin=0.0) -> dict:
     """n Gaussians seen by an identity-pose camera: pixel position uniform in the
-    image, depth uniform in volume, log-scale N(-3, 0.5^2) per axis, random unit
-    quaternion (w,x,y,z), opacity logit N(0,1), RGB U[0,1], MP U[0,1]."""
+    image (widened by `margin` x the image size on every side, for scenes that
+    later views see beyond the first one), depth uniform in volume, log-scale
+    N(-3, 0.5^2) per axis, random unit quaternion (w,x,y,z), opacity logit
+    N(0,1), RGB U[0,1], MP U[0,1]."""
     fx, fy, cx, cy = intrinsics(width, height)
-    px = rng.random(n) * width
-    py = rng.random(n) * height
+    px = (rng.random(n) * (1 + 2 * margin) - margin) * width
+    py = (rng.random(n) * (1 + 2 * margin) - margin) * height
     z = _depth_volume_uniform(rng, n, zmin, zmax)
     mean = np.stack([z * (px - cx) / fx, z * (py - cy) / fy, z])
     log_scale = rng.normal(-3.0, 0.5, size=(3, n))
@@ -164,13 +166,13 @@ def tiny_scene(seed=1, n=2000, width=64, height=48):
     return g, cam, target_cam
 
 
-def moving_box_scene(seed, n, width, height, n_boxes=3, box_frac=0.05):
+def moving_box_scene(seed, n, width, height, n_boxes=3, box_frac=0.05, margin=0.0):
     """Static Gaussians plus `n_boxes` boxes that hold `box_frac` of the
     Gaussians. Returns (gaussians, camera, target camera, target gaussians,
     box slices); the target copy has the boxes moved, as in a new frame."""
     rng = rng_for(seed)
     nb_total = int(round(n * box_frac)) if n_boxes > 0 else 0
-    g_static = static_gaussians(rng, n - nb_total, width, height)
+    g_static = static_gaussians(rng, n - nb_total, width, height, margin=margin)
     parts, slices, start = [g_static], [], n - nb_total
     boxes = random_boxes(rng, n_boxes, width, height)
     per = [nb_total // max(n_boxes, 1)] * n_boxes

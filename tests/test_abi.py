@@ -74,3 +74,30 @@ def test_layout_helpers():
     with pytest.raises(gs.GSError) as e:
         gs.gs_workspace_size(ctx, v, gs.GS_OP_BIN_SORT)
     assert e.value.status == gs.GS_E_UNSUPPORTED
+
+
+def test_structs_keep_their_tensors_alive():
+    """The C structs hold raw addresses: they keep the tensors they point to
+    alive, so a captured graph replayed later never writes freed memory."""
+    import gc
+    import weakref
+
+    import torch
+    from paper_2602_21644_amd import gs
+    n = 10
+    gr = {k: torch.zeros(3, n) for k in ("mean", "log_scale", "color")}
+    gr["quat"] = torch.zeros(4, n)
+    gr["opacity_logit"] = torch.zeros(n)
+    pose = torch.zeros(6)
+    refs = [weakref.ref(t) for t in list(gr.values()) + [pose]]
+    s = gs.grads_struct(gr, pose)
+    g = {k: torch.zeros(3, n) for k in ("mean", "log_scale", "color")}
+    g.update(quat=torch.zeros(4, n), opacity_logit=torch.zeros(n), mp=torch.zeros(n))
+    grefs = [weakref.ref(t) for t in g.values()]
+    gst = gs.gaussians_struct(g)
+    del gr, pose, g
+    gc.collect()
+    assert all(r() is not None for r in refs + grefs)
+    del s, gst
+    gc.collect()
+    assert all(r() is None for r in refs + grefs)
