@@ -99,8 +99,11 @@ typedef struct gs_gaussians {
  * are required; the planar fields are optional (NULL skips them). */
 typedef struct gs_proj {
   int64_t m;
-  float* rec;        /* [m][12] compositing record: ux, uy, depth, opacity, conic
-                        (3), mp, r, g, b, 0. Written by gs_project for every
+  float* rec;        /* [m][12] compositing record: ux, uy, depth, opacity,
+                        c1, c2, c3, mp, r, g, b, 0, where (c1, c2, c3) is the
+                        conic (xx, xy, yy) times -log2(e) * (1/2, 1, 1/2), so
+                        the Gaussian at offset d is exp2(c1 dx^2 + c2 dx dy +
+                        c3 dy^2). Written by gs_project for every
                         record when key_hist is NULL; with key_hist set it is
                         written by gs_bin_sort's prefix path, for the selected
                         records only (the only ones the lists reference). */
@@ -146,6 +149,11 @@ typedef struct gs_image {
   float* mp;         /* [P]  sum alpha T m (MP channel) */
   float* T;          /* [P]  final transmittance */
   uint32_t* n_last;  /* [P]  list position after the last contributing entry */
+  uint32_t* tile_work; /* [n_tiles] optional (NULL skips): written by
+                          gs_render_fwd, per tile the sum over its four
+                          64-pixel groups (pixel rows 4i..4i+3) of the largest
+                          n_last in the group. gs_render_bwd then launches the
+                          tiles heaviest first (scheduling only). */
 } gs_image;
 
 typedef struct gs_target {
@@ -189,12 +197,15 @@ gs_status gs_ctx_destroy(gs_ctx* ctx);
 const char* gs_last_error(const gs_ctx* ctx);
 /* Tuning knobs: "render_batch" (64|128|256 list entries staged per LDS batch
  * in gs_render_fwd), "bwd_batch" (32|64|128, gs_render_bwd), "bin_chunk"
- * (256|512|1024|2048 records per binning workgroup), and "timing" (0|1, see
- * gs_ctx_kernel_times). Values outside the supported set return GS_E_ARG. */
+ * (256|512|1024|2048 records per binning workgroup), "tile_order" (0|1,
+ * default 1: gs_render_bwd launches tiles heaviest first when the image has
+ * tile_work), and "timing" (0|1, see gs_ctx_kernel_times). Values outside the
+ * supported set return GS_E_ARG. */
 gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
 /* Read-only names besides the above: "lds_limit" (LDS bytes per workgroup the
  * context uses), "prefix_cap" (selected records per view the prefix binning
- * path takes). */
+ * path takes), "n_cu" (compute units the tile order deals over; 0 before the
+ * first gs_render_bwd on a GPU). */
 gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value /*[host]*/);
 /* Measurement aid. With "timing" = 1 every kernel launch is bracketed by HIP
  * events on its stream (do not capture such launches in a graph). This call
@@ -234,7 +245,8 @@ gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g,
 
 /* Front-to-back compositing per 16x16 tile: alpha = min(0.99, o exp(p)),
  * entries with alpha < 1/255 skipped, stop before an entry that drops T below
- * 1e-4. Writes C + T bg, D, the MP channel M, T and n_last. bg is [host] RGB. */
+ * 1e-4. Writes C + T bg, D, the MP channel M, T, n_last and, when set,
+ * tile_work. bg is [host] RGB. */
 gs_status gs_render_fwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
                         const gs_bins* bins, const float* bg, gs_image* img, void* stream);
 
@@ -249,7 +261,11 @@ gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const
 /* Adjoint of render + projection for the objective sum_v L_v, to all Gaussian
  * parameters and one pose twist per view (Sec. IV-D: Gaussians and poses are
  * optimised jointly). Transmittance is recomputed back from T_final. `ws` of
- * gs_workspace_size(GS_OP_RENDER_BWD), zero-filled before first use. */
+ * gs_workspace_size(GS_OP_RENDER_BWD), zero-filled before first use; each
+ * call leaves it zero-filled except its last 4 * n_tiles bytes (rounded up to
+ * a multiple of 256), where it keeps the tile launch order. With
+ * img->tile_work set (and "tile_order" on) the tiles run heaviest first; the
+ * gradients differ only in the order of their float atomics. */
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
                         const gs_bins* bins, const gs_image* img, const gs_pixel_grads* pg, const float* bg,
                         gs_grads* grads, void* ws, size_t ws_bytes, void* stream);

@@ -45,6 +45,8 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->bwd_batch = 64;
   c->bin_chunk = 1024;
   c->timing = 0;
+  c->tile_order = 1;
+  c->n_cu = 0;
   c->lds_limit = 0;
   c->err[0] = 0;
   *out = c;
@@ -106,6 +108,9 @@ gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value) {
     ctx->bwd_batch = (int)value;
   } else if (!strcmp(name, "timing")) {
     ctx->timing = value ? 1 : 0;
+  } else if (!strcmp(name, "tile_order")) {
+    if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "tile_order: 0|1");
+    ctx->tile_order = (int)value;
   } else if (!strcmp(name, "bin_chunk")) {
     if (value != 256 && value != 512 && value != 1024 && value != 2048)
       return gs_fail(ctx, GS_E_ARG, "bin_chunk: 256|512|1024|2048");
@@ -122,6 +127,8 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   else if (!strcmp(name, "bwd_batch")) *value = ctx->bwd_batch;
   else if (!strcmp(name, "bin_chunk")) *value = ctx->bin_chunk;
   else if (!strcmp(name, "timing")) *value = ctx->timing;
+  else if (!strcmp(name, "tile_order")) *value = ctx->tile_order;
+  else if (!strcmp(name, "n_cu")) *value = ctx->n_cu;
   else if (!strcmp(name, "lds_limit")) *value = (int64_t)ctx->lds_limit;
   else if (!strcmp(name, "prefix_cap")) *value = bin_prefix_cap();
   else return GS_E_ARG;
@@ -184,7 +191,7 @@ static gs_status make_tab(gs_ctx* ctx, const gs_views* vw, ViewTab& tab) {
 }
 
 struct BwdWs {
-  size_t g2d, touched, pose, bytes;
+  size_t g2d, touched, pose, order, bytes;
 };
 static BwdWs bwd_ws_layout(const ViewTab& tab) {
   BwdWs L;
@@ -192,6 +199,7 @@ static BwdWs bwd_ws_layout(const ViewTab& tab) {
   L.g2d = o; o += al256((size_t)tab.nrec * 10 * 4);
   L.touched = o; o += al256((size_t)tab.nrec);
   L.pose = o; o += al256((size_t)tab.nv * bwd_pose_blocks(tab) * 6 * 4 + 4);
+  L.order = o; o += al256((size_t)tab.ntiles * 4);
   L.bytes = o;
   return L;
 }
@@ -335,7 +343,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   char* w = (char*)ws;
   hipStream_t s = (hipStream_t)stream;
   GS_TRY(launch_render_bwd_tiles(ctx, tab, proj, bins, img, pg, bg, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
-                                 s));
+                                 (uint32_t*)(w + L.order), s));
   return launch_bwd_project(ctx, tab, views->cams_dev, g, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
                             (float*)(w + L.pose), gr, s);
 }

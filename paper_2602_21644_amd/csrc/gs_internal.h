@@ -47,15 +47,20 @@ __device__ __forceinline__ int view_of_tile(const ViewTab& tab, int t) {
   return v;
 }
 
-// Exponent of the Gaussian at offset (dx, dy) = u - pixel, with every rounding
-// spelled out (explicit fma, no contractible mul+add) so the forward and the
-// backward kernels evaluate bit-identical alphas and take identical skips.
-__device__ __forceinline__ float gs_power(float k1, float k2, float k3, float dx, float dy) {
-  const float ax = k1 * dx;
-  const float cy = k3 * dy;
-  const float bx = k2 * dx;
-  const float q = __builtin_fmaf(ax, dx, cy * dy);
-  return __builtin_fmaf(-0.5f, q, -(bx * dy));
+// The compositing record stores the conic in base-2 exponent units:
+// (c1, c2, c3) = (-k1 log2(e) / 2, -k2 log2(e), -k3 log2(e) / 2), so that the
+// Gaussian's value at offset (dx, dy) = u - pixel is exp2 of
+//   c1 dx^2 + c2 dx dy + c3 dy^2 = dx (c1 dx + c2 dy) + c3 dy^2,
+// evaluated with every rounding spelled out (explicit fma, no contractible
+// mul+add), so the forward and the backward kernels compute bit-identical
+// alphas and take identical skips.
+#define GS_LOG2E 1.4426950408889634f
+__device__ __forceinline__ float gs_conic_scale_diag(float k) { return -0.5f * GS_LOG2E * k; }
+__device__ __forceinline__ float gs_conic_scale_off(float k) { return -GS_LOG2E * k; }
+__device__ __forceinline__ float gs_power2(float c1, float c2, float c3, float dx, float dy) {
+  const float t = __builtin_fmaf(c2, dy, c1 * dx);
+  const float u = c3 * dy;
+  return __builtin_fmaf(t, dx, u * dy);
 }
 
 #define GS_ALPHA_MIN (1.0f / 255.0f)
@@ -163,6 +168,8 @@ struct gs_ctx {
   int bwd_batch;
   int bin_chunk;
   int timing;                    // 1: bracket every launch with HIP events
+  int tile_order;                // 1: backward tiles heaviest first when tile_work is given
+  int n_cu;                      // compute units of the device (0: not queried yet)
   size_t lds_limit;              // LDS per workgroup usable by the binning scatter (0: not queried)
   std::vector<GsTimer> pending;  // launches whose events are not read yet
   char err[512];
@@ -175,13 +182,13 @@ struct gs_ctx {
     hipEvent_t e0_ = nullptr, e1_ = nullptr;                                \
     const bool t_ = (ctx) && (ctx)->timing;                                 \
     if (t_) {                                                               \
-      hipEventCreate(&e0_);                                                 \
-      hipEventCreate(&e1_);                                                 \
-      hipEventRecord(e0_, strm);                                            \
+      (void)hipEventCreate(&e0_);                                                 \
+      (void)hipEventCreate(&e1_);                                                 \
+      (void)hipEventRecord(e0_, strm);                                            \
     }                                                                       \
     hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);          \
     if (t_) {                                                               \
-      hipEventRecord(e1_, strm);                                            \
+      (void)hipEventRecord(e1_, strm);                                            \
       (ctx)->pending.push_back(GsTimer{#kern, e0_, e1_});                   \
     }                                                                       \
   } while (0)
@@ -203,7 +210,7 @@ gs_status launch_bin_sort(gs_ctx*, const ViewTab&, const BinTab&, const gs_proj*
 gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const float*, int, gs_image*,
                             hipStream_t);
 gs_status launch_render_bwd_tiles(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const gs_image*,
-                                  const gs_pixel_grads*, const float*, float*, uint8_t*, hipStream_t);
+                                  const gs_pixel_grads*, const float*, float*, uint8_t*, uint32_t*, hipStream_t);
 gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, float*, uint8_t*,
                              float*, gs_grads*, hipStream_t);
 int bwd_pose_blocks(const ViewTab&);

@@ -90,8 +90,9 @@ struct GaussSrc {
 };
 
 // The compositing record of packed Gaussian gk seen by `cam`: (u_x, u_y, z,
-// opacity), (conic, mp), (rgb, 0). Computed by the same project_f as the
-// projection kernel, so it matches the record the tile rect came from.
+// opacity), (conic in base-2 exponent units, mp), (rgb, 0). Computed by the
+// same project_f as the projection kernel, so it matches the record the tile
+// rect came from.
 __device__ __forceinline__ void render_record(const gs_camera& cam, const GaussSrc& g, int64_t gk, float4& a,
                                               float4& b, float4& c) {
   const int64_t N = g.n;
@@ -100,6 +101,6 @@ __device__ __forceinline__ void render_record(const gs_camera& cam, const GaussS
   const float q[4] = {g.quat[gk], g.quat[N + gk], g.quat[2 * N + gk], g.quat[3 * N + gk]};
   const ProjF P = project_f(cam, m, ls, q, g.opl[gk]);
   a = make_float4(P.ux, P.uy, P.pz, P.o);
-  b = make_float4(P.k1, P.k2, P.k3, g.mp[gk]);
+  b = make_float4(gs_conic_scale_diag(P.k1), gs_conic_scale_off(P.k2), gs_conic_scale_diag(P.k3), g.mp[gk]);
   c = make_float4(g.color[gk], g.color[N + gk], g.color[2 * N + gk], 0.f);
 }

@@ -59,7 +59,8 @@ __device__ __forceinline__ uint32_t project_one(const ViewTab& tab, const gs_cam
   key[r] = kout;
   if (rec && nonempty) {
     rec[3 * r + 0] = make_float4(P.ux, P.uy, P.pz, P.o);
-    rec[3 * r + 1] = make_float4(P.k1, P.k2, P.k3, mp[gk]);
+    rec[3 * r + 1] = make_float4(gs_conic_scale_diag(P.k1), gs_conic_scale_off(P.k2), gs_conic_scale_diag(P.k3),
+                                 mp[gk]);
     rec[3 * r + 2] = make_float4(color[gk], color[N + gk], color[2 * N + gk], 0.f);
   }
   if (mean2d) {

@@ -37,8 +37,10 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
     ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, const int32_t* __restrict__ trunc,
     float bg0, float bg1, float bg2, float* __restrict__ outC, float* __restrict__ outD, float* __restrict__ outM,
-    float* __restrict__ outT, uint32_t* __restrict__ nlast, int32_t* __restrict__ incomplete, int truncated_bits) {
+    float* __restrict__ outT, uint32_t* __restrict__ nlast, uint32_t* __restrict__ tile_work,
+    int32_t* __restrict__ incomplete, int truncated_bits) {
   __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
+  __shared__ uint32_t s_wmax[GS_BLOCK / 64];
   if (*overflow) return;
   const int t = blockIdx.x;
   const TileCtx tc = tile_ctx(tab, t);
@@ -49,26 +51,45 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
   uint32_t last = 0;
   bool done = !tc.inside;
   bool exhausted = true;
+  // Software pipeline: while a batch is composited, the loader threads hold
+  // the next batch's records and the ids of the one after in registers, so
+  // neither global load sits between the barriers. Entries past the list
+  // end are zero-opacity padding, which never composites.
+  const bool loader = threadIdx.x < BATCH;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 ra = z4, rb = z4, rc = z4;
+  uint32_t idn = 0;
+  if (loader) {
+    if (b + threadIdx.x < e) {
+      const int64_t r = roff + ids[b + threadIdx.x];
+      ra = rec[3 * r + 0];
+      rb = rec[3 * r + 1];
+      rc = rec[3 * r + 2];
+    }
+    if (b + BATCH + threadIdx.x < e) idn = ids[b + BATCH + threadIdx.x];
+  }
   for (uint32_t base = b; base < e; base += BATCH) {
     if (__syncthreads_count(!done) == 0) {
       exhausted = false;
       break;
     }
-    if (threadIdx.x < BATCH) {
-      if (base + threadIdx.x < e) {
-        const int64_t r = roff + ids[base + threadIdx.x];
-        s_a[threadIdx.x] = rec[3 * r + 0];
-        s_b[threadIdx.x] = rec[3 * r + 1];
-        s_c[threadIdx.x] = rec[3 * r + 2];
-      } else {
-        // padding: zero opacity never composites
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_a[threadIdx.x] = z;
-        s_b[threadIdx.x] = z;
-        s_c[threadIdx.x] = z;
-      }
+    if (loader) {
+      s_a[threadIdx.x] = ra;
+      s_b[threadIdx.x] = rb;
+      s_c[threadIdx.x] = rc;
     }
     __syncthreads();
+    if (loader) {
+      const uint32_t p1 = base + BATCH + threadIdx.x;
+      ra = rb = rc = z4;
+      if (p1 < e) {
+        const int64_t r = roff + idn;
+        ra = rec[3 * r + 0];
+        rb = rec[3 * r + 1];
+        rc = rec[3 * r + 2];
+      }
+      if (p1 + BATCH < e) idn = ids[p1 + BATCH];
+    }
     if (__any(!done)) {  // uniform over the wave
       const int n = (int)min((uint32_t)BATCH, e - base);
       const uint32_t idx0 = base - b + 1;
@@ -80,8 +101,8 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
         const float4 A = s_a[j];
         const float4 B = s_b[j];
         const float4 Cc = s_c[j];
-        const float p = gs_power(B.x, B.y, B.z, A.x - fx, A.y - fy);
-        const float alpha = fminf(GS_ALPHA_MAX, A.w * __expf(p));
+        const float p = gs_power2(B.x, B.y, B.z, A.x - fx, A.y - fy);
+        const float alpha = fminf(GS_ALPHA_MAX, A.w * __builtin_amdgcn_exp2f(p));
         const bool ok = !done && p <= 0.f && alpha >= GS_ALPHA_MIN;
         const float Tn = T * (1.0f - alpha);
         const bool stop = ok && Tn < GS_T_MIN;
@@ -115,19 +136,80 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
     outT[tc.pix] = T;
     nlast[tc.pix] = last;
   }
+  if (tile_work) {
+    // the backward's work on this tile: each wave walks to its largest n_last
+    uint32_t m = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if (__lane_id() == 0) s_wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int i = 0; i < GS_BLOCK / 64; ++i) sum += s_wmax[i];
+      tile_work[t] = sum;
+    }
+  }
   (void)trunc;
 }
 
-// Backward over one tile. g2d is planar [10][nrec]:
-// (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth).
-//
-// Per entry every lane forms ten moment terms of its pixel, with
-// h = dL/d(alpha) * exp(power) where alpha is unclamped, else 0:
-//   h*dx, h*dy, h*dx^2, h*dx*dy, h*dy^2, h, w*gC (3), w*gD   (w = alpha*T)
-// A transposed wave reduction sums them; the cross-wave pass turns the sums
-// into the 2D gradients with the entry's opacity and conic
-// (d/du = -o * conic * (sum h*d), d/dconic = -o/2 * (sum h*d d^T) off-diagonal
-// counted twice), so the per-pixel work carries no conic products.
+// Launch order of the backward's tiles, heaviest first by tile_work: a
+// counting sort into log-scale buckets (16 per octave, from the float32 bits
+// of the work), then rank r goes to block round * n_cu + (round even ? i :
+// m - 1 - i) with round = r / n_cu, i = r mod n_cu and m the blocks of that
+// round. While the whole grid is resident, blocks b and b + n_cu share a
+// compute unit, so this snake deal evens the work per unit; with more blocks
+// than fit, the heaviest tiles still start first. order[b] is the tile block b
+// runs; every tile appears once.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 2048;
+constexpr int kOrderCached = 16384;  // tiles whose buckets stay in LDS
+__device__ __forceinline__ int order_bucket(uint32_t x) {
+  const int k = (int)(__float_as_uint((float)x) >> 19) - (127 << 4) + 1;  // x = 0 -> below 0, x = 1 -> 1
+  return kOrderBuckets - 1 - min(max(k, 0), kOrderBuckets - 1);
+}
+__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_t* __restrict__ work, int ntiles,
+                                                                   int ncu, uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[kOrderBuckets];
+  __shared__ uint16_t s_bk[kOrderCached];
+  __shared__ uint32_t s_wave[kOrderThreads / 64];
+  const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6;
+  const bool cached = ntiles <= kOrderCached;
+  for (int i = tid; i < kOrderBuckets; i += kOrderThreads) s_cnt[i] = 0;
+  __syncthreads();
+  for (int t = tid; t < ntiles; t += kOrderThreads) {
+    const int bk = order_bucket(work[t]);
+    if (cached) s_bk[t] = (uint16_t)bk;
+    atomicAdd(&s_cnt[bk], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the buckets, two per thread
+  const uint32_t c0 = s_cnt[2 * tid], c1 = s_cnt[2 * tid + 1];
+  uint32_t incl = c0 + c1;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_wave[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int i = 0; i < wv; ++i) before += s_wave[i];
+  const uint32_t ex = before + incl - (c0 + c1);
+  s_cnt[2 * tid] = ex;
+  s_cnt[2 * tid + 1] = ex + c0;
+  __syncthreads();
+  const uint32_t n = (uint32_t)ntiles, c = (uint32_t)max(ncu, 1);
+  for (int t = tid; t < ntiles; t += kOrderThreads) {
+    const int bk = cached ? (int)s_bk[t] : order_bucket(work[t]);
+    const uint32_t r = atomicAdd(&s_cnt[bk], 1u);
+    if (r >= n) continue;  // never taken: the ranks are 0 .. n - 1
+    const uint32_t k = r / c, i = r - k * c;
+    const uint32_t mk = min(c, n - k * c);
+    order[k * c + ((k & 1) ? mk - 1 - i : i)] = (uint32_t)t;
+  }
+}
+
 // Backward over one tile. g2d is planar [10][nrec]:
 // (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth).
 //
@@ -144,13 +226,17 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
     const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
     const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
-    float* __restrict__ g2d, uint8_t* __restrict__ touched) {
+    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order) {
   __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
-  __shared__ float4 s_red[BATCH][4][4];  // [entry][wave][row]: the three row totals of wave_sum10
+  // [entry][wave * 4 + row]: the three row totals of wave_sum10; the 17th
+  // slot staggers the entries across LDS banks for the cross-wave pass
+  __shared__ float4 s_red[BATCH][17];
   __shared__ uint32_t s_r[BATCH];
   __shared__ uint32_t s_max;
   if (*overflow) return;
-  const int t = blockIdx.x;
+  const uint32_t tu = order ? order[blockIdx.x] : blockIdx.x;
+  if (tu >= (uint32_t)tab.ntiles) return;  // never taken for a permutation
+  const int t = (int)tu;
   const TileCtx tc = tile_ctx(tab, t);
   const uint32_t b = tile_start[t];
   const int64_t roff = tab.r_off[tc.v];
@@ -180,28 +266,52 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
   if (lane == 0) atomicMax(&s_max, wmax);
   __syncthreads();
   const uint32_t maxl = s_max;
+  // Batches walk back: [lo, hi) with hi = maxl, then hi = previous lo. As in
+  // the forward, the next batch's records and the ids of the one after are
+  // loaded into registers while a batch is processed.
+  const int tid = (int)threadIdx.x;
+  float4 ra, rb, rc;
+  uint32_t rn = 0, idn = 0;
+  {
+    const int lo0 = max(0, (int)maxl - BATCH), lo1 = max(0, lo0 - BATCH);
+    if (tid < (int)maxl - lo0) {
+      rn = (uint32_t)(roff + ids[b + lo0 + tid]);
+      ra = rec[3 * (int64_t)rn + 0];
+      rb = rec[3 * (int64_t)rn + 1];
+      rc = rec[3 * (int64_t)rn + 2];
+    }
+    if (tid < lo0 - lo1) idn = ids[b + lo1 + tid];
+  }
   for (int hi = (int)maxl; hi > 0; hi -= BATCH) {
     const int lo = max(0, hi - BATCH);
     const int n = hi - lo;
     __syncthreads();
-    if ((int)threadIdx.x < n) {
-      const uint32_t r = (uint32_t)(roff + ids[b + lo + threadIdx.x]);
-      s_r[threadIdx.x] = r;
-      s_a[threadIdx.x] = rec[3 * (int64_t)r + 0];
-      s_b[threadIdx.x] = rec[3 * (int64_t)r + 1];
-      s_c[threadIdx.x] = rec[3 * (int64_t)r + 2];
+    if (tid < n) {
+      s_r[tid] = rn;
+      s_a[tid] = ra;
+      s_b[tid] = rb;
+      s_c[tid] = rc;
     }
     __syncthreads();
-    for (int jj = n - 1; jj >= 0; --jj) {
+    {
+      const int lo1 = max(0, lo - BATCH), lo2 = max(0, lo1 - BATCH);
+      if (tid < lo - lo1) {
+        rn = (uint32_t)(roff + idn);
+        ra = rec[3 * (int64_t)rn + 0];
+        rb = rec[3 * (int64_t)rn + 1];
+        rc = rec[3 * (int64_t)rn + 2];
+      }
+      if (tid < lo1 - lo2) idn = ids[b + lo2 + tid];
+    }
+    // One entry of the batch; two register sets alternate below so that the
+    // next entry's record is read from LDS while this one is processed.
+    auto entry = [&](int jj, const float4& A, const float4& B, const float4& Cc) {
       const int j = lo + jj;
       float k[3] = {0.f, 0.f, 0.f};
       if ((uint32_t)j < wmax) {  // uniform over the wave
-        const float4 A = s_a[jj];
-        const float4 B = s_b[jj];
-        const float4 Cc = s_c[jj];
         const float dx = A.x - fx, dy = A.y - fy;
-        const float p = gs_power(B.x, B.y, B.z, dx, dy);
-        const float G = __expf(p);
+        const float p = gs_power2(B.x, B.y, B.z, dx, dy);
+        const float G = __builtin_amdgcn_exp2f(p);
         const float araw = A.w * G;
         const float alpha = fminf(GS_ALPHA_MAX, araw);
         const bool valid = (uint32_t)j < nl && p <= 0.f && alpha >= GS_ALPHA_MIN;
@@ -229,10 +339,30 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
           wave_sum10(v, k);
         }
       }
-      if ((lane & 15) == 15) s_red[jj][w][lane >> 4] = make_float4(k[0], k[1], k[2], 0.f);
+      if ((lane & 15) == 15) s_red[jj][w * 4 + (lane >> 4)] = make_float4(k[0], k[1], k[2], 0.f);
+    };
+    float4 A0 = s_a[n - 1], B0 = s_b[n - 1], C0 = s_c[n - 1], A1, B1, C1;
+    int jj = n - 1;
+    for (; jj >= 1; jj -= 2) {
+      A1 = s_a[jj - 1];
+      B1 = s_b[jj - 1];
+      C1 = s_c[jj - 1];
+      entry(jj, A0, B0, C0);
+      if (jj >= 2) {
+        A0 = s_a[jj - 2];
+        B0 = s_b[jj - 2];
+        C0 = s_c[jj - 2];
+      }
+      entry(jj - 1, A1, B1, C1);
     }
+    if (jj == 0) entry(0, A0, B0, C0);
     __syncthreads();
-    for (int q = threadIdx.x; q < n * 10; q += GS_BLOCK) {
+    // The cross-wave pass runs on the waves that load nothing: one counter
+    // tracks both loads and atomics, so the loader waves' wait for the next
+    // records never includes this batch's atomics.
+    constexpr int kLoadThreads = (BATCH + 63) / 64 * 64;
+    static_assert(kLoadThreads < GS_BLOCK, "some wave must be free of loads");
+    for (int q = tid - kLoadThreads; q >= 0 && q < n * 10; q += GS_BLOCK - kLoadThreads) {
       const int jj = q / 10, c = q - jj * 10;
       // moment index -> (row, slot) of wave_sum10's output
       auto mom = [&](int m) {
@@ -241,7 +371,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
         float acc = 0.f;
 #pragma unroll
         for (int ww = 0; ww < 4; ++ww) {
-          const float4 x = s_red[jj][ww][row];
+          const float4 x = s_red[jj][ww * 4 + row];
           acc += sl == 0 ? x.x : (sl == 1 ? x.y : x.z);
         }
         return acc;
@@ -249,9 +379,11 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
       const float o = s_a[jj].w;
       float gval;
       if (c < 2) {
+        // back from base-2 exponent units to the conic
         const float4 B = s_b[jj];
+        const float k1 = B.x * (-2.0f / GS_LOG2E), k2 = B.y * (-1.0f / GS_LOG2E), k3 = B.z * (-2.0f / GS_LOG2E);
         const float s0 = mom(0), s1 = mom(1);
-        gval = c == 0 ? -o * (B.x * s0 + B.y * s1) : -o * (B.y * s0 + B.z * s1);
+        gval = c == 0 ? -o * (k1 * s0 + k2 * s1) : -o * (k2 * s0 + k3 * s1);
       } else if (c == 2 || c == 4) {
         gval = -0.5f * o * mom(c);
       } else if (c == 3) {
@@ -278,7 +410,7 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
 #define GS_FWD(BATCH)                                                                                         \
   GS_LAUNCH(ctx, render_fwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, nullptr, bg[0], bg[1], bg[2], img->color, img->depth, img->mp, img->T,   \
-                     img->n_last, bins->incomplete, truncated_bits)
+                     img->n_last, img->tile_work, bins->incomplete, truncated_bits)
   switch (ctx->render_batch) {
     case 64: GS_FWD(64); break;
     case 128: GS_FWD(128); break;
@@ -290,14 +422,26 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
 
 gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj, const gs_bins* bins,
                                   const gs_image* img, const gs_pixel_grads* pg, const float* bg, float* g2d,
-                                  uint8_t* touched, hipStream_t s) {
+                                  uint8_t* touched, uint32_t* order_ws, hipStream_t s) {
   if (tab.ntiles == 0) return GS_OK;
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
   const float4* rec = (const float4*)proj->rec;
+  const uint32_t* order = nullptr;
+  if (img->tile_work && ctx->tile_order) {
+    if (ctx->n_cu <= 0) {
+      int n = 0;
+      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n <= 0)
+        return gs_fail(ctx, GS_E_HIP, "cannot query the compute-unit count");
+      ctx->n_cu = n;
+    }
+    GS_LAUNCH(ctx, tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, img->tile_work, (int)tab.ntiles,
+              ctx->n_cu, order_ws);
+    order = order_ws;
+  }
 #define GS_BWD(BATCH)                                                                                          \
   GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, \
-                     pg->dT, g2d, touched)
+                     pg->dT, g2d, touched, order)
   switch (ctx->bwd_batch) {
     case 32: GS_BWD(32); break;
     case 128: GS_BWD(128); break;

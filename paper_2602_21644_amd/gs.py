@@ -64,7 +64,7 @@ class Bins(ctypes.Structure):
 
 
 class Image(ctypes.Structure):
-    _fields_ = [(k, c_void_p) for k in ("color", "depth", "mp", "T", "n_last")]
+    _fields_ = [(k, c_void_p) for k in ("color", "depth", "mp", "T", "n_last", "tile_work")]
 
 
 class Target(ctypes.Structure):
@@ -459,8 +459,9 @@ class Pipeline:
         self.img_mp = torch.empty(P, dtype=f32, device=dev)
         self.img_T = torch.empty(P, dtype=f32, device=dev)
         self.img_nlast = torch.empty(P, dtype=i32, device=dev)
+        self.img_tile_work = torch.empty(T, dtype=i32, device=dev)
         self.img = Image(ptr(self.img_color), ptr(self.img_depth), ptr(self.img_mp), ptr(self.img_T),
-                         ptr(self.img_nlast))
+                         ptr(self.img_nlast), ptr(self.img_tile_work))
         self.dC = torch.empty(3 * P, dtype=f32, device=dev)
         self.dD = torch.empty(P, dtype=f32, device=dev)
         self.dM = torch.zeros(P, dtype=f32, device=dev)

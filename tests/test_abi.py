@@ -39,6 +39,12 @@ def test_status_strings_and_param_validation():
         ctx.set_param("bwd_batch", 33)
     with pytest.raises(gs.GSError):
         ctx.set_param("nope", 1)
+    assert ctx.get_param("tile_order") == 1
+    ctx.set_param("tile_order", 0)
+    assert ctx.get_param("tile_order") == 0
+    with pytest.raises(gs.GSError):
+        ctx.set_param("tile_order", 2)
+    assert ctx.get_param("n_cu") == 0  # queried by the first backward on a GPU
 
 
 def test_layout_helpers():

@@ -8,7 +8,8 @@ import pytest
 import torch
 
 from paper_2602_21644_amd import gs, synth
-from tests.gpu_util import assert_grads_close, assert_image_close, image_view, oracle_target, torch_np
+from tests.gpu_util import (assert_grads_close, assert_image_close, bwd_zero_part, image_view, oracle_target,
+                            torch_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -172,4 +173,4 @@ def test_graph_replay_matches_eager(ctx):
             torch.testing.assert_close(grads[k], eager_g[k], rtol=1e-5,
                                        atol=1e-6 * float(eager_g[k].abs().max()) + 1e-30)
         torch.testing.assert_close(pose, eager_pose, rtol=1e-5, atol=1e-5 * float(eager_pose.abs().max()))
-        assert torch.count_nonzero(pipe.ws_bwd) == 0
+        assert torch.count_nonzero(bwd_zero_part(pipe, vb)) == 0
