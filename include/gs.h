@@ -199,7 +199,10 @@ const char* gs_last_error(const gs_ctx* ctx);
  * in gs_render_fwd), "bwd_batch" (32|64|128, gs_render_bwd), "bin_chunk"
  * (256|512|1024|2048 records per binning workgroup), "tile_order" (0|1,
  * default 1: gs_render_bwd launches tiles heaviest first when the image has
- * tile_work), and "timing" (0|1, see gs_ctx_kernel_times). Values outside the
+ * tile_work), "bwd_copies" (1|2|4|8, default 8: accumulators of the per-record
+ * 2D adjoint in the gs_render_bwd scratch, one per group of XCDs, so atomics
+ * from different XCDs do not contend for one address; summed in a fixed
+ * order), and "timing" (0|1, see gs_ctx_kernel_times). Values outside the
  * supported set return GS_E_ARG. */
 gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
 /* Read-only names besides the above: "lds_limit" (LDS bytes per workgroup the
@@ -221,8 +224,9 @@ int64_t gs_pixel_count(const gs_views* views);
 
 enum { GS_OP_BIN_SORT = 1, GS_OP_RENDER_BWD = 2, GS_OP_LOSS = 3, GS_OP_MP_UPDATE = 4, GS_OP_MLP_TRAIN = 5 };
 /* Scratch bytes needed by `op` for this batch; `capacity` is the list capacity
- * of gs_bins (used by GS_OP_BIN_SORT only). For GS_OP_RENDER_BWD the scratch
- * must be zero-filled before its first use; each call leaves it zero-filled. */
+ * of gs_bins (used by GS_OP_BIN_SORT only). For GS_OP_RENDER_BWD the size
+ * grows with the context's "bwd_copies" (query it after setting the knob); the
+ * scratch must be zero-filled before its first use (see gs_render_bwd). */
 gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes);
 
 /* ---------------------------------------------------------------- the path */

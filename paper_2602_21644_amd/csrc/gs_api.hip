@@ -46,6 +46,7 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->bin_chunk = 1024;
   c->timing = 0;
   c->tile_order = 1;
+  c->bwd_copies = 8;
   c->n_cu = 0;
   c->lds_limit = 0;
   c->err[0] = 0;
@@ -108,6 +109,9 @@ gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value) {
     ctx->bwd_batch = (int)value;
   } else if (!strcmp(name, "timing")) {
     ctx->timing = value ? 1 : 0;
+  } else if (!strcmp(name, "bwd_copies")) {
+    if (value != 1 && value != 2 && value != 4 && value != 8) return gs_fail(ctx, GS_E_ARG, "bwd_copies: 1|2|4|8");
+    ctx->bwd_copies = (int)value;
   } else if (!strcmp(name, "tile_order")) {
     if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "tile_order: 0|1");
     ctx->tile_order = (int)value;
@@ -128,6 +132,7 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   else if (!strcmp(name, "bin_chunk")) *value = ctx->bin_chunk;
   else if (!strcmp(name, "timing")) *value = ctx->timing;
   else if (!strcmp(name, "tile_order")) *value = ctx->tile_order;
+  else if (!strcmp(name, "bwd_copies")) *value = ctx->bwd_copies;
   else if (!strcmp(name, "n_cu")) *value = ctx->n_cu;
   else if (!strcmp(name, "lds_limit")) *value = (int64_t)ctx->lds_limit;
   else if (!strcmp(name, "prefix_cap")) *value = bin_prefix_cap();
@@ -193,10 +198,10 @@ static gs_status make_tab(gs_ctx* ctx, const gs_views* vw, ViewTab& tab) {
 struct BwdWs {
   size_t g2d, touched, pose, order, bytes;
 };
-static BwdWs bwd_ws_layout(const ViewTab& tab) {
+static BwdWs bwd_ws_layout(const gs_ctx* ctx, const ViewTab& tab) {
   BwdWs L;
   size_t o = 0;
-  L.g2d = o; o += al256((size_t)tab.nrec * 10 * 4);
+  L.g2d = o; o += al256((size_t)tab.nrec * 10 * 4 * (size_t)ctx->bwd_copies);
   L.touched = o; o += al256((size_t)tab.nrec);
   L.pose = o; o += al256((size_t)tab.nv * bwd_pose_blocks(tab) * 6 * 4 + 4);
   L.order = o; o += al256((size_t)tab.ntiles * 4);
@@ -255,7 +260,7 @@ gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int6
       *bytes = a > b ? a : b;
       return GS_OK;
     }
-    case GS_OP_RENDER_BWD: *bytes = bwd_ws_layout(tab).bytes; return GS_OK;
+    case GS_OP_RENDER_BWD: *bytes = bwd_ws_layout(ctx, tab).bytes; return GS_OK;
     case GS_OP_LOSS: *bytes = al256((size_t)tab.nv * loss_blocks(tab) * 8 + 8); return GS_OK;
     case GS_OP_MP_UPDATE:
       if (tab.nv != 1) return gs_fail(ctx, GS_E_ARG, "mp_update takes one view");
@@ -338,7 +343,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
   if (!gr->pose_only && (!gr->mean || !gr->log_scale || !gr->quat || !gr->opacity_logit || !gr->color))
     return gs_fail(ctx, GS_E_ARG, "gradient arrays NULL");
-  const BwdWs L = bwd_ws_layout(tab);
+  const BwdWs L = bwd_ws_layout(ctx, tab);
   if (!ws || ws_bytes < L.bytes) return gs_fail(ctx, GS_E_ARG, "render_bwd workspace %zu < %zu", ws_bytes, L.bytes);
   char* w = (char*)ws;
   hipStream_t s = (hipStream_t)stream;

@@ -2,7 +2,8 @@
 //
 // One thread per Gaussian (all scenes); it visits every view of its scene,
 // reads the 2D adjoint the tile pass accumulated for that (view, Gaussian)
-// record only when the record was touched, chains it through the projection
+// record (the sum of its per-XCD copies) only when the record was touched,
+// chains it through the projection
 // in float32 and sums the parameter gradients over views in registers. Read
 // records are reset to zero so the scratch stays zero-filled between calls.
 // Pose-twist partials are reduced per block and summed in a fixed order by a
@@ -15,6 +16,8 @@
 
 namespace {
 
+constexpr int kMaxCopies = 8;  // largest "bwd_copies"
+
 __device__ __forceinline__ void block_sum6(float (&x)[6], float* s_tmp /*[4][6]*/, float* out) {
   const int w = threadIdx.x >> 6, lane = __lane_id();
 #pragma unroll
@@ -25,6 +28,38 @@ __device__ __forceinline__ void block_sum6(float (&x)[6], float* s_tmp /*[4][6]*
   if (threadIdx.x < 6) out[threadIdx.x] = s_tmp[threadIdx.x] + s_tmp[6 + threadIdx.x] + s_tmp[12 + threadIdx.x] +
                                           s_tmp[18 + threadIdx.x];
   __syncthreads();
+}
+
+// Adds copies 1 .. copies-1 of every touched record's 2D adjoint into copy 0
+// (in copy order) and resets them to zero. Layout [copy][record][10].
+__global__ __launch_bounds__(GS_BLOCK) void fold_copies_kernel(int64_t M, int copies, float* __restrict__ g2d,
+                                                               const uint8_t* __restrict__ touched) {
+  const int64_t r = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+  if (r >= M || !touched[r]) return;
+  float2* p0 = reinterpret_cast<float2*>(g2d + r * 10);
+  float2 acc[5], t[kMaxCopies - 1][5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) acc[k] = p0[k];
+#pragma unroll
+  for (int x = 1; x < kMaxCopies; ++x)
+    if (x < copies) {
+      const float2* px = reinterpret_cast<const float2*>(g2d + ((int64_t)x * M + r) * 10);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) t[x - 1][k] = px[k];
+    }
+#pragma unroll
+  for (int x = 1; x < kMaxCopies; ++x)
+    if (x < copies) {
+      float2* px = reinterpret_cast<float2*>(g2d + ((int64_t)x * M + r) * 10);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        acc[k].x += t[x - 1][k].x;
+        acc[k].y += t[x - 1][k].y;
+        px[k] = make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) p0[k] = acc[k];
 }
 
 __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
@@ -50,11 +85,17 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
       if (touched[r]) {
         has = true;
         touched[r] = 0;
+        // the fold kernel left the record's sum in copy 0
         float a[10];
+        {
+          float2* px = reinterpret_cast<float2*>(g2d + r * 10);
 #pragma unroll
-        for (int c = 0; c < 10; ++c) {
-          a[c] = g2d[c * M + r];
-          g2d[c * M + r] = 0.f;
+          for (int k = 0; k < 5; ++k) {
+            const float2 t = px[k];
+            a[2 * k] = t.x;
+            a[2 * k + 1] = t.y;
+            px[k] = make_float2(0.f, 0.f);
+          }
         }
         if (!loaded) {
           for (int c = 0; c < 3; ++c) {
@@ -207,6 +248,11 @@ __global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict_
 gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams, const gs_gaussians* g,
                              float* g2d, uint8_t* touched, float* pose_part, gs_grads* gr, hipStream_t s) {
   const int nblk = bwd_pose_blocks(tab);
+  if (ctx->bwd_copies > 1 && tab.nrec > 0) {
+    const int64_t fb = (tab.nrec + GS_BLOCK - 1) / GS_BLOCK;
+    GS_LAUNCH(ctx, fold_copies_kernel, dim3((unsigned)fb), dim3(GS_BLOCK), 0, s, (int64_t)tab.nrec, ctx->bwd_copies,
+              g2d, touched);
+  }
   {
     GS_LAUNCH(ctx, bwd_project_kernel, dim3(nblk), dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale,
                        g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,

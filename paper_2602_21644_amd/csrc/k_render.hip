@@ -210,8 +210,8 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_
   }
 }
 
-// Backward over one tile. g2d is planar [10][nrec]:
-// (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth).
+// Backward over one tile. g2d holds per record ten values
+// (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth), [copy][record][10].
 //
 // Per entry every lane forms ten moment terms of its pixel, with
 // h = dL/d(alpha) * exp(power) where alpha is unclamped, else 0:
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
     const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
     const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
-    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order) {
+    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies) {
   __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
   // [entry][wave * 4 + row]: the three row totals of wave_sum10; the 17th
   // slot staggers the entries across LDS banks for the cross-wave pass
@@ -243,6 +243,12 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
   const int64_t P = tab.npix;
   const int64_t M = tab.nrec;
   const int w = threadIdx.x >> 6, lane = __lane_id();
+  // The 2D adjoint has `copies` accumulators; a workgroup adds into the one of
+  // the XCD it runs on (hardware register XCC_ID). The sums do not depend on
+  // the split; it keeps the atomics of the XCDs on a record apart, which
+  // would otherwise contend for the same addresses.
+  // Layout [copy][record][10].
+  if (copies > 1) g2d += (int64_t)(__builtin_amdgcn_s_getreg((31 << 11) | 20) & (uint32_t)(copies - 1)) * 10 * M;
   const float fx = (float)tc.px, fy = (float)tc.py;
   float T = 1.f, gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gd = 0.f, gm = 0.f, Tbar = 0.f;
   uint32_t nl = 0;
@@ -393,7 +399,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
       }
       if (gval != 0.f) {
         const uint32_t r = s_r[jj];
-        atomicAdd(&g2d[(int64_t)c * M + r], gval);
+        atomicAdd(&g2d[(int64_t)r * 10 + c], gval);
         touched[r] = 1;
       }
     }
@@ -441,7 +447,7 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
 #define GS_BWD(BATCH)                                                                                          \
   GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, \
-                     pg->dT, g2d, touched, order)
+                     pg->dT, g2d, touched, order, ctx->bwd_copies)
   switch (ctx->bwd_batch) {
     case 32: GS_BWD(32); break;
     case 128: GS_BWD(128); break;

@@ -292,7 +292,8 @@ def _host_tile_work(nlast, W, H):
 
 def test_backward_tile_order(ctx, orc):
     """The forward's per-tile work matches its definition; the backward run
-    heaviest-tile-first gives the gradients of the plain tile order."""
+    heaviest-tile-first, and with 1, 2 or 8 accumulator copies, gives the
+    gradients of the plain tile order."""
     g, cam, tcam, g_t, sl = synth.moving_box_scene(8, 30000, 640, 480)
     cam2 = synth.camera(320, 240, cam["T_cw"])
     views, pipe, gt, gst = make_pipeline(ctx, g, [cam, cam2], bg=(0.1, 0.2, 0.3))
@@ -306,16 +307,20 @@ def test_backward_tile_order(ctx, orc):
     pipe.loss_and_grads(tc, td)
     n = synth.n_gaussians(g)
     outs = []
-    for order in (1, 0, 1):
+    # (tile order, accumulator copies); the scratch was sized for 8 copies
+    for order, copies in ((1, 8), (0, 8), (1, 8), (1, 1), (0, 2)):
         ctx.set_param("tile_order", order)
+        ctx.set_param("bwd_copies", copies)
         grads = gs.alloc_grads(n)
         pose = torch.zeros(12, device="cuda")
         pipe.backward(gst, gs.grads_struct(grads, pose))
         torch.cuda.synchronize()
         outs.append((grads, pose))
+        if copies == 8:
+            assert torch.count_nonzero(bwd_zero_part(pipe, views)) == 0
     ctx.set_param("tile_order", 1)
+    ctx.set_param("bwd_copies", 8)
     assert ctx.get_param("n_cu") > 0
-    assert torch.count_nonzero(bwd_zero_part(pipe, views)) == 0
     # only the order of the float atomics differs: agreement far inside the
     # 1e-3 gradient tolerance
     for other in outs[1:]:
