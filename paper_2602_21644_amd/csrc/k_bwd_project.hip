@@ -2,10 +2,10 @@
 //
 // One thread per Gaussian (all scenes); it visits every view of its scene,
 // reads the 2D adjoint the tile pass accumulated for that (view, Gaussian)
-// record (the sum of its per-XCD copies) only when the record was touched,
-// chains it through the projection
-// in float32 and sums the parameter gradients over views in registers. Read
-// records are reset to zero so the scratch stays zero-filled between calls.
+// record (the sum of its per-XCD copies, gathered by the whole wave) only
+// when the record was touched, chains it through the projection in float32
+// and sums the parameter gradients over views in registers. Read records are
+// reset to zero so the scratch stays zero-filled between calls.
 // Pose-twist partials are reduced per block and summed in a fixed order by a
 // second kernel (deterministic).
 //
@@ -30,36 +30,43 @@ __device__ __forceinline__ void block_sum6(float (&x)[6], float* s_tmp /*[4][6]*
   __syncthreads();
 }
 
-// Adds copies 1 .. copies-1 of every touched record's 2D adjoint into copy 0
-// (in copy order) and resets them to zero. Layout [copy][record][10].
-__global__ __launch_bounds__(GS_BLOCK) void fold_copies_kernel(int64_t M, int copies, float* __restrict__ g2d,
-                                                               const uint8_t* __restrict__ touched) {
-  const int64_t r = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
-  if (r >= M || !touched[r]) return;
-  float2* p0 = reinterpret_cast<float2*>(g2d + r * 10);
-  float2 acc[5], t[kMaxCopies - 1][5];
+// The 2D adjoint of record r, summed over its `copies` accumulators (layout
+// [copy][record][10]) and reset to zero, for every lane with hit set. The
+// whole wave gathers one record at a time: lane 5 x + k loads float2 k of
+// copy x, a fixed shuffle tree sums the copies, and the owning lane takes the
+// five sums. Wave-uniform control flow; lanes without a hit get zeros.
+__device__ __forceinline__ void gather_adjoint(bool hit, int64_t r, int64_t M, int copies, float* __restrict__ g2d,
+                                               float (&a)[10]) {
+  const int lane = __lane_id();
 #pragma unroll
-  for (int k = 0; k < 5; ++k) acc[k] = p0[k];
+  for (int c = 0; c < 10; ++c) a[c] = 0.f;
+  uint64_t m = __ballot(hit);
+  const int cp = lane / 5, kk = lane - 5 * (lane / 5);
+  while (m) {
+    const int src = __ffsll((long long)m) - 1;
+    m &= m - 1;
+    const int64_t rs = __shfl(r, src, 64);
+    float2 t = make_float2(0.f, 0.f);
+    if (cp < copies) {
+      float2* p = reinterpret_cast<float2*>(g2d + ((int64_t)cp * M + rs) * 10) + kk;
+      t = *p;
+      *p = make_float2(0.f, 0.f);
+    }
+    // copies x and x + 4, then x + 2, then x + 1 (zeros past `copies`)
 #pragma unroll
-  for (int x = 1; x < kMaxCopies; ++x)
-    if (x < copies) {
-      const float2* px = reinterpret_cast<const float2*>(g2d + ((int64_t)x * M + r) * 10);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) t[x - 1][k] = px[k];
+    for (int off = 20; off >= 5; off >>= 1) {
+      t.x += __shfl_down(t.x, off, 64);
+      t.y += __shfl_down(t.y, off, 64);
     }
 #pragma unroll
-  for (int x = 1; x < kMaxCopies; ++x)
-    if (x < copies) {
-      float2* px = reinterpret_cast<float2*>(g2d + ((int64_t)x * M + r) * 10);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        acc[k].x += t[x - 1][k].x;
-        acc[k].y += t[x - 1][k].y;
-        px[k] = make_float2(0.f, 0.f);
+    for (int k = 0; k < 5; ++k) {
+      const float x = __shfl(t.x, k, 64), y = __shfl(t.y, k, 64);
+      if (lane == src) {
+        a[2 * k] = x;
+        a[2 * k + 1] = y;
       }
     }
-#pragma unroll
-  for (int k = 0; k < 5; ++k) p0[k] = acc[k];
+  }
 }
 
 __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
@@ -67,7 +74,7 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
     const float* __restrict__ log_scale, const float* __restrict__ quat, const float* __restrict__ opl,
     float* __restrict__ g2d, uint8_t* __restrict__ touched, float* __restrict__ d_mean,
     float* __restrict__ d_ls, float* __restrict__ d_quat, float* __restrict__ d_opl, float* __restrict__ d_color,
-    float* __restrict__ pose_part, int pose_only, int accumulate) {
+    float* __restrict__ pose_part, int pose_only, int accumulate, int copies) {
   __shared__ float s_tmp[24];
   const int64_t gk = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
   const int64_t N = tab.ng;
@@ -80,23 +87,15 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
     float pv[6] = {0, 0, 0, 0, 0, 0};
     bool has = false;
     const int64_t k = gk - tab.g_off[v];
-    if (valid && k >= 0 && k < tab.n[v]) {
-      const int64_t r = tab.r_off[v] + k;
-      if (touched[r]) {
+    const bool in = valid && k >= 0 && k < tab.n[v];
+    const int64_t r = in ? tab.r_off[v] + k : 0;
+    const bool hit = in && touched[r] != 0;
+    float a[10];
+    gather_adjoint(hit, r, M, copies, g2d, a);
+    {
+      if (hit) {
         has = true;
         touched[r] = 0;
-        // the fold kernel left the record's sum in copy 0
-        float a[10];
-        {
-          float2* px = reinterpret_cast<float2*>(g2d + r * 10);
-#pragma unroll
-          for (int k = 0; k < 5; ++k) {
-            const float2 t = px[k];
-            a[2 * k] = t.x;
-            a[2 * k + 1] = t.y;
-            px[k] = make_float2(0.f, 0.f);
-          }
-        }
         if (!loaded) {
           for (int c = 0; c < 3; ++c) {
             m[c] = mean[c * N + gk];
@@ -216,30 +215,43 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
 // Sums the per-block pose partials of every view in a fixed order (one
 // workgroup, float64) and resets them to zero, so the scratch stays
 // zero-filled.
-__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict__ part, int nblk, int nv,
-                                                              float* __restrict__ pose, int accumulate) {
-  __shared__ double s_red[4][6];
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  for (int v = 0; v < nv; ++v) {
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) {
-      float* q = part + ((int64_t)v * nblk + b) * 6;
-      for (int c = 0; c < 6; ++c) {
-        acc[c] += (double)q[c];
-        q[c] = 0.f;
-      }
+constexpr int kFinalThreads = 1024;
+__global__ __launch_bounds__(kFinalThreads) void pose_final_kernel(float* __restrict__ part, int nblk,
+                                                                   float* __restrict__ pose, int accumulate) {
+  __shared__ double s_red[kFinalThreads / 64][6];
+  const int v = blockIdx.x, lane = __lane_id(), w = threadIdx.x >> 6;
+  float* base = part + (int64_t)v * nblk * 6;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  // four rows per thread in flight at once; rows summed in a fixed order
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += 4 * kFinalThreads) {
+    float q[4][6];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = b0 + i * kFinalThreads;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) q[i][c] = b < nblk ? base[(int64_t)b * 6 + c] : 0.f;
     }
-    for (int c = 0; c < 6; ++c) {
-      acc[c] = wave_sum_to_lane63_d(acc[c]);
-      if (lane == 63) s_red[w][c] = acc[c];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = b0 + i * kFinalThreads;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] += (double)q[i][c];
+      if (b < nblk)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) base[(int64_t)b * 6 + c] = 0.f;
     }
-    __syncthreads();
-    if (threadIdx.x < 6 && pose) {
-      const int c = threadIdx.x;
-      const double t = s_red[0][c] + s_red[1][c] + s_red[2][c] + s_red[3][c];
-      pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + t : t);
-    }
-    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    acc[c] = wave_sum_to_lane63_d(acc[c]);
+    if (lane == 63) s_red[w][c] = acc[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6 && pose) {
+    const int c = threadIdx.x;
+    double t = 0.0;
+    for (int i = 0; i < kFinalThreads / 64; ++i) t += s_red[i][c];
+    pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + t : t);
   }
 }
 
@@ -248,17 +260,12 @@ __global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict_
 gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams, const gs_gaussians* g,
                              float* g2d, uint8_t* touched, float* pose_part, gs_grads* gr, hipStream_t s) {
   const int nblk = bwd_pose_blocks(tab);
-  if (ctx->bwd_copies > 1 && tab.nrec > 0) {
-    const int64_t fb = (tab.nrec + GS_BLOCK - 1) / GS_BLOCK;
-    GS_LAUNCH(ctx, fold_copies_kernel, dim3((unsigned)fb), dim3(GS_BLOCK), 0, s, (int64_t)tab.nrec, ctx->bwd_copies,
-              g2d, touched);
-  }
   {
     GS_LAUNCH(ctx, bwd_project_kernel, dim3(nblk), dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale,
                        g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
-                       gr->color, pose_part, gr->pose_only, gr->accumulate);
+                       gr->color, pose_part, gr->pose_only, gr->accumulate, ctx->bwd_copies);
   }
-  GS_LAUNCH(ctx, pose_final_kernel, dim3(1), dim3(GS_BLOCK), 0, s, pose_part, nblk, tab.nv, gr->pose,
+  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(kFinalThreads), 0, s, pose_part, nblk, gr->pose,
             gr->accumulate);
   return gs_check_launch(ctx, "render_bwd_project");
 }
