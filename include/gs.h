@@ -202,8 +202,10 @@ const char* gs_last_error(const gs_ctx* ctx);
  * tile_work), "bwd_copies" (1|2|4|8, default 8: accumulators of the per-record
  * 2D adjoint in the gs_render_bwd scratch, one per group of XCDs, so atomics
  * from different XCDs do not contend for one address; summed in a fixed
- * order), and "timing" (0|1, see gs_ctx_kernel_times). Values outside the
- * supported set return GS_E_ARG. */
+ * order), "wave_cull" (0|1, default 1: in gs_render_fwd each 64-pixel wave
+ * skips the entries whose alpha >= 1/255 region misses its 16x4 pixel strip;
+ * the outputs are bit-identical either way), and "timing" (0|1, see
+ * gs_ctx_kernel_times). Values outside the supported set return GS_E_ARG. */
 gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
 /* Read-only names besides the above: "lds_limit" (LDS bytes per workgroup the
  * context uses), "prefix_cap" (selected records per view the prefix binning

@@ -47,6 +47,7 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->timing = 0;
   c->tile_order = 1;
   c->bwd_copies = 8;
+  c->wave_cull = 1;
   c->n_cu = 0;
   c->lds_limit = 0;
   c->err[0] = 0;
@@ -112,6 +113,9 @@ gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value) {
   } else if (!strcmp(name, "bwd_copies")) {
     if (value != 1 && value != 2 && value != 4 && value != 8) return gs_fail(ctx, GS_E_ARG, "bwd_copies: 1|2|4|8");
     ctx->bwd_copies = (int)value;
+  } else if (!strcmp(name, "wave_cull")) {
+    if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "wave_cull: 0|1");
+    ctx->wave_cull = (int)value;
   } else if (!strcmp(name, "tile_order")) {
     if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "tile_order: 0|1");
     ctx->tile_order = (int)value;
@@ -132,6 +136,7 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   else if (!strcmp(name, "bin_chunk")) *value = ctx->bin_chunk;
   else if (!strcmp(name, "timing")) *value = ctx->timing;
   else if (!strcmp(name, "tile_order")) *value = ctx->tile_order;
+  else if (!strcmp(name, "wave_cull")) *value = ctx->wave_cull;
   else if (!strcmp(name, "bwd_copies")) *value = ctx->bwd_copies;
   else if (!strcmp(name, "n_cu")) *value = ctx->n_cu;
   else if (!strcmp(name, "lds_limit")) *value = (int64_t)ctx->lds_limit;

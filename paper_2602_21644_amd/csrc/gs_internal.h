@@ -170,6 +170,7 @@ struct gs_ctx {
   int timing;                    // 1: bracket every launch with HIP events
   int tile_order;                // 1: backward tiles heaviest first when tile_work is given
   int bwd_copies;                // accumulators of the backward's 2D adjoint (1, 2, 4, 8)
+  int wave_cull;                 // 1: each wave skips the entries that cannot reach its 16x4 strip
   int n_cu;                      // compute units of the device (0: not queried yet)
   size_t lds_limit;              // LDS per workgroup usable by the binning scatter (0: not queried)
   std::vector<GsTimer> pending;  // launches whose events are not read yet

@@ -32,18 +32,54 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewTab& tab, int t) {
   return c;
 }
 
+// Which of a tile's four 16x4 pixel strips (wave w: rows 4w .. 4w+3) an entry
+// can composite in: bit w clear only when no pixel of the strip reaches
+// alpha >= 1/255. The region where o 2^p >= 1/255, p = c1 dx^2 + c2 dx dy +
+// c3 dy^2 (the record's base-2 conic), is the ellipse Q <= tau with
+// Q = -p and tau = log2(255 o); its bounding box has half-widths
+// sqrt(4 c tau / D) and sqrt(4 a tau / D), (a, b, c) = -(c1, c2, c3),
+// D = 4ac - b^2. The box is widened by 0.1% and one pixel against rounding;
+// degenerate or non-finite cases keep every strip, o < 1/255 none.
+__device__ __forceinline__ uint32_t strip_mask(const float4& A, const float4& B, int x0, int y0) {
+  const float tau = __log2f(255.0f * A.w);
+  if (tau < 0.f) return 0u;
+  const float a = -B.x, bq = -B.y, c = -B.z;
+  const float D = 4.0f * a * c - bq * bq;
+  if (!(D > 0.f) || !(tau < 1e30f)) return 0xFu;
+  const float rx = sqrtf(4.0f * c * tau / D) * 1.001f + 1.0f;
+  const float ry = sqrtf(4.0f * a * tau / D) * 1.001f + 1.0f;
+  if (!(rx < 1e30f) || !(ry < 1e30f) || !(fabsf(A.x) < 1e30f) || !(fabsf(A.y) < 1e30f)) return 0xFu;
+  if (A.x + rx < (float)x0 || A.x - rx > (float)(x0 + 15)) return 0u;
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const float ya = (float)(y0 + 4 * w), yb = (float)(y0 + 4 * w + 3);
+    if (!(A.y + ry < ya || A.y - ry > yb)) m |= 1u << w;
+  }
+  return m;
+}
+
 template <int BATCH>
 __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
     ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, const int32_t* __restrict__ trunc,
     float bg0, float bg1, float bg2, float* __restrict__ outC, float* __restrict__ outD, float* __restrict__ outM,
     float* __restrict__ outT, uint32_t* __restrict__ nlast, uint32_t* __restrict__ tile_work,
-    int32_t* __restrict__ incomplete, int truncated_bits) {
-  __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
+    int32_t* __restrict__ incomplete, int truncated_bits, int cull) {
+  // slot BATCH is a zero-opacity entry that pads a wave's last group of four
+  __shared__ float4 s_a[BATCH + 1], s_b[BATCH + 1], s_c[BATCH + 1];
+  __shared__ uint8_t s_mask[BATCH];
   __shared__ uint32_t s_wmax[GS_BLOCK / 64];
   if (*overflow) return;
   const int t = blockIdx.x;
   const TileCtx tc = tile_ctx(tab, t);
+  const int w = threadIdx.x >> 6, lane = __lane_id();
+  if (threadIdx.x == 0) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    s_a[BATCH] = z;
+    s_b[BATCH] = z;
+    s_c[BATCH] = z;
+  }
   const uint32_t b = tile_start[t], e = tile_start[t + 1];
   const int64_t roff = tab.r_off[tc.v];
   const float fx = (float)tc.px, fy = (float)tc.py;
@@ -77,6 +113,9 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
       s_a[threadIdx.x] = ra;
       s_b[threadIdx.x] = rb;
       s_c[threadIdx.x] = rc;
+      s_mask[threadIdx.x] = base + threadIdx.x >= e ? 0u
+                            : cull ? (uint8_t)strip_mask(ra, rb, tc.tx * GS_TILE, tc.ty * GS_TILE)
+                                   : (uint8_t)0xF;
     }
     __syncthreads();
     if (loader) {
@@ -93,31 +132,48 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
     if (__any(!done)) {  // uniform over the wave
       const int n = (int)min((uint32_t)BATCH, e - base);
       const uint32_t idx0 = base - b + 1;
-      // branch-free per entry: every lane evaluates, the predicates select;
-      // groups of four, the early exit tested once per group
-      for (int j0 = 0; j0 < n; j0 += 4) {
+      // The wave walks only the entries whose mask has its strip, in list
+      // order, taken 64 at a time from a ballot; branch-free per entry (every
+      // lane evaluates, the predicates select), groups of four padded with
+      // the zero entry, the early exit tested once per group.
+      bool all_done = false;
+      for (int c0 = 0; c0 < n && !all_done; c0 += 64) {
+        const int jl = c0 + lane;
+        uint64_t ball = __ballot(jl < n && ((s_mask[jl < BATCH ? jl : 0] >> w) & 1u));
+        while (ball) {
+          int js[4];
 #pragma unroll
-      for (int j = j0; j < j0 + 4; ++j) {
-        const float4 A = s_a[j];
-        const float4 B = s_b[j];
-        const float4 Cc = s_c[j];
-        const float p = gs_power2(B.x, B.y, B.z, A.x - fx, A.y - fy);
-        const float alpha = fminf(GS_ALPHA_MAX, A.w * __builtin_amdgcn_exp2f(p));
-        const bool ok = !done && p <= 0.f && alpha >= GS_ALPHA_MIN;
-        const float Tn = T * (1.0f - alpha);
-        const bool stop = ok && Tn < GS_T_MIN;
-        const bool add = ok && !stop;
-        done = done || stop;
-        const float wgt = add ? alpha * T : 0.f;
-        C0 += wgt * Cc.x;
-        C1 += wgt * Cc.y;
-        C2 += wgt * Cc.z;
-        D += wgt * A.z;
-        Mm += wgt * B.w;
-        T = add ? Tn : T;
-        last = add ? idx0 + j : last;
-      }
-      if (__all(done)) break;
+          for (int u = 0; u < 4; ++u) {
+            js[u] = ball ? c0 + __ffsll((long long)ball) - 1 : BATCH;
+            ball &= ball - 1;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = js[u];
+            const float4 A = s_a[j];
+            const float4 B = s_b[j];
+            const float4 Cc = s_c[j];
+            const float p = gs_power2(B.x, B.y, B.z, A.x - fx, A.y - fy);
+            const float alpha = fminf(GS_ALPHA_MAX, A.w * __builtin_amdgcn_exp2f(p));
+            const bool ok = !done && p <= 0.f && alpha >= GS_ALPHA_MIN;
+            const float Tn = T * (1.0f - alpha);
+            const bool stop = ok && Tn < GS_T_MIN;
+            const bool add = ok && !stop;
+            done = done || stop;
+            const float wgt = add ? alpha * T : 0.f;
+            C0 += wgt * Cc.x;
+            C1 += wgt * Cc.y;
+            C2 += wgt * Cc.z;
+            D += wgt * A.z;
+            Mm += wgt * B.w;
+            T = add ? Tn : T;
+            last = add ? idx0 + j : last;
+          }
+          if (__all(done)) {
+            all_done = true;
+            break;
+          }
+        }
       }
     }
   }
@@ -416,7 +472,7 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
 #define GS_FWD(BATCH)                                                                                         \
   GS_LAUNCH(ctx, render_fwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, nullptr, bg[0], bg[1], bg[2], img->color, img->depth, img->mp, img->T,   \
-                     img->n_last, img->tile_work, bins->incomplete, truncated_bits)
+                     img->n_last, img->tile_work, bins->incomplete, truncated_bits, ctx->wave_cull)
   switch (ctx->render_batch) {
     case 64: GS_FWD(64); break;
     case 128: GS_FWD(128); break;

@@ -330,6 +330,41 @@ def test_backward_tile_order(ctx, orc):
     assert float(outs[0][0]["color"].abs().sum()) > 0
 
 
+@pytest.mark.parametrize("seed,n,W,H,max_rank", [(21, 20000, 640, 480, 0), (22, 200000, 320, 240, 8192),
+                                                 (23, 3000, 100, 75, 0)])
+def test_wave_cull_exact(ctx, seed, n, W, H, max_rank):
+    """Skipping, per 16x4 pixel strip, the entries whose alpha >= 1/255 region
+    misses the strip leaves every output bit-identical; the gradients agree
+    up to the order of their float atomics."""
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(seed, n, W, H)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], max_rank=max_rank, bg=(0.2, 0.1, 0.0))
+    outs, grads = [], []
+    tc = td = None
+    for cull in (1, 0, 1):
+        ctx.set_param("wave_cull", cull)
+        pipe.forward(gst)
+        if tc is None:
+            tc, td = (pipe.img_color * 0.8).contiguous(), (pipe.img_depth * 1.1).contiguous()
+        pipe.loss_and_grads(tc, td)
+        gr = gs.alloc_grads(n)
+        pose = torch.zeros(6, device="cuda")
+        pipe.backward(gst, gs.grads_struct(gr, pose))
+        torch.cuda.synchronize()
+        outs.append([t.clone() for t in (pipe.img_color, pipe.img_depth, pipe.img_mp, pipe.img_T, pipe.img_nlast,
+                                         pipe.img_tile_work)])
+        grads.append((gr, pose))
+    ctx.set_param("wave_cull", 1)
+    over, n_inst, inc = pipe.check()
+    assert not over and n_inst > 0
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert torch.equal(a, b)
+    for other in grads[1:]:
+        for k in grads[0][0]:
+            assert_grads_close(torch_np(other[0][k]), torch_np(grads[0][0][k]), rel=1e-4, name=k)
+        assert_grads_close(torch_np(other[1]), torch_np(grads[0][1]), rel=1e-4, name="pose")
+
+
 def test_max_rank_prefix_lists(ctx, orc):
     """Binning only the R nearest records gives exact prefixes of the full
     lists; when every tile saturates inside them the image is identical."""
