@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--max-rank", type=int, default=-1,
                     help="prefix rank for binning (-1: smallest power of two >= 256 that is exact; 0: full lists)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch knobs")
+    ap.add_argument("--knobs", default="",
+                    help="comma-separated name=value context knobs set before tuning (e.g. bwd_batch=64)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-window, uneven-batch and learned-MP forms reported beside the step")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -147,6 +149,9 @@ def main():
         R, n_inst = optim.choose_rank(ctx, views, gst, a.n)
     log(f"[bench] prefix rank {R} ({'full lists' if R == 0 else 'prefix lists'}), {n_inst} list entries")
     knobs = None
+    for kv in filter(None, a.knobs.split(",")):
+        name, val = kv.split("=")
+        ctx.set_param(name.strip(), int(val))
     if not a.no_tune:
         import tempfile
         ent = tune.tune(ctx, views, gt, tc, td, cache=os.path.join(tempfile.gettempdir(), "gs_bench_tune.json"),

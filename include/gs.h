@@ -204,8 +204,11 @@ const char* gs_last_error(const gs_ctx* ctx);
  * from different XCDs do not contend for one address; summed in a fixed
  * order), "wave_cull" (0|1, default 1: in gs_render_fwd each 64-pixel wave
  * skips the entries whose alpha >= 1/255 region misses its 16x4 pixel strip;
- * the outputs are bit-identical either way), and "timing" (0|1, see
- * gs_ctx_kernel_times). Values outside the supported set return GS_E_ARG. */
+ * the outputs are bit-identical either way), "bwd_mfma" (0|1, default 0: 1
+ * forms the backward's per-entry pixel sums with FP32 matrix instructions
+ * instead of wave reductions; same gradients up to summation order), and
+ * "timing" (0|1, see gs_ctx_kernel_times). Values outside the supported set
+ * return GS_E_ARG. */
 gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
 /* Read-only names besides the above: "lds_limit" (LDS bytes per workgroup the
  * context uses), "prefix_cap" (selected records per view the prefix binning

@@ -48,6 +48,7 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->tile_order = 1;
   c->bwd_copies = 8;
   c->wave_cull = 1;
+  c->bwd_mfma = 0;
   c->n_cu = 0;
   c->lds_limit = 0;
   c->err[0] = 0;
@@ -113,6 +114,9 @@ gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value) {
   } else if (!strcmp(name, "bwd_copies")) {
     if (value != 1 && value != 2 && value != 4 && value != 8) return gs_fail(ctx, GS_E_ARG, "bwd_copies: 1|2|4|8");
     ctx->bwd_copies = (int)value;
+  } else if (!strcmp(name, "bwd_mfma")) {
+    if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "bwd_mfma: 0|1");
+    ctx->bwd_mfma = (int)value;
   } else if (!strcmp(name, "wave_cull")) {
     if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "wave_cull: 0|1");
     ctx->wave_cull = (int)value;
@@ -137,6 +141,7 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   else if (!strcmp(name, "timing")) *value = ctx->timing;
   else if (!strcmp(name, "tile_order")) *value = ctx->tile_order;
   else if (!strcmp(name, "wave_cull")) *value = ctx->wave_cull;
+  else if (!strcmp(name, "bwd_mfma")) *value = ctx->bwd_mfma;
   else if (!strcmp(name, "bwd_copies")) *value = ctx->bwd_copies;
   else if (!strcmp(name, "n_cu")) *value = ctx->n_cu;
   else if (!strcmp(name, "lds_limit")) *value = (int64_t)ctx->lds_limit;

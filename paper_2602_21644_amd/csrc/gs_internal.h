@@ -117,32 +117,6 @@ __device__ __forceinline__ void wave_sum10(const float v[10], float k[3]) {
   for (int i = 0; i < 3; ++i) k[i] += dpp_mov<0x118>(k[i]);
 }
 
-// The same for twenty values: the totals land in lane 15 of every row r as
-// k[0..4]:  row 0: (v0, v2, .., v8)    row 1: (v1, v3, .., v9)
-//           row 2: (v10, v12, .., v18) row 3: (v11, v13, .., v19)
-__device__ __forceinline__ void wave_sum20(const float v[20], float k[5]) {
-  float h[10];
-#pragma unroll
-  for (int i = 0; i < 10; ++i) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 10]), false, false);
-    h[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const auto r =
-        __builtin_amdgcn_permlane16_swap(__float_as_uint(h[2 * i]), __float_as_uint(h[2 * i + 1]), false, false);
-    k[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-#pragma unroll
-  for (int i = 0; i < 5; ++i) k[i] += dpp_mov<0x111>(k[i]);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) k[i] += dpp_mov<0x112>(k[i]);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) k[i] += dpp_mov<0x114>(k[i]);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) k[i] += dpp_mov<0x118>(k[i]);
-}
-
 __device__ __forceinline__ double wave_sum_to_lane63_d(double x) {
   // exact-order-independent enough for FP64 partials: butterfly via shuffles
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -171,6 +145,7 @@ struct gs_ctx {
   int tile_order;                // 1: backward tiles heaviest first when tile_work is given
   int bwd_copies;                // accumulators of the backward's 2D adjoint (1, 2, 4, 8)
   int wave_cull;                 // 1: each wave skips the entries that cannot reach its 16x4 strip
+  int bwd_mfma;                  // 1: the backward forms its per-entry sums on the matrix cores
   int n_cu;                      // compute units of the device (0: not queried yet)
   size_t lds_limit;              // LDS per workgroup usable by the binning scatter (0: not queried)
   std::vector<GsTimer> pending;  // launches whose events are not read yet

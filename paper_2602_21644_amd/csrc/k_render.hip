@@ -462,6 +462,235 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
   }
 }
 
+
+// The same backward with the per-entry moment sums on the matrix cores.
+//
+// The ten sums over a wave's 64 pixels are a product (entries x pixels) x
+// (pixels x features): with tile-local pixel coordinates (lx, ly) and
+// d = u - pixel = (ux_l - lx, uy_l - ly), u_l the entry's tile-local mean,
+//   sum h d_x   = ux_l S0 - S1,   sum h d_y = uy_l S0 - S2,
+//   sum h d_x^2 = ux_l^2 S0 - 2 ux_l S1 + S3,
+//   sum h d_x d_y = ux_l uy_l S0 - ux_l S2 - uy_l S1 + S4,
+//   sum h d_y^2 = uy_l^2 S0 - 2 uy_l S2 + S5,
+// where S = sum_p h_p (1, lx, ly, lx^2, lx ly, ly^2); the colour and depth
+// sums are sum_p w_p (g_r, g_g, g_b, g_D). Each wave takes the entries in
+// groups of 16: every lane computes h and w of its pixel for the 16 entries
+// (the transmittance recursion is unchanged), h goes to an LDS tile [entry]
+// [pixel], and 16 v_mfma_f32_16x16x4f32 steps multiply it by the per-pixel
+// features (step s, lane group k: pixel 16k + s of the wave); then w replaces
+// h in the same tile for the colour and depth features. The accumulator
+// holds D[entry][feature]; the cross-wave pass adds the four waves, expands
+// the sums into the moments about u and applies opacity and conic as before.
+typedef float gs_floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kGroup = 16;
+constexpr int kRow = 64 + 4;  // pixels per LDS row, padded across banks
+
+template <int BATCH>
+__global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
+    ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
+    const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
+    const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
+    const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
+    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies) {
+  static_assert(BATCH % kGroup == 0, "a batch holds whole groups");
+  __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
+  __shared__ uint32_t s_r[BATCH];
+  __shared__ float s_t[GS_BLOCK / 64][kGroup][kRow];  // per wave: h, then w, of a group
+  __shared__ float4 s_dm[BATCH][10];                  // per entry and sum: the four waves' values
+  __shared__ uint32_t s_max;
+  if (*overflow) return;
+  const uint32_t tu = order ? order[blockIdx.x] : blockIdx.x;
+  if (tu >= (uint32_t)tab.ntiles) return;  // never taken for a permutation
+  const int t = (int)tu;
+  const TileCtx tc = tile_ctx(tab, t);
+  const uint32_t b = tile_start[t];
+  const int64_t roff = tab.r_off[tc.v];
+  const int64_t P = tab.npix;
+  const int64_t M = tab.nrec;
+  const int w = threadIdx.x >> 6, lane = __lane_id();
+  // accumulator of the XCD the workgroup runs on, as in render_bwd_kernel
+  if (copies > 1) g2d += (int64_t)(__builtin_amdgcn_s_getreg((31 << 11) | 20) & (uint32_t)(copies - 1)) * 10 * M;
+  const float fx = (float)tc.px, fy = (float)tc.py;
+  const float x0 = (float)(tc.tx * GS_TILE), y0 = (float)(tc.ty * GS_TILE);
+  float T = 1.f, gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gd = 0.f, gm = 0.f, Tbar = 0.f;
+  uint32_t nl = 0;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  if (tc.inside) {
+    T = imgT[tc.pix];
+    nl = nlast[tc.pix];
+    gc0 = dC[tc.pix];
+    gc1 = dC[P + tc.pix];
+    gc2 = dC[2 * P + tc.pix];
+    gd = dD[tc.pix];
+    gm = dM ? dM[tc.pix] : 0.f;
+    const float gt = dT ? dT[tc.pix] : 0.f;
+    Tbar = gt + gc0 * bg0 + gc1 * bg1 + gc2 * bg2;
+  }
+  uint32_t wmax = nl;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, o, 64));
+  if (lane == 0) atomicMax(&s_max, wmax);
+  // B operands of the matrix steps: lane (k = lane >> 4, j = lane & 15) at
+  // step s supplies feature j of the wave's pixel 16k + s (lx = s, ly = 4w + k)
+  const int mk = lane >> 4, mj = lane & 15;
+  float bphi[kGroup], bpsi[kGroup];
+  {
+    const float ly = (float)(4 * w + mk);
+#pragma unroll
+    for (int st = 0; st < kGroup; ++st) {
+      const float lx = (float)st;
+      bphi[st] = mj == 0 ? 1.f : mj == 1 ? lx : mj == 2 ? ly : mj == 3 ? lx * lx : mj == 4 ? lx * ly
+                 : mj == 5 ? ly * ly : 0.f;
+      const int src = 16 * mk + st;
+      const float q0 = __shfl(gc0, src, 64), q1 = __shfl(gc1, src, 64), q2 = __shfl(gc2, src, 64),
+                  q3 = __shfl(gd, src, 64);
+      bpsi[st] = mj == 6 ? q0 : mj == 7 ? q1 : mj == 8 ? q2 : mj == 9 ? q3 : 0.f;
+    }
+  }
+  __syncthreads();
+  const uint32_t maxl = s_max;
+  const int tid = (int)threadIdx.x;
+  float4 ra, rb, rc;
+  uint32_t rn = 0, idn = 0;
+  {
+    const int lo0 = max(0, (int)maxl - BATCH), lo1 = max(0, lo0 - BATCH);
+    if (tid < (int)maxl - lo0) {
+      rn = (uint32_t)(roff + ids[b + lo0 + tid]);
+      ra = rec[3 * (int64_t)rn + 0];
+      rb = rec[3 * (int64_t)rn + 1];
+      rc = rec[3 * (int64_t)rn + 2];
+    }
+    if (tid < lo0 - lo1) idn = ids[b + lo1 + tid];
+  }
+  float* rowp = &s_t[w][0][0];
+  for (int hi = (int)maxl; hi > 0; hi -= BATCH) {
+    const int lo = max(0, hi - BATCH);
+    const int n = hi - lo;
+    __syncthreads();
+    if (tid < n) {
+      s_r[tid] = rn;
+      s_a[tid] = ra;
+      s_b[tid] = rb;
+      s_c[tid] = rc;
+    }
+    __syncthreads();
+    {
+      const int lo1 = max(0, lo - BATCH), lo2 = max(0, lo1 - BATCH);
+      if (tid < lo - lo1) {
+        rn = (uint32_t)(roff + idn);
+        ra = rec[3 * (int64_t)rn + 0];
+        rb = rec[3 * (int64_t)rn + 1];
+        rc = rec[3 * (int64_t)rn + 2];
+      }
+      if (tid < lo1 - lo2) idn = ids[b + lo2 + tid];
+    }
+    for (int g0 = ((n - 1) / kGroup) * kGroup; g0 >= 0; g0 -= kGroup) {
+      float wr[kGroup];
+      bool any = false;  // some entry of the group had a valid pixel in this wave
+#pragma unroll
+      for (int e = kGroup - 1; e >= 0; --e) {
+        const int jj = g0 + e;
+        const int j = lo + jj;
+        float hv = 0.f, wv = 0.f;
+        if (jj < n && (uint32_t)j < wmax) {  // uniform over the wave
+          const float4 A = s_a[jj];
+          const float4 B = s_b[jj];
+          const float dx = A.x - fx, dy = A.y - fy;
+          const float p = gs_power2(B.x, B.y, B.z, dx, dy);
+          const float G = __builtin_amdgcn_exp2f(p);
+          const float araw = A.w * G;
+          const float alpha = fminf(GS_ALPHA_MAX, araw);
+          const bool valid = (uint32_t)j < nl && p <= 0.f && alpha >= GS_ALPHA_MIN;
+          if (__ballot(valid)) {  // uniform
+            any = true;
+            const float4 Cc = s_c[jj];
+            const float a = valid ? alpha : 0.f;
+            const float one_m = 1.0f - a;
+            const float Tj = T * __builtin_amdgcn_rcpf(one_m);
+            const float vdot = gc0 * Cc.x + gc1 * Cc.y + gc2 * Cc.z + gd * A.z + gm * B.w;
+            const float abar = Tj * (vdot - Tbar);
+            wv = a * Tj;
+            hv = (valid && araw < GS_ALPHA_MAX) ? abar * G : 0.f;
+            Tbar = vdot * a + Tbar * one_m;
+            T = Tj;
+          }
+        }
+        rowp[e * kRow + lane] = hv;
+        wr[e] = wv;
+      }
+      // D[entry][feature] over the wave's pixels (zero without a valid entry)
+      gs_floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      const float* arow = rowp + mj * kRow + 16 * mk;
+      if (any) {
+#pragma unroll
+      for (int q = 0; q < kGroup / 4; ++q) {
+        const float4 av = *reinterpret_cast<const float4*>(arow + 4 * q);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bphi[4 * q + 0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bphi[4 * q + 1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bphi[4 * q + 2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bphi[4 * q + 3], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < kGroup; ++e) rowp[e * kRow + lane] = wr[e];
+#pragma unroll
+      for (int q = 0; q < kGroup / 4; ++q) {
+        const float4 av = *reinterpret_cast<const float4*>(arow + 4 * q);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bpsi[4 * q + 0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bpsi[4 * q + 1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bpsi[4 * q + 2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bpsi[4 * q + 3], acc, 0, 0, 0);
+      }
+      }
+      // lane holds D[4k + r][j]: entry g0 + 4k + r, feature j
+      if (mj < 10) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int jj = g0 + 4 * mk + r;
+          if (jj < n) reinterpret_cast<float*>(&s_dm[jj][mj])[w] = acc[r];
+        }
+      }
+    }
+    __syncthreads();
+    // cross-wave pass on the waves that load nothing (see render_bwd_kernel)
+    constexpr int kLoadThreads = (BATCH + 63) / 64 * 64;
+    static_assert(kLoadThreads < GS_BLOCK, "some wave must be free of loads");
+    for (int q = tid - kLoadThreads; q >= 0 && q < n * 10; q += GS_BLOCK - kLoadThreads) {
+      const int jj = q / 10, c = q - jj * 10;
+      auto sm = [&](int f) {
+        const float4 v = s_dm[jj][f];
+        return (v.x + v.y) + (v.z + v.w);
+      };
+      const float4 A = s_a[jj];
+      const float o = A.w;
+      float gval;
+      if (c < 5) {
+        const float ux = A.x - x0, uy = A.y - y0;
+        const float S0 = sm(0), S1 = sm(1), S2 = sm(2);
+        if (c < 2) {
+          const float4 B = s_b[jj];
+          const float k1 = B.x * (-2.0f / GS_LOG2E), k2 = B.y * (-1.0f / GS_LOG2E), k3 = B.z * (-2.0f / GS_LOG2E);
+          const float mx = ux * S0 - S1, my = uy * S0 - S2;
+          gval = c == 0 ? -o * (k1 * mx + k2 * my) : -o * (k2 * mx + k3 * my);
+        } else if (c == 2) {
+          gval = -0.5f * o * (ux * (ux * S0 - 2.0f * S1) + sm(3));
+        } else if (c == 3) {
+          gval = -o * (ux * (uy * S0 - S2) - uy * S1 + sm(4));
+        } else {
+          gval = -0.5f * o * (uy * (uy * S0 - 2.0f * S2) + sm(5));
+        }
+      } else {
+        gval = sm(c == 5 ? 0 : c);
+      }
+      if (gval != 0.f) {
+        const uint32_t r = s_r[jj];
+        atomicAdd(&g2d[(int64_t)r * 10 + c], gval);
+        touched[r] = 1;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj, const gs_bins* bins,
@@ -501,9 +730,14 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
     order = order_ws;
   }
 #define GS_BWD(BATCH)                                                                                          \
-  GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
-                     bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, \
-                     pg->dT, g2d, touched, order, ctx->bwd_copies)
+  if (ctx->bwd_mfma)                                                                                           \
+    GS_LAUNCH(ctx, render_bwd_mfma_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start, \
+              bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
+              g2d, touched, order, ctx->bwd_copies);                                                           \
+  else                                                                                                         \
+    GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,    \
+              bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
+              g2d, touched, order, ctx->bwd_copies)
   switch (ctx->bwd_batch) {
     case 32: GS_BWD(32); break;
     case 128: GS_BWD(128); break;

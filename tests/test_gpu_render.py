@@ -365,6 +365,34 @@ def test_wave_cull_exact(ctx, seed, n, W, H, max_rank):
         assert_grads_close(torch_np(other[1]), torch_np(grads[0][1]), rel=1e-4, name="pose")
 
 
+@pytest.mark.parametrize("seed,n,W,H,batch", [(31, 20000, 640, 480, 64), (32, 3000, 100, 75, 32),
+                                              (33, 60000, 320, 240, 128)])
+def test_bwd_mfma_matches_vector_path(ctx, seed, n, W, H, batch):
+    """The matrix-core form of the backward's per-entry sums gives the
+    gradients of the vector-reduction form (only summation order differs)."""
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(seed, n, W, H)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], bg=(0.1, 0.1, 0.1))
+    pipe.forward(gst)
+    tc, td = (pipe.img_color * 0.7).contiguous(), (pipe.img_depth * 1.2).contiguous()
+    pipe.loss_and_grads(tc, td)
+    ctx.set_param("bwd_batch", batch)
+    res = []
+    for mf in (1, 0):
+        ctx.set_param("bwd_mfma", mf)
+        gr = gs.alloc_grads(n)
+        pose = torch.zeros(6, device="cuda")
+        pipe.backward(gst, gs.grads_struct(gr, pose))
+        torch.cuda.synchronize()
+        res.append((gr, pose))
+        assert torch.count_nonzero(bwd_zero_part(pipe, views)) == 0
+    ctx.set_param("bwd_mfma", 0)
+    ctx.set_param("bwd_batch", 64)
+    for k in res[0][0]:
+        assert_grads_close(torch_np(res[0][0][k]), torch_np(res[1][0][k]), rel=1e-4, name=k)
+    assert_grads_close(torch_np(res[0][1]), torch_np(res[1][1]), rel=1e-4, name="pose")
+    assert float(res[0][0]["mean"].abs().sum()) > 0
+
+
 def test_max_rank_prefix_lists(ctx, orc):
     """Binning only the R nearest records gives exact prefixes of the full
     lists; when every tile saturates inside them the image is identical."""
