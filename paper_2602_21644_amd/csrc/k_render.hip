@@ -367,7 +367,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     }
     // One entry of the batch; two register sets alternate below so that the
     // next entry's record is read from LDS while this one is processed.
-    auto entry = [&](int jj, const float4& A, const float4& B, const float4& Cc) {
+    auto entry = [&](int jj, const float4& A, const float4& B) {
       const int j = lo + jj;
       float k[3] = {0.f, 0.f, 0.f};
       if ((uint32_t)j < wmax) {  // uniform over the wave
@@ -378,6 +378,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
         const float alpha = fminf(GS_ALPHA_MAX, araw);
         const bool valid = (uint32_t)j < nl && p <= 0.f && alpha >= GS_ALPHA_MIN;
         if (__ballot(valid)) {  // uniform
+          const float4 Cc = s_c[jj];  // colour only for entries some pixel composites
           const float a = valid ? alpha : 0.f;
           const float one_m = 1.0f - a;
           const float Tj = T * __builtin_amdgcn_rcpf(one_m);
@@ -403,21 +404,19 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
       }
       if ((lane & 15) == 15) s_red[jj][w * 4 + (lane >> 4)] = make_float4(k[0], k[1], k[2], 0.f);
     };
-    float4 A0 = s_a[n - 1], B0 = s_b[n - 1], C0 = s_c[n - 1], A1, B1, C1;
+    float4 A0 = s_a[n - 1], B0 = s_b[n - 1], A1, B1;
     int jj = n - 1;
     for (; jj >= 1; jj -= 2) {
       A1 = s_a[jj - 1];
       B1 = s_b[jj - 1];
-      C1 = s_c[jj - 1];
-      entry(jj, A0, B0, C0);
+      entry(jj, A0, B0);
       if (jj >= 2) {
         A0 = s_a[jj - 2];
         B0 = s_b[jj - 2];
-        C0 = s_c[jj - 2];
       }
-      entry(jj - 1, A1, B1, C1);
+      entry(jj - 1, A1, B1);
     }
-    if (jj == 0) entry(0, A0, B0, C0);
+    if (jj == 0) entry(0, A0, B0);
     __syncthreads();
     // The cross-wave pass runs on the waves that load nothing: one counter
     // tracks both loads and atomics, so the loader waves' wait for the next
