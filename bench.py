@@ -39,8 +39,10 @@ FLOPS_PER_PAIR = {"render_fwd_kernel": 28, "render_bwd_kernel": 54}
 # the counters are scaled by what they read for a 256 MiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0)
 PMC_TRAFFIC = {
-    "render_bwd_kernel<64>": {"fetch_kib": 10399.5, "write_kib": 26228.1,
-                              "sha256": "d29d12c4e9f3bc757704abb13e8f55eeb61238d629f6539bfed742ac521612c1"},
+    "render_bwd_kernel<64>": {"fetch_kib": 9955.3, "write_kib": 5612.2,
+                              "sha256": "ac6119f8900c19174229d2016b942a5d8246e45c8b4d43795f462286f462333a"},
+    "render_bwd_kernel<32>": {"fetch_kib": 10032.4, "write_kib": 5607.6,
+                              "sha256": "ac6119f8900c19174229d2016b942a5d8246e45c8b4d43795f462286f462333a"},
 }
 PMC_SCALE = {"fetch": 2.0, "write": 1.0}
 

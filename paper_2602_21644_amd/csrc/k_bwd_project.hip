@@ -215,33 +215,20 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
 // Sums the per-block pose partials of every view in a fixed order (one
 // workgroup, float64) and resets them to zero, so the scratch stays
 // zero-filled.
-constexpr int kFinalThreads = 1024;
-__global__ __launch_bounds__(kFinalThreads) void pose_final_kernel(float* __restrict__ part, int nblk,
-                                                                   float* __restrict__ pose, int accumulate) {
-  __shared__ double s_red[kFinalThreads / 64][6];
+// Sums one view's per-block pose partials in a fixed order (one workgroup per
+// view, float64) and resets them to zero, so the scratch stays zero-filled.
+__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict__ part, int nblk,
+                                                              float* __restrict__ pose, int accumulate) {
+  __shared__ double s_red[GS_BLOCK / 64][6];
   const int v = blockIdx.x, lane = __lane_id(), w = threadIdx.x >> 6;
-  float* base = part + (int64_t)v * nblk * 6;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  // four rows per thread in flight at once; rows summed in a fixed order
-  for (int b0 = threadIdx.x; b0 < nblk; b0 += 4 * kFinalThreads) {
-    float q[4][6];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int b = b0 + i * kFinalThreads;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) q[i][c] = b < nblk ? base[(int64_t)b * 6 + c] : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int b = b0 + i * kFinalThreads;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) acc[c] += (double)q[i][c];
-      if (b < nblk)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) base[(int64_t)b * 6 + c] = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) {
+    float* q = part + ((int64_t)v * nblk + b) * 6;
+    for (int c = 0; c < 6; ++c) {
+      acc[c] += (double)q[c];
+      q[c] = 0.f;
     }
   }
-#pragma unroll
   for (int c = 0; c < 6; ++c) {
     acc[c] = wave_sum_to_lane63_d(acc[c]);
     if (lane == 63) s_red[w][c] = acc[c];
@@ -249,8 +236,7 @@ __global__ __launch_bounds__(kFinalThreads) void pose_final_kernel(float* __rest
   __syncthreads();
   if (threadIdx.x < 6 && pose) {
     const int c = threadIdx.x;
-    double t = 0.0;
-    for (int i = 0; i < kFinalThreads / 64; ++i) t += s_red[i][c];
+    const double t = s_red[0][c] + s_red[1][c] + s_red[2][c] + s_red[3][c];
     pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + t : t);
   }
 }
@@ -265,8 +251,7 @@ gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* c
                        g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
                        gr->color, pose_part, gr->pose_only, gr->accumulate, ctx->bwd_copies);
   }
-  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(kFinalThreads), 0, s, pose_part, nblk, gr->pose,
-            gr->accumulate);
+  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, nblk, gr->pose, gr->accumulate);
   return gs_check_launch(ctx, "render_bwd_project");
 }
 

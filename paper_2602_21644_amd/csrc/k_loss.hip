@@ -67,29 +67,17 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_kernel(ViewTab tab, const float
 }
 
 // Sums the per-block partials of a view in a fixed order (one workgroup per
-// view, four partials per thread in flight at once).
-constexpr int kFinalThreads = 1024;
-__global__ __launch_bounds__(kFinalThreads) void loss_final_kernel(const double* __restrict__ part, int nblk,
-                                                                   float* __restrict__ loss) {
-  __shared__ double s[kFinalThreads / 64];
+// view).
+__global__ __launch_bounds__(GS_BLOCK) void loss_final_kernel(const double* __restrict__ part, int nblk,
+                                                              float* __restrict__ loss) {
+  __shared__ double s[GS_BLOCK / 64];
   const int v = blockIdx.x;
-  const double* base = part + (int64_t)v * nblk;
   double t = 0.0;
-  for (int b0 = threadIdx.x; b0 < nblk; b0 += 4 * kFinalThreads) {
-    double q[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) q[i] = b0 + i * kFinalThreads < nblk ? base[b0 + i * kFinalThreads] : 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) t += q[i];
-  }
+  for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) t += part[(int64_t)v * nblk + b];
   t = wave_sum_to_lane63_d(t);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = t;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0;
-    for (int i = 0; i < kFinalThreads / 64; ++i) a += s[i];
-    loss[v] = (float)a;
-  }
+  if (threadIdx.x == 0) loss[v] = (float)(s[0] + s[1] + s[2] + s[3]);
 }
 
 }  // namespace
@@ -107,6 +95,6 @@ gs_status launch_loss(gs_ctx* ctx, const ViewTab& tab, const gs_image* img, cons
   GS_LAUNCH(ctx, loss_kernel, dim3(nb, tab.nv), dim3(GS_BLOCK), 0, s, tab, img->color, img->depth, img->mp,
                      img->T, tgt->color, tgt->depth, lp->lambda_pho, lp->lambda_depth, lp->eps_A, lp->weight_mode,
                      lp->grad_through_weight, pg->dcolor, pg->ddepth, pg->dmp, pg->dT, part);
-  GS_LAUNCH(ctx, loss_final_kernel, dim3(tab.nv), dim3(kFinalThreads), 0, s, part, nb, loss);
+  GS_LAUNCH(ctx, loss_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, part, nb, loss);
   return gs_check_launch(ctx, "loss");
 }
