@@ -20,14 +20,13 @@
 namespace {
 
 constexpr int MAXR = 16;         // regions: background + up to 15 instances
-constexpr int PIX_ITEMS = 16;    // pixels per thread in the region pass
+constexpr int PIX_ITEMS = 4;     // pixels per thread in the region pass
 constexpr int REG_TILE = GS_BLOCK * PIX_ITEMS;
 
 struct MpScal {
   uint32_t umin, umax;      // ordered-int encodings of min/max U
   uint32_t n_obs, n_dyn, n_prune, pad0;
   uint32_t prefix[2], rank[2];
-  uint32_t hist[2][256];
   float region[MAXR][4];    // mu, sigma, e_ub, Gamma_geo
 };
 
@@ -61,7 +60,6 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
                                                              const float* __restrict__ Cg,
                                                              const int32_t* __restrict__ inst, float beta,
                                                              float* __restrict__ e_out, double* __restrict__ part) {
-  __shared__ double s[4];
   const int64_t base = (int64_t)blockIdx.x * REG_TILE;
   float ev[PIX_ITEMS];
   int rv[PIX_ITEMS];
@@ -79,6 +77,8 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
       }
     }
   }
+  // per-wave partial sums of every region (no block barrier)
+  const int64_t row = (int64_t)blockIdx.x * (GS_BLOCK / 64) + (threadIdx.x >> 6);
   for (int r = 0; r <= K; ++r) {
     double c = 0, s1 = 0, s2 = 0;
 #pragma unroll
@@ -88,11 +88,11 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
         s1 += (double)ev[i];
         s2 += (double)ev[i] * (double)ev[i];
       }
-    c = block_sum_d(c, s);
-    s1 = block_sum_d(s1, s);
-    s2 = block_sum_d(s2, s);
-    if (threadIdx.x == 0) {
-      double* o = part + ((int64_t)blockIdx.x * MAXR + r) * 3;
+    c = wave_sum_to_lane63_d(c);
+    s1 = wave_sum_to_lane63_d(s1);
+    s2 = wave_sum_to_lane63_d(s2);
+    if (__lane_id() == 0) {
+      double* o = part + (row * MAXR + r) * 3;
       o[0] = c;
       o[1] = s1;
       o[2] = s2;
@@ -100,22 +100,23 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
   }
 }
 
-__global__ void mp_region_final_kernel(const double* __restrict__ part, int nb, int K, float lambda_e, float e_floor,
-                                       float sigma_g, MpScal* __restrict__ sc) {
-  const int r = threadIdx.x;
-  if (threadIdx.x == 0) {
-    sc->umin = 0xFFFFFFFFu;
-    sc->umax = 0u;
-    sc->n_obs = sc->n_dyn = sc->n_prune = 0;
-  }
+// One wave per region sums the per-wave partials (rows) in a fixed order.
+__global__ __launch_bounds__(MAXR * 64) void mp_region_final_kernel(const double* __restrict__ part, int nrows, int K,
+                                                                    float lambda_e, float e_floor, float sigma_g,
+                                                                    MpScal* __restrict__ sc) {
+  const int r = threadIdx.x >> 6, lane = __lane_id();
   if (r > K) return;
   double c = 0, s1 = 0, s2 = 0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = lane; b < nrows; b += 64) {
     const double* o = part + ((int64_t)b * MAXR + r) * 3;
     c += o[0];
     s1 += o[1];
     s2 += o[2];
   }
+  c = wave_sum_to_lane63_d(c);
+  s1 = wave_sum_to_lane63_d(s1);
+  s2 = wave_sum_to_lane63_d(s2);
+  if (lane != 0) return;
   double mu = 0, sd = 0;
   if (c > 0) {
     mu = s1 / c;
@@ -134,14 +135,17 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_pixel_kernel(int64_t npix, int K,
                                                             const float* __restrict__ conf,
                                                             const float* __restrict__ mlp, float sigma_small,
                                                             const MpScal* __restrict__ sc, float* __restrict__ Mp,
-                                                            float* __restrict__ e_copy) {
+                                                            float* __restrict__ e_copy, const float* __restrict__ Dg,
+                                                            float4* __restrict__ pk) {
   const int64_t p = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
   if (p >= npix) return;
   const int r = min(max(inst[p], 0), K);
   const float e = e_in[p];
   if (e_copy) e_copy[p] = e;
   if (mlp) {
-    Mp[p] = mlp[p];
+    const float m = mlp[p];
+    Mp[p] = m;
+    pk[p] = make_float4(m, e, Dg[p], 0.f);
     return;
   }
   const float mu = sc->region[r][0], sd = sc->region[r][1], ub = sc->region[r][2], gg = sc->region[r][3];
@@ -150,7 +154,10 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_pixel_kernel(int64_t npix, int K,
   const float gi = conf[r];
   const float den = gi + gg;
   const float Kp = den > 0.f ? gg / den : 0.5f;
-  Mp[p] = (1.f - Kp) * prior[r] + Kp * geo;
+  const float m = (1.f - Kp) * prior[r] + Kp * geo;
+  Mp[p] = m;
+  // (M_p, e, observed depth) packed for the per-Gaussian windows
+  pk[p] = make_float4(m, e, Dg[p], 0.f);
 }
 
 struct GaussOut {
@@ -162,12 +169,10 @@ struct GaussOut {
 
 __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const float* __restrict__ mean2d,
                                                             const uint32_t* __restrict__ key,
-                                                            const float* __restrict__ Dg,
-                                                            const float* __restrict__ Mp,
-                                                            const float* __restrict__ e_in,
+                                                            const float4* __restrict__ pk,
                                                             const float* __restrict__ mp, float radius, float sigma_w,
                                                             float lambda_u, float eps, GaussOut go,
-                                                            MpScal* __restrict__ sc) {
+                                                            uint32_t* __restrict__ part_u) {
   __shared__ uint32_t s_min, s_max, s_cnt;
   if (threadIdx.x == 0) {
     s_min = 0xFFFFFFFFu;
@@ -178,6 +183,8 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const f
   const int64_t k = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
   const int W = tab.W[0], H = tab.H[0];
   const int64_t M = tab.nrec;
+  uint32_t umin = 0xFFFFFFFFu, umax = 0u;  // order-preserving bits of U when observed
+  bool seen = false;
   if (k < tab.n[0]) {
     const int64_t r = tab.r_off[0] + k;
     bool obs = false;
@@ -191,58 +198,133 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const f
       const int x0 = max(0, cx - rr), x1 = min(W - 1, cx + rr);
       const int y0 = max(0, cy - rr), y1 = min(H - 1, cy + rr);
       const float inv2 = 1.0f / (2.0f * sigma_w * sigma_w);
+      // one pass over the window: weighted mean of M_p, and the population
+      // variances of M_p and e from sums shifted by the first valid sample
+      // (exact zero for constant samples)
       int n = 0;
-      float sw = 0.f, swm = 0.f, sm = 0.f, se = 0.f;
-      for (int y = y0; y <= y1; ++y)
-        for (int x = x0; x <= x1; ++x) {
-          const float dx = __fsub_rn((float)x, ux), dy = __fsub_rn((float)y, uy);
-          const float d2 = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
-          const int64_t p = (int64_t)y * W + x;
-          if (d2 <= r2 && Dg[p] > 0.f) {
-            const float w = __expf(-d2 * inv2);
-            const float m = Mp[p];
-            ++n;
-            sw += w;
-            swm += w * m;
-            sm += m;
-            se += e_in[p];
-          }
+      float sw = 0.f, swm = 0.f, km = 0.f, ke = 0.f, am = 0.f, am2 = 0.f, ae = 0.f, ae2 = 0.f;
+      auto take = [&](const float4& v, float d2) {
+        const float w = __expf(-d2 * inv2);
+        if (n == 0) {
+          km = v.x;
+          ke = v.y;
         }
-      if (n > 0) {
-        obs = true;
-        const float mm = sm / n, me = se / n;
-        float vm = 0.f, ve = 0.f;
+        ++n;
+        sw += w;
+        swm += w * v.x;
+        const float a = v.x - km, b = v.y - ke;
+        am += a;
+        am2 += a * a;
+        ae += b;
+        ae2 += b * b;
+      };
+      if (radius <= 2.0f) {
+        // every pixel within 2 px lies in the 5x5 box from (ceil(ux-2),
+        // ceil(uy-2)); its loads are issued together, visited in the same
+        // row-major order as the general loop below
+        const int xs = (int)ceilf(ux - 2.0f), ys = (int)ceilf(uy - 2.0f);
+        float4 v[25];
+        float dd[25];
+        bool in[25];
+#pragma unroll
+        for (int i = 0; i < 25; ++i) {
+          const int x = xs + i % 5, y = ys + i / 5;
+          const float dx = __fsub_rn((float)x, ux), dy = __fsub_rn((float)y, uy);
+          dd[i] = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+          in[i] = x >= x0 && x <= x1 && y >= y0 && y <= y1 && dd[i] <= r2;
+          v[i] = in[i] ? pk[(int64_t)y * W + x] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < 25; ++i)
+          if (in[i] && v[i].z > 0.f) take(v[i], dd[i]);
+      } else {
         for (int y = y0; y <= y1; ++y)
           for (int x = x0; x <= x1; ++x) {
             const float dx = __fsub_rn((float)x, ux), dy = __fsub_rn((float)y, uy);
             const float d2 = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
-            const int64_t p = (int64_t)y * W + x;
-            if (d2 <= r2 && Dg[p] > 0.f) {
-              const float a = Mp[p] - mm, b = e_in[p] - me;
-              vm += a * a;
-              ve += b * b;
+            if (d2 <= r2) {
+              const float4 v = pk[(int64_t)y * W + x];
+              if (v.z > 0.f) take(v, d2);
             }
           }
-        const float var = vm / n;
-        sde = sqrtf(ve / n);
+      }
+      if (n > 0) {
+        obs = true;
+        const float fn = (float)n;
+        const float var = fmaxf(0.f, (am2 - am * am / fn) / fn);
+        sde = sqrtf(fmaxf(0.f, (ae2 - ae * ae / fn) / fn));
         Mhat = swm / sw;
         const float M0 = mp[tab.g_off[0] + k];
         U = -M0 * logf(M0 + eps) - (1.f - M0) * logf(1.f - M0 + eps) + lambda_u * var;
-        atomicMin(&s_min, f2ord(U));
-        atomicMax(&s_max, f2ord(U));
-        atomicAdd(&s_cnt, 1u);
       }
     }
     go.Mhat[k] = Mhat;
     go.sde[k] = sde;
     go.U[k] = U;
     go.obs[k] = obs ? 1 : 0;
+    if (obs) {
+      umin = f2ord(U);
+      umax = umin;
+      seen = true;
+    }
+  }
+  // range and count of U over the block: per wave by shuffles, then one LDS
+  // atomic per wave
+  const uint32_t cnt = (uint32_t)__popcll(__ballot(seen));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    umin = min(umin, (uint32_t)__shfl_xor((int)umin, o, 64));
+    umax = max(umax, (uint32_t)__shfl_xor((int)umax, o, 64));
+  }
+  if (__lane_id() == 0 && cnt) {
+    atomicMin(&s_min, umin);
+    atomicMax(&s_max, umax);
+    atomicAdd(&s_cnt, cnt);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && s_cnt > 0) {
-    atomicMin(&sc->umin, s_min);
-    atomicMax(&sc->umax, s_max);
-    atomicAdd(&sc->n_obs, s_cnt);
+  // the block's partial (min, max, count), summed by mp_ureduce_kernel
+  if (threadIdx.x == 0) {
+    part_u[3 * (int64_t)blockIdx.x + 0] = s_min;
+    part_u[3 * (int64_t)blockIdx.x + 1] = s_max;
+    part_u[3 * (int64_t)blockIdx.x + 2] = s_cnt;
+  }
+}
+
+// Range and count of U over all blocks of mp_gauss_kernel (one workgroup).
+__global__ __launch_bounds__(1024) void mp_ureduce_kernel(const uint32_t* __restrict__ part_u, int nb,
+                                                          MpScal* __restrict__ sc) {
+  __shared__ uint32_t s_v[3][16];
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u, cnt = 0u;
+  for (int b = threadIdx.x; b < nb; b += 1024) {
+    mn = min(mn, part_u[3 * b + 0]);
+    mx = max(mx, part_u[3 * b + 1]);
+    cnt += part_u[3 * b + 2];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, o, 64));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    cnt += (uint32_t)__shfl_xor((int)cnt, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == 0) {
+    s_v[0][w] = mn;
+    s_v[1][w] = mx;
+    s_v[2][w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 16; ++i) {
+      mn = min(mn, s_v[0][i]);
+      mx = max(mx, s_v[1][i]);
+    }
+    uint32_t c = 0;
+    for (int i = 0; i < 16; ++i) c += s_v[2][i];
+    mn = min(mn, s_v[0][0]);
+    mx = max(mx, s_v[1][0]);
+    sc->umin = mn;
+    sc->umax = mx;
+    sc->n_obs = c;
   }
 }
 
@@ -290,59 +372,84 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_state_kernel(ViewTab tab, GaussOu
 __global__ __launch_bounds__(GS_BLOCK) void mp_sel_hist_kernel(int64_t n, int64_t g_off, const uint8_t* __restrict__ obs,
                                                                const float* __restrict__ v0,
                                                                const float* __restrict__ v1, int pass,
-                                                               MpScal* __restrict__ sc) {
+                                                               const MpScal* __restrict__ sc,
+                                                               uint32_t* __restrict__ part_h) {
   __shared__ uint32_t h[2][256];
   h[0][threadIdx.x] = 0;
   h[1][threadIdx.x] = 0;
   __syncthreads();
   const int shift = 24 - 8 * pass;
   const uint32_t hmask = pass == 0 ? 0u : (0xFFFFFFFFu << (shift + 8));
-  const uint32_t p0 = sc->prefix[0], p1 = sc->prefix[1];
-  for (int64_t k = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x; k < n; k += (int64_t)gridDim.x * GS_BLOCK) {
-    if (!obs[k]) continue;
-    const uint32_t a = __float_as_uint(v0[g_off + k]);
-    const uint32_t b = __float_as_uint(v1[g_off + k]);
-    if ((a & hmask) == (p0 & hmask)) atomicAdd(&h[0][(a >> shift) & 255u], 1u);
-    if ((b & hmask) == (p1 & hmask)) atomicAdd(&h[1][(b >> shift) & 255u], 1u);
+  const uint32_t p0 = pass == 0 ? 0u : sc->prefix[0], p1 = pass == 0 ? 0u : sc->prefix[1];
+  for (int64_t base = (int64_t)blockIdx.x * GS_BLOCK; base < n; base += (int64_t)gridDim.x * GS_BLOCK) {
+    const int64_t k = base + threadIdx.x;
+    const bool o = k < n && obs[k];
+    const uint32_t a = o ? __float_as_uint(v0[g_off + k]) : 0u;
+    const uint32_t b = o ? __float_as_uint(v1[g_off + k]) : 0u;
+    if (o && (a & hmask) == (p0 & hmask)) atomicAdd(&h[0][(a >> shift) & 255u], 1u);
+    if (o && (b & hmask) == (p1 & hmask)) atomicAdd(&h[1][(b >> shift) & 255u], 1u);
   }
   __syncthreads();
-  if (h[0][threadIdx.x]) atomicAdd(&sc->hist[0][threadIdx.x], h[0][threadIdx.x]);
-  if (h[1][threadIdx.x]) atomicAdd(&sc->hist[1][threadIdx.x], h[1][threadIdx.x]);
+  // the block's histograms, summed by mp_sel_pick_kernel (no contended atomics)
+  part_h[(int64_t)blockIdx.x * 512 + threadIdx.x] = h[0][threadIdx.x];
+  part_h[(int64_t)blockIdx.x * 512 + 256 + threadIdx.x] = h[1][threadIdx.x];
 }
 
-__global__ void mp_sel_pick_kernel(int pass, MpScal* __restrict__ sc) {
-  const int which = threadIdx.x;  // 2 threads
-  if (which < 2) {
-    if (pass == 0) {
-      sc->rank[which] = sc->n_obs > 0 ? (sc->n_obs - 1) / 2 : 0;
-      sc->prefix[which] = 0;
-    }
-    const int shift = 24 - 8 * pass;
-    uint32_t rank = sc->rank[which], acc = 0;
-    int d = 0;
-    for (; d < 256; ++d) {
-      const uint32_t c = sc->hist[which][d];
-      if (rank < acc + c) break;
-      acc += c;
-    }
-    if (d > 255) d = 255;
-    sc->rank[which] = rank - acc;
-    sc->prefix[which] |= (uint32_t)d << shift;
-    for (int i = 0; i < 256; ++i) sc->hist[which][i] = 0;
+// Sums the blocks' digit histograms and picks the digit holding the running
+// rank (one workgroup: 512 columns summed by two threads each, then one wave
+// per 64 bins of each value scans them).
+constexpr int SEL_BLOCKS = 64;
+__global__ __launch_bounds__(1024) void mp_sel_pick_kernel(int pass, const uint32_t* __restrict__ part_h,
+                                                           MpScal* __restrict__ sc) {
+  __shared__ uint32_t s_half[2][512];
+  __shared__ uint32_t s_h[512];
+  __shared__ uint32_t s_wsum[8];
+  __shared__ uint32_t s_rank[2], s_prefix[2];
+  const int t = threadIdx.x, col = t & 511, half = t >> 9;
+  if (t < 2) {  // the running state, read before any thread updates it
+    s_rank[t] = pass == 0 ? (sc->n_obs > 0 ? (sc->n_obs - 1) / 2 : 0) : sc->rank[t];
+    s_prefix[t] = pass == 0 ? 0u : sc->prefix[t];
   }
-}
-
-__global__ void mp_sel_reset_kernel(MpScal* __restrict__ sc) {
-  for (int i = threadIdx.x; i < 512; i += blockDim.x) (&sc->hist[0][0])[i] = 0;
-  if (threadIdx.x < 2) {
-    sc->prefix[threadIdx.x] = 0;
-    sc->rank[threadIdx.x] = 0;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int b = half; b < SEL_BLOCKS; b += 2) acc += part_h[(int64_t)b * 512 + col];
+  s_half[half][col] = acc;
+  __syncthreads();
+  // inclusive scan of each value's 256 bins: four waves per value
+  uint32_t incl = 0, cnt = 0;
+  const int lane = __lane_id(), w = t >> 6;
+  if (t < 512) {
+    cnt = s_half[0][t] + s_half[1][t];
+    s_h[t] = cnt;
+    incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wsum[w] = incl;
+  }
+  __syncthreads();
+  if (t < 512) {
+    const int which = t >> 8, d = t & 255;
+    for (int i = which * 4; i < w; ++i) incl += s_wsum[i];
+    const uint32_t excl = incl - cnt;
+    const uint32_t rank = s_rank[which], prefix = s_prefix[which];
+    const int shift = 24 - 8 * pass;
+    // the bin holding the rank; past every bin, the last one with all counted
+    const bool hit = rank >= excl && rank < incl;
+    const bool last = d == 255 && rank >= incl;
+    if (hit || last) {
+      sc->rank[which] = rank - (hit ? excl : incl);
+      sc->prefix[which] = prefix | ((uint32_t)d << shift);
+    }
   }
 }
 
 __global__ __launch_bounds__(GS_BLOCK) void mp_label_kernel(ViewTab tab, const float* __restrict__ mp,
-                                                            float prune_above, MpScal* __restrict__ sc,
-                                                            uint8_t* __restrict__ dyn, uint8_t* __restrict__ prune) {
+                                                            float prune_above, const MpScal* __restrict__ sc,
+                                                            uint8_t* __restrict__ dyn, uint8_t* __restrict__ prune,
+                                                            uint32_t* __restrict__ part_l) {
   __shared__ uint32_t s_d, s_p;
   if (threadIdx.x == 0) {
     s_d = 0;
@@ -352,24 +459,54 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_label_kernel(ViewTab tab, const f
   const float med = sc->n_obs > 0 ? __uint_as_float(sc->prefix[0]) : 0.f;
   const float tau = sc->n_obs > 0 ? fmaxf(med, 0.5f) : 0.5f;
   const int64_t k = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+  bool d = false, p = false;
   if (k < tab.n[0]) {
     const int64_t gk = tab.g_off[0] + k;
     const float m = mp[gk];
-    const bool d = m > tau, p = m > prune_above;
+    d = m > tau;
+    p = m > prune_above;
     dyn[gk] = d;
     prune[gk] = p;
-    if (d) atomicAdd(&s_d, 1u);
-    if (p) atomicAdd(&s_p, 1u);
+  }
+  // counts per wave by ballot, one LDS atomic per wave
+  const uint32_t cd = (uint32_t)__popcll(__ballot(d)), cp = (uint32_t)__popcll(__ballot(p));
+  if (__lane_id() == 0) {
+    if (cd) atomicAdd(&s_d, cd);
+    if (cp) atomicAdd(&s_p, cp);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (s_d) atomicAdd(&sc->n_dyn, s_d);
-    if (s_p) atomicAdd(&sc->n_prune, s_p);
+    part_l[2 * (int64_t)blockIdx.x + 0] = s_d;
+    part_l[2 * (int64_t)blockIdx.x + 1] = s_p;
   }
 }
 
-__global__ void mp_stats_kernel(const MpScal* __restrict__ sc, float* __restrict__ stats) {
+__global__ __launch_bounds__(1024) void mp_stats_kernel(MpScal* __restrict__ sc, const uint32_t* __restrict__ part_l,
+                                                        int nb, float* __restrict__ stats) {
+  __shared__ uint32_t s_v[2][16];
+  uint32_t cd = 0, cp = 0;
+  for (int b = threadIdx.x; b < nb; b += 1024) {
+    cd += part_l[2 * b + 0];
+    cp += part_l[2 * b + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    cd += (uint32_t)__shfl_xor((int)cd, o, 64);
+    cp += (uint32_t)__shfl_xor((int)cp, o, 64);
+  }
+  if (__lane_id() == 0) {
+    s_v[0][threadIdx.x >> 6] = cd;
+    s_v[1][threadIdx.x >> 6] = cp;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  cd = cp = 0;
+  for (int i = 0; i < 16; ++i) {
+    cd += s_v[0][i];
+    cp += s_v[1][i];
+  }
+  sc->n_dyn = cd;
+  sc->n_prune = cp;
   const bool any = sc->n_obs > 0;
   const float med = any ? __uint_as_float(sc->prefix[0]) : 0.f;
   stats[0] = any ? __uint_as_float(sc->prefix[1]) : 0.f;
@@ -385,16 +522,21 @@ __global__ void mp_stats_kernel(const MpScal* __restrict__ sc, float* __restrict
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct MpWs {
-  size_t e, Mp, part, scal, Mhat, sde, U, obs, bytes;
+  size_t e, Mp, pk, part, part_u, part_l, part_h, scal, Mhat, sde, U, obs, bytes;
 };
 
 MpWs mp_layout(int64_t n, int64_t P) {
   MpWs L;
   size_t o = 0;
   const int64_t nb = (P + REG_TILE - 1) / REG_TILE;
+  const int64_t gb = (n + GS_BLOCK - 1) / GS_BLOCK;
   L.e = o; o += al(P * 4);
   L.Mp = o; o += al(P * 4);
-  L.part = o; o += al((size_t)(nb > 0 ? nb : 1) * MAXR * 3 * 8);
+  L.pk = o; o += al(P * 16);
+  L.part = o; o += al((size_t)(nb > 0 ? nb : 1) * (GS_BLOCK / 64) * MAXR * 3 * 8);
+  L.part_u = o; o += al((size_t)(gb > 0 ? gb : 1) * 3 * 4);
+  L.part_l = o; o += al((size_t)(gb > 0 ? gb : 1) * 2 * 4);
+  L.part_h = o; o += al((size_t)SEL_BLOCKS * 512 * 4);
   L.scal = o; o += al(sizeof(MpScal));
   L.Mhat = o; o += al(n * 4);
   L.sde = o; o += al(n * 4);
@@ -416,37 +558,40 @@ gs_status launch_mp_update(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj,
   float* e = (float*)(ws + L.e);
   float* Mp = out->M_p ? out->M_p : (float*)(ws + L.Mp);
   double* part = (double*)(ws + L.part);
+  uint32_t* part_u = (uint32_t*)(ws + L.part_u);
+  uint32_t* part_l = (uint32_t*)(ws + L.part_l);
+  uint32_t* part_h = (uint32_t*)(ws + L.part_h);
   MpScal* sc = (MpScal*)(ws + L.scal);
   GaussOut go{(float*)(ws + L.Mhat), (float*)(ws + L.sde), (float*)(ws + L.U), (uint8_t*)(ws + L.obs)};
+  float4* pk = (float4*)(ws + L.pk);
   const int K = fr->n_inst;
   const int nb = (int)((P + REG_TILE - 1) / REG_TILE);
   if (nb > 0)
     GS_LAUNCH(ctx, mp_region_kernel, dim3(nb), dim3(GS_BLOCK), 0, s, P, P, K, img->depth, tgt->depth, img->color,
-                       tgt->color, fr->instance_id, pp->beta_color, e, part);
-  GS_LAUNCH(ctx, mp_region_final_kernel, dim3(1), dim3(64), 0, s, part, nb, K, pp->lambda_e, pp->e_floor,
-                     pp->sigma_g, sc);
+              tgt->color, fr->instance_id, pp->beta_color, e, part);
+  GS_LAUNCH(ctx, mp_region_final_kernel, dim3(1), dim3(MAXR * 64), 0, s, part, nb * (GS_BLOCK / 64), K,
+            pp->lambda_e, pp->e_floor, pp->sigma_g, sc);
   if (P > 0)
     GS_LAUNCH(ctx, mp_pixel_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s, P, K,
-                       e, fr->instance_id, fr->inst_prior, fr->inst_conf, fr->mlp_mp, pp->sigma_small, sc, Mp,
-                       out->e);
+              e, fr->instance_id, fr->inst_prior, fr->inst_conf, fr->mlp_mp, pp->sigma_small, sc, Mp, out->e,
+              tgt->depth, pk);
   const unsigned gb = (unsigned)((n + GS_BLOCK - 1) / GS_BLOCK);
-  if (n > 0) {
-    GS_LAUNCH(ctx, mp_gauss_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, proj->mean2d, proj->depth_key,
-                       tgt->depth, Mp, e, mp, pp->radius_px, pp->sigma_w, pp->lambda_u, pp->eps, go, sc);
+  if (n > 0)
+    GS_LAUNCH(ctx, mp_gauss_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, proj->mean2d, proj->depth_key, pk, mp,
+              pp->radius_px, pp->sigma_w, pp->lambda_u, pp->eps, go, part_u);
+  GS_LAUNCH(ctx, mp_ureduce_kernel, dim3(1), dim3(1024), 0, s, part_u, (int)gb, sc);
+  if (n > 0)
     GS_LAUNCH(ctx, mp_state_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, go, sc, pp->sigma_c, pp->lambda_u,
-                       pp->alpha_min, pp->alpha_max, pp->rho, fr->seg_updated, pp->mode, pp->u_norm, pp->logodds_eps,
-                       pp->logodds_max, mp, out->U_tilde, out->alpha);
-  }
-  GS_LAUNCH(ctx, mp_sel_reset_kernel, dim3(1), dim3(GS_BLOCK), 0, s, sc);
-  const unsigned sb = gb < 1024 ? (gb > 0 ? gb : 1) : 1024;
+              pp->alpha_min, pp->alpha_max, pp->rho, fr->seg_updated, pp->mode, pp->u_norm, pp->logodds_eps,
+              pp->logodds_max, mp, out->U_tilde, out->alpha);
   for (int pass = 0; pass < 4; ++pass) {
-    GS_LAUNCH(ctx, mp_sel_hist_kernel, dim3(sb), dim3(GS_BLOCK), 0, s, n, tab.g_off[0], go.obs, mp, out->U_tilde,
-                       pass, sc);
-    GS_LAUNCH(ctx, mp_sel_pick_kernel, dim3(1), dim3(64), 0, s, pass, sc);
+    GS_LAUNCH(ctx, mp_sel_hist_kernel, dim3(SEL_BLOCKS), dim3(GS_BLOCK), 0, s, n, tab.g_off[0], go.obs, mp,
+              out->U_tilde, pass, sc, part_h);
+    GS_LAUNCH(ctx, mp_sel_pick_kernel, dim3(1), dim3(1024), 0, s, pass, part_h, sc);
   }
   if (n > 0)
     GS_LAUNCH(ctx, mp_label_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, mp, pp->prune_above, sc, out->dynamic,
-                       out->prune);
-  GS_LAUNCH(ctx, mp_stats_kernel, dim3(1), dim3(64), 0, s, sc, out->stats);
+              out->prune, part_l);
+  GS_LAUNCH(ctx, mp_stats_kernel, dim3(1), dim3(1024), 0, s, sc, part_l, (int)gb, out->stats);
   return gs_check_launch(ctx, "mp_update");
 }

@@ -87,6 +87,7 @@ CASES = [
     dict(seed=4, n=2500, W=64, H=48, K=0, params=dict(e_floor=0.03, prune_above=0.8), seg=True),
     dict(seed=5, n=20000, W=320, H=240, K=5, params=dict(alpha_min=1.0, alpha_max=1.0), seg=True),
     dict(seed=6, n=3000, W=64, H=48, K=15, params=dict(radius_px=3.5, sigma_w=1.5), seg=True),
+    dict(seed=7, n=6000, W=70, H=50, K=3, params=dict(radius_px=1.3, sigma_w=0.8), seg=True),
 ]
 
 
