@@ -22,6 +22,8 @@ namespace {
 constexpr int MAXR = 16;         // regions: background + up to 15 instances
 constexpr int PIX_ITEMS = 4;     // pixels per thread in the region pass
 constexpr int REG_TILE = GS_BLOCK * PIX_ITEMS;
+constexpr int SEL_BLOCKS = 256;
+constexpr int SEL_COPIES = 8;  // histogram copies, one per XCD
 
 struct MpScal {
   uint32_t umin, umax;      // ordered-int encodings of min/max U
@@ -292,8 +294,10 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const f
 
 // Range and count of U over all blocks of mp_gauss_kernel (one workgroup).
 __global__ __launch_bounds__(1024) void mp_ureduce_kernel(const uint32_t* __restrict__ part_u, int nb,
-                                                          MpScal* __restrict__ sc) {
+                                                          MpScal* __restrict__ sc, uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_v[3][16];
+  // the selection's histogram copies start every update cleared
+  for (int i = threadIdx.x; i < SEL_COPIES * 512; i += 1024) hist[i] = 0;
   uint32_t mn = 0xFFFFFFFFu, mx = 0u, cnt = 0u;
   for (int b = threadIdx.x; b < nb; b += 1024) {
     mn = min(mn, part_u[3 * b + 0]);
@@ -367,6 +371,7 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_state_kernel(ViewTab tab, GaussOu
   a_out[gk] = a;
 }
 
+
 // Radix select: pass `pass` (0 = bits 31..24) histograms the digit of every
 // observed value whose higher digits match the running prefix.
 __global__ __launch_bounds__(GS_BLOCK) void mp_sel_hist_kernel(int64_t n, int64_t g_off, const uint8_t* __restrict__ obs,
@@ -390,36 +395,41 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_sel_hist_kernel(int64_t n, int64_
     if (o && (b & hmask) == (p1 & hmask)) atomicAdd(&h[1][(b >> shift) & 255u], 1u);
   }
   __syncthreads();
-  // the block's histograms, summed by mp_sel_pick_kernel (no contended atomics)
-  part_h[(int64_t)blockIdx.x * 512 + threadIdx.x] = h[0][threadIdx.x];
-  part_h[(int64_t)blockIdx.x * 512 + 256 + threadIdx.x] = h[1][threadIdx.x];
+  // added into the histogram copy of the XCD the workgroup runs on, so the
+  // workgroups of different XCDs do not contend for one address; the pick
+  // sums the copies and clears them
+  uint32_t* hc = part_h + (__builtin_amdgcn_s_getreg((31 << 11) | 20) & (SEL_COPIES - 1)) * 512;
+  if (h[0][threadIdx.x]) atomicAdd(&hc[threadIdx.x], h[0][threadIdx.x]);
+  if (h[1][threadIdx.x]) atomicAdd(&hc[256 + threadIdx.x], h[1][threadIdx.x]);
 }
 
-// Sums the blocks' digit histograms and picks the digit holding the running
-// rank (one workgroup: 512 columns summed by two threads each, then one wave
-// per 64 bins of each value scans them).
-constexpr int SEL_BLOCKS = 64;
-__global__ __launch_bounds__(1024) void mp_sel_pick_kernel(int pass, const uint32_t* __restrict__ part_h,
+// Sums the histogram copies (and clears them) and picks the digit holding
+// the running rank (one workgroup; one wave per 64 bins of each value scans
+// them).
+__global__ __launch_bounds__(1024) void mp_sel_pick_kernel(int pass, uint32_t* __restrict__ part_h,
                                                            MpScal* __restrict__ sc) {
-  __shared__ uint32_t s_half[2][512];
   __shared__ uint32_t s_h[512];
   __shared__ uint32_t s_wsum[8];
   __shared__ uint32_t s_rank[2], s_prefix[2];
-  const int t = threadIdx.x, col = t & 511, half = t >> 9;
+  const int t = threadIdx.x;
   if (t < 2) {  // the running state, read before any thread updates it
     s_rank[t] = pass == 0 ? (sc->n_obs > 0 ? (sc->n_obs - 1) / 2 : 0) : sc->rank[t];
     s_prefix[t] = pass == 0 ? 0u : sc->prefix[t];
   }
   uint32_t acc = 0;
+  if (t < 512) {
 #pragma unroll
-  for (int b = half; b < SEL_BLOCKS; b += 2) acc += part_h[(int64_t)b * 512 + col];
-  s_half[half][col] = acc;
+    for (int c = 0; c < SEL_COPIES; ++c) {
+      acc += part_h[c * 512 + t];
+      part_h[c * 512 + t] = 0;
+    }
+  }
   __syncthreads();
   // inclusive scan of each value's 256 bins: four waves per value
   uint32_t incl = 0, cnt = 0;
   const int lane = __lane_id(), w = t >> 6;
   if (t < 512) {
-    cnt = s_half[0][t] + s_half[1][t];
+    cnt = acc;
     s_h[t] = cnt;
     incl = cnt;
 #pragma unroll
@@ -536,7 +546,7 @@ MpWs mp_layout(int64_t n, int64_t P) {
   L.part = o; o += al((size_t)(nb > 0 ? nb : 1) * (GS_BLOCK / 64) * MAXR * 3 * 8);
   L.part_u = o; o += al((size_t)(gb > 0 ? gb : 1) * 3 * 4);
   L.part_l = o; o += al((size_t)(gb > 0 ? gb : 1) * 2 * 4);
-  L.part_h = o; o += al((size_t)SEL_BLOCKS * 512 * 4);
+  L.part_h = o; o += al((size_t)SEL_COPIES * 512 * 4);
   L.scal = o; o += al(sizeof(MpScal));
   L.Mhat = o; o += al(n * 4);
   L.sde = o; o += al(n * 4);
@@ -579,7 +589,7 @@ gs_status launch_mp_update(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj,
   if (n > 0)
     GS_LAUNCH(ctx, mp_gauss_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, proj->mean2d, proj->depth_key, pk, mp,
               pp->radius_px, pp->sigma_w, pp->lambda_u, pp->eps, go, part_u);
-  GS_LAUNCH(ctx, mp_ureduce_kernel, dim3(1), dim3(1024), 0, s, part_u, (int)gb, sc);
+  GS_LAUNCH(ctx, mp_ureduce_kernel, dim3(1), dim3(1024), 0, s, part_u, (int)gb, sc, part_h);
   if (n > 0)
     GS_LAUNCH(ctx, mp_state_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, go, sc, pp->sigma_c, pp->lambda_u,
               pp->alpha_min, pp->alpha_max, pp->rho, fr->seg_updated, pp->mode, pp->u_norm, pp->logodds_eps,
