@@ -149,11 +149,16 @@ typedef struct gs_image {
   float* mp;         /* [P]  sum alpha T m (MP channel) */
   float* T;          /* [P]  final transmittance */
   uint32_t* n_last;  /* [P]  list position after the last contributing entry */
-  uint32_t* tile_work; /* [n_tiles] optional (NULL skips): written by
+  uint32_t* tile_work; /* [2 n_tiles + 1] optional (NULL skips), zero-filled
+                          before first use, then owned by the library: tile
+                          scheduling state. [0, n_tiles): written by
                           gs_render_fwd, per tile the sum over its four
                           64-pixel groups (pixel rows 4i..4i+3) of the largest
-                          n_last in the group. gs_render_bwd then launches the
-                          tiles heaviest first (scheduling only). */
+                          n_last in the group. [n_tiles, 2 n_tiles]: a launch
+                          order heaviest first and a marker, written by
+                          gs_render_bwd and used by it and by the next
+                          gs_render_fwd with the same tile count (scheduling
+                          only: results do not depend on it). */
 } gs_image;
 
 typedef struct gs_target {
@@ -271,10 +276,9 @@ gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const
  * parameters and one pose twist per view (Sec. IV-D: Gaussians and poses are
  * optimised jointly). Transmittance is recomputed back from T_final. `ws` of
  * gs_workspace_size(GS_OP_RENDER_BWD), zero-filled before first use; each
- * call leaves it zero-filled except its last 4 * n_tiles bytes (rounded up to
- * a multiple of 256), where it keeps the tile launch order. With
- * img->tile_work set (and "tile_order" on) the tiles run heaviest first; the
- * gradients differ only in the order of their float atomics. */
+ * call leaves it zero-filled. With img->tile_work set (and "tile_order" on)
+ * the tiles run heaviest first; the gradients differ only in the order of
+ * their float atomics. */
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
                         const gs_bins* bins, const gs_image* img, const gs_pixel_grads* pg, const float* bg,
                         gs_grads* grads, void* ws, size_t ws_bytes, void* stream);

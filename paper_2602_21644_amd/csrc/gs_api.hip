@@ -206,7 +206,7 @@ static gs_status make_tab(gs_ctx* ctx, const gs_views* vw, ViewTab& tab) {
 }
 
 struct BwdWs {
-  size_t g2d, touched, pose, order, bytes;
+  size_t g2d, touched, pose, bytes;
 };
 static BwdWs bwd_ws_layout(const gs_ctx* ctx, const ViewTab& tab) {
   BwdWs L;
@@ -214,7 +214,6 @@ static BwdWs bwd_ws_layout(const gs_ctx* ctx, const ViewTab& tab) {
   L.g2d = o; o += al256((size_t)tab.nrec * 10 * 4 * (size_t)ctx->bwd_copies);
   L.touched = o; o += al256((size_t)tab.nrec);
   L.pose = o; o += al256((size_t)tab.nv * bwd_pose_blocks(tab) * 6 * 4 + 4);
-  L.order = o; o += al256((size_t)tab.ntiles * 4);
   L.bytes = o;
   return L;
 }
@@ -358,7 +357,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   char* w = (char*)ws;
   hipStream_t s = (hipStream_t)stream;
   GS_TRY(launch_render_bwd_tiles(ctx, tab, proj, bins, img, pg, bg, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
-                                 (uint32_t*)(w + L.order), s));
+                                 s));
   return launch_bwd_project(ctx, tab, views->cams_dev, g, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
                             (float*)(w + L.pose), gr, s);
 }

@@ -187,7 +187,7 @@ gs_status launch_bin_sort(gs_ctx*, const ViewTab&, const BinTab&, const gs_proj*
 gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const float*, int, gs_image*,
                             hipStream_t);
 gs_status launch_render_bwd_tiles(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const gs_image*,
-                                  const gs_pixel_grads*, const float*, float*, uint8_t*, uint32_t*, hipStream_t);
+                                  const gs_pixel_grads*, const float*, float*, uint8_t*, hipStream_t);
 gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, float*, uint8_t*,
                              float*, gs_grads*, hipStream_t);
 int bwd_pose_blocks(const ViewTab&);

@@ -71,7 +71,15 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
   __shared__ uint8_t s_mask[BATCH];
   __shared__ uint32_t s_wmax[GS_BLOCK / 64];
   if (*overflow) return;
-  const int t = blockIdx.x;
+  // Launch order: the one the last gs_render_bwd dealt for this tile count
+  // (second half of the scheduling state, valid while its marker matches),
+  // else the natural order. Any stored order is a permutation of the tiles.
+  int t = blockIdx.x;
+  if (tile_work) {
+    const uint32_t ntl = (uint32_t)tab.ntiles;
+    const uint32_t mark = tile_work[2 * (int64_t)ntl], cand = tile_work[ntl + blockIdx.x];
+    if (mark == ntl + 1u && cand < ntl) t = (int)cand;
+  }
   const TileCtx tc = tile_ctx(tab, t);
   const int w = threadIdx.x >> 6, lane = __lane_id();
   if (threadIdx.x == 0) {
@@ -216,7 +224,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
 // round. While the whole grid is resident, blocks b and b + n_cu share a
 // compute unit, so this snake deal evens the work per unit; with more blocks
 // than fit, the heaviest tiles still start first. order[b] is the tile block b
-// runs; every tile appears once.
+// runs; every tile appears once; order[n] = n + 1 marks it complete.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 2048;
 constexpr int kOrderCached = 16384;  // tiles whose buckets stay in LDS
@@ -264,6 +272,7 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_
     const uint32_t mk = min(c, n - k * c);
     order[k * c + ((k & 1) ? mk - 1 - i : i)] = (uint32_t)t;
   }
+  if (tid == 0) order[n] = n + 1u;  // marks the order valid for n tiles
 }
 
 // Backward over one tile. g2d holds per record ten values
@@ -712,7 +721,7 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
 
 gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj, const gs_bins* bins,
                                   const gs_image* img, const gs_pixel_grads* pg, const float* bg, float* g2d,
-                                  uint8_t* touched, uint32_t* order_ws, hipStream_t s) {
+                                  uint8_t* touched, hipStream_t s) {
   if (tab.ntiles == 0) return GS_OK;
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
   const float4* rec = (const float4*)proj->rec;
@@ -724,9 +733,10 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
         return gs_fail(ctx, GS_E_HIP, "cannot query the compute-unit count");
       ctx->n_cu = n;
     }
+    uint32_t* ord = img->tile_work + tab.ntiles;  // second half of the scheduling state
     GS_LAUNCH(ctx, tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, img->tile_work, (int)tab.ntiles,
-              ctx->n_cu, order_ws);
-    order = order_ws;
+              ctx->n_cu, ord);
+    order = ord;
   }
 #define GS_BWD(BATCH)                                                                                          \
   if (ctx->bwd_mfma)                                                                                           \

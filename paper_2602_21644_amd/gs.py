@@ -459,7 +459,9 @@ class Pipeline:
         self.img_mp = torch.empty(P, dtype=f32, device=dev)
         self.img_T = torch.empty(P, dtype=f32, device=dev)
         self.img_nlast = torch.empty(P, dtype=i32, device=dev)
-        self.img_tile_work = torch.empty(T, dtype=i32, device=dev)
+        # tile scheduling state: per-tile work, then the launch order and its
+        # marker (zero-filled: no order yet)
+        self.img_tile_work = torch.zeros(2 * T + 1, dtype=i32, device=dev)
         self.img = Image(ptr(self.img_color), ptr(self.img_depth), ptr(self.img_mp), ptr(self.img_T),
                          ptr(self.img_nlast), ptr(self.img_tile_work))
         self.dC = torch.empty(3 * P, dtype=f32, device=dev)

@@ -84,11 +84,8 @@ def assert_grads_close(gpu, ref, rel=1e-3, name=""):
 
 
 def bwd_zero_part(pipe, views):
-    """The part of the backward scratch every call leaves zero-filled: all but
-    its tail, where the tile launch order is kept (4 bytes per tile, rounded
-    up to 256)."""
-    order_bytes = (views.tile_count * 4 + 255) // 256 * 256
-    return pipe.ws_bwd[:-order_bytes]
+    """The backward scratch, which every call leaves zero-filled."""
+    return pipe.ws_bwd
 
 
 def torch_np(t):
