@@ -432,35 +432,53 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     // records never includes this batch's atomics.
     constexpr int kLoadThreads = (BATCH + 63) / 64 * 64;
     static_assert(kLoadThreads < GS_BLOCK, "some wave must be free of loads");
-    for (int q = tid - kLoadThreads; q >= 0 && q < n * 10; q += GS_BLOCK - kLoadThreads) {
-      const int jj = q / 10, c = q - jj * 10;
-      // moment index -> (row, slot) of wave_sum10's output
-      auto mom = [&](int m) {
-        const int row = m < 5 ? (m & 1) : 2 + ((m - 5) & 1);
-        const int sl = m < 5 ? (m >> 1) : ((m - 5) >> 1);
-        float acc = 0.f;
+    // one thread per entry: all sixteen row totals in one LDS round trip,
+    // then the entry's ten gradient components and their atomics
+    static_assert(GS_BLOCK - kLoadThreads >= BATCH, "a thread per entry");
+    const int q = tid - kLoadThreads;
+    if (q >= 0 && q < n) {
+      const int jj = q;
+      float4 rw[4][4];
 #pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
-          const float4 x = s_red[jj][ww * 4 + row];
-          acc += sl == 0 ? x.x : (sl == 1 ? x.y : x.z);
-        }
-        return acc;
-      };
-      const float o = s_a[jj].w;
-      float gval;
-      if (c < 2) {
-        // back from base-2 exponent units to the conic
-        const float4 B = s_b[jj];
-        const float k1 = B.x * (-2.0f / GS_LOG2E), k2 = B.y * (-1.0f / GS_LOG2E), k3 = B.z * (-2.0f / GS_LOG2E);
-        const float s0 = mom(0), s1 = mom(1);
-        gval = c == 0 ? -o * (k1 * s0 + k2 * s1) : -o * (k2 * s0 + k3 * s1);
-      } else if (c == 2 || c == 4) {
-        gval = -0.5f * o * mom(c);
-      } else if (c == 3) {
-        gval = -o * mom(3);
-      } else {
-        gval = mom(c);
+      for (int ww = 0; ww < 4; ++ww)
+#pragma unroll
+        for (int row = 0; row < 4; ++row) rw[ww][row] = s_red[jj][ww * 4 + row];
+      float4 t0 = rw[0][0], t1 = rw[0][1], t2 = rw[0][2], t3 = rw[0][3];
+#pragma unroll
+      for (int ww = 1; ww < 4; ++ww) {
+        t0.x += rw[ww][0].x; t0.y += rw[ww][0].y; t0.z += rw[ww][0].z;
+        t1.x += rw[ww][1].x; t1.y += rw[ww][1].y;
+        t2.x += rw[ww][2].x; t2.y += rw[ww][2].y; t2.z += rw[ww][2].z;
+        t3.x += rw[ww][3].x; t3.y += rw[ww][3].y;
       }
+      // wave_sum10's rows: (m0, m2, m4), (m1, m3, -), (m5, m7, m9), (m6, m8, -)
+      const float m0 = t0.x, m2 = t0.y, m4 = t0.z, m1 = t1.x, m3 = t1.y;
+      const float m5 = t2.x, m7 = t2.y, m9 = t2.z, m6 = t3.x, m8 = t3.y;
+      const float o = s_a[jj].w;
+      const float4 B = s_b[jj];
+      // back from base-2 exponent units to the conic
+      const float k1 = B.x * (-2.0f / GS_LOG2E), k2 = B.y * (-1.0f / GS_LOG2E), k3 = B.z * (-2.0f / GS_LOG2E);
+      float gv[10];
+      gv[0] = -o * (k1 * m0 + k2 * m1);
+      gv[1] = -o * (k2 * m0 + k3 * m1);
+      gv[2] = -0.5f * o * m2;
+      gv[3] = -o * m3;
+      gv[4] = -0.5f * o * m4;
+      gv[5] = m5;
+      gv[6] = m6;
+      gv[7] = m7;
+      gv[8] = m8;
+      gv[9] = m9;
+      // back into the entry's first three slots (this thread read them)
+      s_red[jj][0] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+      s_red[jj][1] = make_float4(gv[4], gv[5], gv[6], gv[7]);
+      s_red[jj][2] = make_float4(gv[8], gv[9], 0.f, 0.f);
+    }
+    __syncthreads();
+    // ten adjacent threads per entry: a wave's atomics fall on few lines
+    for (int qq = tid - kLoadThreads; qq >= 0 && qq < n * 10; qq += GS_BLOCK - kLoadThreads) {
+      const int jj = qq / 10, c = qq - jj * 10;
+      const float gval = reinterpret_cast<const float*>(&s_red[jj][0])[c];
       if (gval != 0.f) {
         const uint32_t r = s_r[jj];
         atomicAdd(&g2d[(int64_t)r * 10 + c], gval);
