@@ -39,10 +39,10 @@ FLOPS_PER_PAIR = {"render_fwd_kernel": 28, "render_bwd_kernel": 54}
 # the counters are scaled by what they read for a 256 MiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0)
 PMC_TRAFFIC = {
-    "render_bwd_kernel<64>": {"fetch_kib": 9955.3, "write_kib": 5612.2,
-                              "sha256": "ac6119f8900c19174229d2016b942a5d8246e45c8b4d43795f462286f462333a"},
-    "render_bwd_kernel<32>": {"fetch_kib": 10032.4, "write_kib": 5607.6,
-                              "sha256": "ac6119f8900c19174229d2016b942a5d8246e45c8b4d43795f462286f462333a"},
+    "render_bwd_kernel<64>": {"fetch_kib": 10036.6, "write_kib": 5588.3,
+                              "sha256": "f0220062d2640297513da3c689a62b98018908e3448be24fbd6cb0a8e13bee88"},
+    "render_bwd_kernel<32>": {"fetch_kib": 10019.2, "write_kib": 5588.8,
+                              "sha256": "f0220062d2640297513da3c689a62b98018908e3448be24fbd6cb0a8e13bee88"},
 }
 PMC_SCALE = {"fetch": 2.0, "write": 1.0}
 
