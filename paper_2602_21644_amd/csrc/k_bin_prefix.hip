@@ -18,11 +18,14 @@
 //   psort:  one 1024-thread workgroup per view gathers the segments into
 //           registers, sorts them on (key, id) in LDS (counting pass on the top
 //           12 bits of the key range, then each record's rank inside its
-//           bucket), writes the sorted ids and rects, and counts the instances
-//           of every tile with a 2D difference array;
+//           bucket), writes the sorted ids and rects and the view's instance
+//           total (the sum of the rect areas);
 //   ptiles: a workgroup per 2x2 block of tiles keeps, in order, the sorted
-//           records that meet the block (in LDS), then one wave per tile
-//           appends the ids that cover its tile.
+//           records that meet the block (in LDS) and finds where each of its
+//           tile lists starts: the instances in front of tile t in row-major
+//           order, summed over the records in closed form (rows of the rect
+//           above t times its width, plus its columns left of t in t's row).
+//           Then one wave per tile appends the ids that cover its tile.
 // A view whose selection exceeds PS_CAP records gets empty lists and raises
 // `incomplete`.
 #include "bin_common.h"
@@ -38,12 +41,9 @@ constexpr int PS_CAP = 12288;                   // selected records per view
 constexpr int PS_PER = PS_CAP / PS_THREADS;
 constexpr int PS_BUCKETS = 4096;
 constexpr int PS_MAXBLK = 4096;                 // selection blocks per view (8.4M records)
-constexpr int PS_MAXCELLS = 4096;               // (gx + 1) * (gy + 1), enforced by the view table
 // dynamic LDS of psort: keys and ids grouped by bucket, bucket cursors, and
-// the block offsets (later the bucket starts); the difference array reuses
-// the key buffer
+// the block offsets (later the bucket starts)
 constexpr size_t PS_LDS = (size_t)PS_CAP * 8 + (size_t)PS_BUCKETS * 4 + (size_t)(PS_MAXBLK + 1) * 4;
-static_assert(PS_MAXCELLS <= PS_CAP, "difference array must fit the key buffer");
 static_assert(PS_BUCKETS == 4 * PS_THREADS && PS_MAXBLK == 4 * PS_THREADS, "4 entries per thread");
 
 __device__ __forceinline__ int sel_blocks(int64_t npad) { return (int)((npad + SEL_TILE - 1) / SEL_TILE); }
@@ -165,19 +165,18 @@ __device__ __forceinline__ uint32_t block1024_excl(uint32_t x, uint32_t* s_w /*[
 __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     ViewTab tab, int nb_max, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ seg_key,
     const uint32_t* __restrict__ seg_id, const int2* __restrict__ seg_rect, uint32_t* __restrict__ hist,
-    uint32_t* __restrict__ sorted_ids, int2* __restrict__ srect, uint32_t* __restrict__ lstart,
-    uint32_t* __restrict__ view_total, uint32_t* __restrict__ nsel_out, int32_t* __restrict__ incomplete) {
+    uint32_t* __restrict__ sorted_ids, int2* __restrict__ srect, uint32_t* __restrict__ view_total,
+    uint32_t* __restrict__ nsel_out, int32_t* __restrict__ incomplete) {
   extern __shared__ uint32_t s_dyn[];
   uint32_t* gk = s_dyn;              // [PS_CAP] keys grouped by bucket; later the difference array
   uint32_t* gi = gk + PS_CAP;        // [PS_CAP] ids
   uint32_t* cur = gi + PS_CAP;       // [PS_BUCKETS] bucket cursors
   uint32_t* bst = cur + PS_BUCKETS;  // [PS_MAXBLK + 1] block offsets, then bucket starts
   __shared__ uint32_t s_w[PS_THREADS / 64];
-  __shared__ uint32_t s_min, s_max;
+  __shared__ uint32_t s_min, s_max, s_area;
   const int v = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t roff = tab.r_off[v];
-  const int gx = tab.gx[v], gy = tab.gy[v], T = gx * gy;
   const int nb = sel_blocks(tab.npad[v]);
   // 1. offsets of the block segments
   uint32_t c4[4], s4 = 0;
@@ -198,12 +197,12 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     bst[PS_MAXBLK] = n;
     s_min = 0xFFFFFFFFu;
     s_max = 0u;
+    s_area = 0u;
   }
   for (int i = tid; i < HB; i += PS_THREADS) hist[(int64_t)v * HB + i] = 0;  // consumed
   __syncthreads();
   if (n > (uint32_t)PS_CAP) {
     // too many records in front of the threshold for this path: empty lists
-    for (int t = tid; t < T; t += PS_THREADS) lstart[tab.tile_base[v] + t] = 0;
     if (tid == 0) {
       view_total[v] = 0;
       nsel_out[v] = 0;
@@ -237,22 +236,27 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     ir[q] = adr[q] >= 0 ? seg_id[adr[q]] : 0u;
     rr[q] = adr[q] >= 0 ? seg_rect[adr[q]] : make_int2(1 | (1 << 16), 0);
   }
-  uint32_t lmin = 0xFFFFFFFFu, lmax = 0u;
+  uint32_t lmin = 0xFFFFFFFFu, lmax = 0u, larea = 0u;
 #pragma unroll
   for (int q = 0; q < PS_PER; ++q) {
     if (adr[q] >= 0) {
       lmin = min(lmin, kr[q]);
       lmax = max(lmax, kr[q]);
+      int x0, y0, x1, y1;
+      rect_of(rr[q], x0, y0, x1, y1);
+      larea += (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
     }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, o, 64));
     lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, o, 64));
+    larea += (uint32_t)__shfl_xor((int)larea, o, 64);
   }
   if (__lane_id() == 0) {
     atomicMin(&s_min, lmin);
     atomicMax(&s_max, lmax);
+    atomicAdd(&s_area, larea);
   }
   for (int i = tid; i < PS_BUCKETS; i += PS_THREADS) cur[i] = 0;
   __syncthreads();
@@ -322,59 +326,33 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
   }
   __syncthreads();
   for (uint32_t i = tid; i < n; i += PS_THREADS) srect[roff + i] = make_int2((int)gk[i], (int)gi[i]);
-  __syncthreads();
-  // 5. instances per tile: 2D difference array of the rects, integrated
-  int* dif = (int*)gk;
-  const int cells = (gx + 1) * (gy + 1);
-  for (int i = tid; i < cells; i += PS_THREADS) dif[i] = 0;
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PS_PER; ++q) {
-    if ((uint32_t)(q * PS_THREADS + tid) < n) {
-      int x0, y0, x1, y1;
-      rect_of(rr[q], x0, y0, x1, y1);
-      diff_add(dif, gx + 1, x0, y0, x1, y1);
-    }
-  }
-  __syncthreads();
-  diff_integrate(dif, gx, gy, tid >> 6, PS_THREADS / 64);
-  // 6. local exclusive offsets of the tile lists (T < 4096: 4 tiles per thread)
-  s4 = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int t = tid * 4 + q;
-    c4[q] = 0u;
-    if (t < T) {
-      const int ty = t / gx, tx = t - ty * gx;
-      c4[q] = (uint32_t)dif[ty * (gx + 1) + tx];
-    }
-    s4 += c4[q];
-  }
-  run = block1024_excl(s4, s_w, tot);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int t = tid * 4 + q;
-    if (t < T) lstart[tab.tile_base[v] + t] = run;
-    run += c4[q];
-  }
   if (tid == 0) {
-    view_total[v] = tot;
+    view_total[v] = s_area;
     nsel_out[v] = n;
   }
+}
+
+// Instances of a record's rect [x0, x1] x [y0, y1] that come before tile
+// (tx, ty) in row-major tile order: its full rows above ty, plus its columns
+// left of tx when row ty crosses the rect.
+__device__ __forceinline__ uint32_t rect_before(int x0, int y0, int x1, int y1, int tx, int ty) {
+  const int rows = max(0, min(ty, y1 + 1) - y0);
+  const int cols = (y0 <= ty && ty <= y1) ? max(0, min(tx, x1 + 1) - x0) : 0;
+  return (uint32_t)(rows * (x1 - x0 + 1) + cols);
 }
 
 // A 256-thread workgroup per 2x2 block of tiles of one view. The 4 waves
 // split the view's depth-sorted selection into 4 consecutive segments and
 // keep, in order, the records whose rect meets the block, each packed with the
-// 4-bit mask of the block's tiles it covers in the top bits of its id. Then
-// wave w builds the list of tile w of the block from the kept records.
+// 4-bit mask of the block's tiles it covers in the top bits of its id; on the
+// way they sum, for each tile of the block, the instances in front of it.
+// Then wave w builds the list of tile w of the block from the kept records.
 constexpr int PT_THREADS = 256;
 constexpr int PT_ROUND = 12;  // loads in flight per lane and array
 static_assert(PS_CAP % 4 == 0 && (PS_CAP / 4) % 64 == 0, "wave segments are whole 64-record groups");
 
 __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const uint32_t* __restrict__ view_total,
                                                             const uint32_t* __restrict__ nsel,
-                                                            const uint32_t* __restrict__ lstart,
                                                             const uint32_t* __restrict__ sorted_ids,
                                                             const int2* __restrict__ srect, int64_t capacity,
                                                             uint32_t* __restrict__ tile_start,
@@ -383,6 +361,7 @@ __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const u
                                                             int32_t* __restrict__ overflow) {
   __shared__ uint32_t s_keep[PS_CAP];
   __shared__ uint32_t s_cnt[4];
+  __shared__ uint32_t s_front[4][4];  // [wave][tile of the block]
   const int v = blockIdx.y;
   const int gx = tab.gx[v], gy = tab.gy[v];
   const int nbx = (gx + 1) >> 1, nby = (gy + 1) >> 1;
@@ -398,6 +377,7 @@ __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const u
   const uint32_t s0 = (uint32_t)w * L, s1 = min(n, s0 + L);
   uint32_t* keep = s_keep + s0;
   uint32_t kept = 0;
+  uint32_t front[4] = {0u, 0u, 0u, 0u};
   for (uint32_t r0 = s0; r0 < s1; r0 += PT_ROUND * 64) {
     int2 rc[PT_ROUND];
     uint32_t idv[PT_ROUND];
@@ -422,9 +402,20 @@ __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const u
       const uint64_t m = __ballot(mk != 0);
       if (mk) keep[kept + __popcll(m & lmask)] = mk << 28 | idv[u];
       kept += (uint32_t)__popcll(m);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) front[k] += rect_before(x0, y0, x1, y1, X0 + (k & 1), Y0 + (k >> 1));
     }
   }
-  if (lane == 0) s_cnt[w] = kept;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) front[k] += (uint32_t)__shfl_xor((int)front[k], o, 64);
+  }
+  if (lane == 0) {
+    s_cnt[w] = kept;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_front[w][k] = front[k];
+  }
   __syncthreads();
   // 2. wave w builds the list of tile (X0 + w % 2, Y0 + w / 2)
   const int tx = X0 + (w & 1), ty = Y0 + (w >> 1);
@@ -438,9 +429,7 @@ __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const u
     before += (uint32_t)__shfl_xor((int)before, o, 64);
     all += (uint32_t)__shfl_xor((int)all, o, 64);
   }
-  const uint32_t l0 = lstart[t];
-  const uint32_t l1 = lt + 1 < gx * gy ? lstart[t + 1] : view_total[v];
-  const uint32_t start = before + l0;
+  const uint32_t start = before + s_front[0][w] + s_front[1][w] + s_front[2][w] + s_front[3][w];
   const bool ovf = (int64_t)all > capacity;
   if (lane == 0) tile_start[t] = start;
   if (t == tab.ntiles - 1 && lane == 0) {
@@ -448,7 +437,7 @@ __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const u
     *n_inst = all;
     *overflow = ovf ? 1 : 0;
   }
-  if (ovf || l1 == l0) return;
+  if (ovf) return;
   uint32_t* out = out_ids + start;
   const int bit = 28 + w;
   uint32_t got = 0;
@@ -479,7 +468,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ host side
 struct PrefWs {
-  size_t cnt, seg_key, seg_id, seg_rect, srect, lstart, vtot, nsel, bytes;
+  size_t cnt, seg_key, seg_id, seg_rect, srect, vtot, nsel, bytes;
   int nb_max;
 };
 
@@ -495,7 +484,6 @@ static PrefWs pref_layout(const ViewTab& tab) {
   L.seg_id = o; o += al256(M * 4);
   L.seg_rect = o; o += al256(M * 8);
   L.srect = o; o += al256(M * 8);
-  L.lstart = o; o += al256((size_t)tab.ntiles * 4 + 4);
   L.vtot = o; o += al256(4 * GS_MAX_VIEWS);
   L.nsel = o; o += al256(4 * GS_MAX_VIEWS);
   L.bytes = o;
@@ -550,18 +538,16 @@ gs_status launch_bin_prefix(gs_ctx* ctx, const ViewTab& tab, const gs_camera* ca
   uint32_t* seg_id = (uint32_t*)(ws + L.seg_id);
   int2* seg_rect = (int2*)(ws + L.seg_rect);
   int2* srect = (int2*)(ws + L.srect);
-  uint32_t* lstart = (uint32_t*)(ws + L.lstart);
   uint32_t* vtot = (uint32_t*)(ws + L.vtot);
   uint32_t* nsel = (uint32_t*)(ws + L.nsel);
   GS_LAUNCH(ctx, psel_kernel, dim3(L.nb_max, tab.nv), dim3(GS_BLOCK), 0, s, tab, proj->depth_key, proj->key_hist,
             (const int2*)proj->rect, bins->max_rank, L.nb_max, cams, gsrc, (float4*)proj->rec, seg_key, seg_id,
             seg_rect, cnt, bins->overflow, bins->incomplete);
   GS_LAUNCH(ctx, psort_kernel, dim3(tab.nv), dim3(PS_THREADS), PS_LDS, s, tab, L.nb_max, cnt, seg_key, seg_id,
-            seg_rect, proj->key_hist, bins->sorted_ids, srect, lstart, vtot, nsel, bins->incomplete);
+            seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete);
   int nblk = 1;
   for (int v = 0; v < tab.nv; ++v) nblk = max(nblk, ((tab.gx[v] + 1) >> 1) * ((tab.gy[v] + 1) >> 1));
-  GS_LAUNCH(ctx, ptiles_kernel, dim3(nblk, tab.nv), dim3(PT_THREADS), 0, s, tab, vtot, nsel, lstart,
-            bins->sorted_ids, srect, bins->capacity, bins->tile_start, bins->gauss_id, bins->n_instances,
+  GS_LAUNCH(ctx, ptiles_kernel, dim3(nblk, tab.nv), dim3(PT_THREADS), 0, s, tab, vtot, nsel, bins->sorted_ids, srect, bins->capacity, bins->tile_start, bins->gauss_id, bins->n_instances,
             bins->overflow);
   return gs_check_launch(ctx, "bin_sort (prefix)");
 }
