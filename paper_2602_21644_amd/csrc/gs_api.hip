@@ -50,6 +50,7 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->wave_cull = 1;
   c->bwd_mfma = 0;
   c->n_cu = 0;
+  c->proj_resident = 0;
   c->lds_limit = 0;
   c->err[0] = 0;
   *out = c;
@@ -208,12 +209,12 @@ static gs_status make_tab(gs_ctx* ctx, const gs_views* vw, ViewTab& tab) {
 struct BwdWs {
   size_t g2d, touched, pose, bytes;
 };
-static BwdWs bwd_ws_layout(const gs_ctx* ctx, const ViewTab& tab) {
+static BwdWs bwd_ws_layout(gs_ctx* ctx, const ViewTab& tab) {
   BwdWs L;
   size_t o = 0;
   L.g2d = o; o += al256((size_t)tab.nrec * 10 * 4 * (size_t)ctx->bwd_copies);
   L.touched = o; o += al256((size_t)tab.nrec);
-  L.pose = o; o += al256((size_t)tab.nv * bwd_pose_blocks(tab) * 6 * 4 + 4);
+  L.pose = o; o += al256((size_t)tab.nv * bwd_pose_stride(ctx, tab) * 6 * 4);
   L.bytes = o;
   return L;
 }

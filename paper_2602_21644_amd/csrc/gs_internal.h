@@ -147,6 +147,7 @@ struct gs_ctx {
   int wave_cull;                 // 1: each wave skips the entries that cannot reach its 16x4 strip
   int bwd_mfma;                  // 1: the backward forms its per-entry sums on the matrix cores
   int n_cu;                      // compute units of the device (0: not queried yet)
+  int proj_resident;             // bwd_project blocks the device holds at once (0: not queried yet)
   size_t lds_limit;              // LDS per workgroup usable by the binning scatter (0: not queried)
   std::vector<GsTimer> pending;  // launches whose events are not read yet
   char err[512];
@@ -190,7 +191,8 @@ gs_status launch_render_bwd_tiles(gs_ctx*, const ViewTab&, const gs_proj*, const
                                   const gs_pixel_grads*, const float*, float*, uint8_t*, hipStream_t);
 gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, float*, uint8_t*,
                              float*, gs_grads*, hipStream_t);
-int bwd_pose_blocks(const ViewTab&);
+int bwd_pose_blocks(gs_ctx*, const ViewTab&);
+int bwd_pose_stride(gs_ctx*, const ViewTab&);  // row stride of the per-block pose partials, a multiple of 4
 int loss_blocks(const ViewTab&);
 gs_status launch_loss(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_loss_params*, float*,
                       gs_pixel_grads*, double*, hipStream_t);

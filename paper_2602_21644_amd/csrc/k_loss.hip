@@ -67,13 +67,21 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_kernel(ViewTab tab, const float
 }
 
 // Sums the per-block partials of a view in a fixed order (one workgroup per
-// view).
+// view); each thread has eight loads in flight before it sums them.
+constexpr int kLossUnroll = 8;
 __global__ __launch_bounds__(GS_BLOCK) void loss_final_kernel(const double* __restrict__ part, int nblk,
                                                               float* __restrict__ loss) {
   __shared__ double s[GS_BLOCK / 64];
   const int v = blockIdx.x;
+  const double* pv = part + (int64_t)v * nblk;
   double t = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += GS_BLOCK) t += part[(int64_t)v * nblk + b];
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += kLossUnroll * GS_BLOCK) {
+    double x[kLossUnroll];
+#pragma unroll
+    for (int u = 0; u < kLossUnroll; ++u) x[u] = b0 + u * GS_BLOCK < nblk ? pv[b0 + u * GS_BLOCK] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kLossUnroll; ++u) t += x[u];
+  }
   t = wave_sum_to_lane63_d(t);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = t;
   __syncthreads();
