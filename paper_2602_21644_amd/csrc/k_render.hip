@@ -492,21 +492,29 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
 // The same backward with the per-entry moment sums on the matrix cores.
 //
 // The ten sums over a wave's 64 pixels are a product (entries x pixels) x
-// (pixels x features): with tile-local pixel coordinates (lx, ly) and
-// d = u - pixel = (ux_l - lx, uy_l - ly), u_l the entry's tile-local mean,
-//   sum h d_x   = ux_l S0 - S1,   sum h d_y = uy_l S0 - S2,
-//   sum h d_x^2 = ux_l^2 S0 - 2 ux_l S1 + S3,
-//   sum h d_x d_y = ux_l uy_l S0 - ux_l S2 - uy_l S1 + S4,
-//   sum h d_y^2 = uy_l^2 S0 - 2 uy_l S2 + S5,
+// (pixels x features). With pixel coordinates (lx, ly) relative to the tile
+// centre and the entry's mean u relative to it, d = u - (lx, ly), so
+//   sum h d_x   = u_x S0 - S1,   sum h d_y = u_y S0 - S2,
+//   sum h d_x^2 = u_x^2 S0 - 2 u_x S1 + S3,
+//   sum h d_x d_y = u_x u_y S0 - u_x S2 - u_y S1 + S4,
+//   sum h d_y^2 = u_y^2 S0 - 2 u_y S2 + S5,
 // where S = sum_p h_p (1, lx, ly, lx^2, lx ly, ly^2); the colour and depth
-// sums are sum_p w_p (g_r, g_g, g_b, g_D). Each wave takes the entries in
-// groups of 16: every lane computes h and w of its pixel for the 16 entries
-// (the transmittance recursion is unchanged), h goes to an LDS tile [entry]
-// [pixel], and 16 v_mfma_f32_16x16x4f32 steps multiply it by the per-pixel
-// features (step s, lane group k: pixel 16k + s of the wave); then w replaces
-// h in the same tile for the colour and depth features. The accumulator
-// holds D[entry][feature]; the cross-wave pass adds the four waves, expands
-// the sums into the moments about u and applies opacity and conic as before.
+// sums are sum_p w_p (g_r, g_g, g_b, g_D). Each wave takes, back to front,
+// the batch's entries below its largest n_last whose alpha >= 1/255 box meets
+// its 16x4 strip (the forward's strip test; the others composite none of its
+// pixels), gathered 16 at a time from a ballot. Every lane runs the
+// transmittance recursion of its pixel over the group branch-free (slots past
+// the last entry read a zero record; invalid entries leave T and the suffix
+// term unchanged),
+// storing h and w to two LDS tiles [entry][pixel]; then 16
+// v_mfma_f32_16x16x4f32 steps multiply the h tile by the per-pixel features
+// (step s, lane group k: pixel 16k + s of the wave) and 16 more the w tile
+// by the colour and depth features, skipped when no entry of the group
+// composites a pixel of the wave. The accumulators hold D[slot][feature];
+// the per-entry sums start at zero each batch, so entries a wave skips count
+// zero for it; the cross-wave pass adds the four waves, expands the sums
+// into moments about the entry's mean and applies opacity and conic as the
+// wave reduction path does.
 typedef float gs_floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kGroup = 16;
 constexpr int kRow = 64 + 4;  // pixels per LDS row, padded across banks
@@ -517,12 +525,15 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
     const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
     const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
-    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies) {
-  static_assert(BATCH % kGroup == 0, "a batch holds whole groups");
-  __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
+    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies,
+    int cull) {
+  static_assert(BATCH % 64 == 0 || BATCH < 64, "entries are gathered in windows of 64");
+  // slot BATCH is a zero record for the slots past the last entry
+  __shared__ float4 s_a[BATCH + 1], s_b[BATCH + 1], s_c[BATCH + 1];
   __shared__ uint32_t s_r[BATCH];
-  __shared__ float s_t[GS_BLOCK / 64][kGroup][kRow];  // per wave: h, then w, of a group
-  __shared__ float4 s_dm[BATCH][10];                  // per entry and sum: the four waves' values
+  __shared__ uint8_t s_mask[BATCH];
+  __shared__ float s_t[GS_BLOCK / 64][2][kGroup][kRow];  // per wave: the h and w tiles of a group
+  __shared__ float4 s_dm[BATCH][10];                  // [entry][sum]: the four waves' values
   __shared__ uint32_t s_max;
   if (*overflow) return;
   const uint32_t tu = order ? order[blockIdx.x] : blockIdx.x;
@@ -537,10 +548,17 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
   // accumulator of the XCD the workgroup runs on, as in render_bwd_kernel
   if (copies > 1) g2d += (int64_t)(__builtin_amdgcn_s_getreg((31 << 11) | 20) & (uint32_t)(copies - 1)) * 10 * M;
   const float fx = (float)tc.px, fy = (float)tc.py;
-  const float x0 = (float)(tc.tx * GS_TILE), y0 = (float)(tc.ty * GS_TILE);
+  constexpr float kHalf = 0.5f * (GS_TILE - 1);  // tile centre in pixel units from its first pixel
+  const float cx = (float)(tc.tx * GS_TILE) + kHalf, cy = (float)(tc.ty * GS_TILE) + kHalf;
   float T = 1.f, gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gd = 0.f, gm = 0.f, Tbar = 0.f;
   uint32_t nl = 0;
-  if (threadIdx.x == 0) s_max = 0;
+  if (threadIdx.x == 0) {
+    s_max = 0;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    s_a[BATCH] = z;
+    s_b[BATCH] = z;
+    s_c[BATCH] = z;
+  }
   __syncthreads();
   if (tc.inside) {
     T = imgT[tc.pix];
@@ -557,15 +575,15 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, o, 64));
   if (lane == 0) atomicMax(&s_max, wmax);
-  // B operands of the matrix steps: lane (k = lane >> 4, j = lane & 15) at
-  // step s supplies feature j of the wave's pixel 16k + s (lx = s, ly = 4w + k)
+  // B operands: lane (k = lane >> 4, j = lane & 15) at step s supplies feature
+  // j of the wave's pixel 16k + s (lx = s, ly = 4w + k, both from the centre)
   const int mk = lane >> 4, mj = lane & 15;
   float bphi[kGroup], bpsi[kGroup];
   {
-    const float ly = (float)(4 * w + mk);
+    const float ly = (float)(4 * w + mk) - kHalf;
 #pragma unroll
     for (int st = 0; st < kGroup; ++st) {
-      const float lx = (float)st;
+      const float lx = (float)st - kHalf;
       bphi[st] = mj == 0 ? 1.f : mj == 1 ? lx : mj == 2 ? ly : mj == 3 ? lx * lx : mj == 4 ? lx * ly
                  : mj == 5 ? ly * ly : 0.f;
       const int src = 16 * mk + st;
@@ -589,7 +607,10 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
     }
     if (tid < lo0 - lo1) idn = ids[b + lo1 + tid];
   }
-  float* rowp = &s_t[w][0][0];
+  float* rowh = &s_t[w][0][0][0];
+  float* roww = &s_t[w][1][0][0];
+  const float* arow = rowh + mj * kRow + 16 * mk;
+  const float* brow = roww + mj * kRow + 16 * mk;
   for (int hi = (int)maxl; hi > 0; hi -= BATCH) {
     const int lo = max(0, hi - BATCH);
     const int n = hi - lo;
@@ -599,7 +620,9 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
       s_a[tid] = ra;
       s_b[tid] = rb;
       s_c[tid] = rc;
+      s_mask[tid] = cull ? (uint8_t)strip_mask(ra, rb, tc.tx * GS_TILE, tc.ty * GS_TILE) : (uint8_t)0xF;
     }
+    for (int i = tid; i < BATCH * 10; i += GS_BLOCK) (&s_dm[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     {
       const int lo1 = max(0, lo - BATCH), lo2 = max(0, lo1 - BATCH);
@@ -611,103 +634,115 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
       }
       if (tid < lo1 - lo2) idn = ids[b + lo2 + tid];
     }
-    for (int g0 = ((n - 1) / kGroup) * kGroup; g0 >= 0; g0 -= kGroup) {
-      float wr[kGroup];
-      bool any = false;  // some entry of the group had a valid pixel in this wave
-#pragma unroll
-      for (int e = kGroup - 1; e >= 0; --e) {
-        const int jj = g0 + e;
-        const int j = lo + jj;
-        float hv = 0.f, wv = 0.f;
-        if (jj < n && (uint32_t)j < wmax) {  // uniform over the wave
-          const float4 A = s_a[jj];
-          const float4 B = s_b[jj];
+    // entries that can reach a pixel of this wave: below its largest n_last
+    const int jtop = (uint32_t)lo < wmax ? min(n, (int)(wmax - (uint32_t)lo)) : 0;
+    for (int c0 = ((jtop - 1) >> 6) << 6; c0 >= 0; c0 -= 64) {
+      const int jl = c0 + lane;
+      uint64_t ball = __ballot(jl < jtop && ((s_mask[jl < BATCH ? jl : 0] >> w) & 1u));
+      while (ball) {
+        // the next 16 of them from the top; slot e takes entry jj (lane e
+        // keeps it), slots past the last entry the zero record
+        gs_floatx4 acc_h = {0.f, 0.f, 0.f, 0.f}, acc_w = {0.f, 0.f, 0.f, 0.f};
+        bool anyv = false;
+        int jsv = BATCH;
+#pragma unroll 4
+        for (int e = 0; e < kGroup; ++e) {
+          const int hb = 63 - __builtin_clzll(ball | 1ull);
+          const int jj = ball ? c0 + hb : BATCH;
+          ball &= ~(1ull << hb);
+          jsv = lane == e ? jj : jsv;
+          const int js_ = jj;
+          const float4 A = s_a[js_];
+          const float4 B = s_b[js_];
+          const float4 Cc = s_c[js_];
           const float dx = A.x - fx, dy = A.y - fy;
           const float p = gs_power2(B.x, B.y, B.z, dx, dy);
           const float G = __builtin_amdgcn_exp2f(p);
           const float araw = A.w * G;
           const float alpha = fminf(GS_ALPHA_MAX, araw);
-          const bool valid = (uint32_t)j < nl && p <= 0.f && alpha >= GS_ALPHA_MIN;
-          if (__ballot(valid)) {  // uniform
-            any = true;
-            const float4 Cc = s_c[jj];
-            const float a = valid ? alpha : 0.f;
-            const float one_m = 1.0f - a;
-            const float Tj = T * __builtin_amdgcn_rcpf(one_m);
-            const float vdot = gc0 * Cc.x + gc1 * Cc.y + gc2 * Cc.z + gd * A.z + gm * B.w;
-            const float abar = Tj * (vdot - Tbar);
-            wv = a * Tj;
-            hv = (valid && araw < GS_ALPHA_MAX) ? abar * G : 0.f;
-            Tbar = vdot * a + Tbar * one_m;
-            T = Tj;
-          }
+          const bool valid = (uint32_t)(lo + jj) < nl && p <= 0.f && alpha >= GS_ALPHA_MIN;
+          anyv = anyv || valid;
+          const float a = valid ? alpha : 0.f;
+          const float one_m = 1.0f - a;
+          const float Tj = T * __builtin_amdgcn_rcpf(one_m);
+          const float vdot = gc0 * Cc.x + gc1 * Cc.y + gc2 * Cc.z + gd * A.z + gm * B.w;
+          const float abar = Tj * (vdot - Tbar);
+          const float h = (valid && araw < GS_ALPHA_MAX) ? abar * G : 0.f;
+          rowh[e * kRow + lane] = h;
+          roww[e * kRow + lane] = a * Tj;
+          Tbar = vdot * a + Tbar * one_m;
+          T = Tj;
         }
-        rowp[e * kRow + lane] = hv;
-        wr[e] = wv;
-      }
-      // D[entry][feature] over the wave's pixels (zero without a valid entry)
-      gs_floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-      const float* arow = rowp + mj * kRow + 16 * mk;
-      if (any) {
+        if (__ballot(anyv)) {  // uniform
 #pragma unroll
-      for (int q = 0; q < kGroup / 4; ++q) {
-        const float4 av = *reinterpret_cast<const float4*>(arow + 4 * q);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bphi[4 * q + 0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bphi[4 * q + 1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bphi[4 * q + 2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bphi[4 * q + 3], acc, 0, 0, 0);
-      }
+          for (int q = 0; q < kGroup / 4; ++q) {
+            const float4 av = *reinterpret_cast<const float4*>(arow + 4 * q);
+            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bphi[4 * q + 0], acc_h, 0, 0, 0);
+            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bphi[4 * q + 1], acc_h, 0, 0, 0);
+            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bphi[4 * q + 2], acc_h, 0, 0, 0);
+            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bphi[4 * q + 3], acc_h, 0, 0, 0);
+          }
 #pragma unroll
-      for (int e = 0; e < kGroup; ++e) rowp[e * kRow + lane] = wr[e];
+          for (int q = 0; q < kGroup / 4; ++q) {
+            const float4 av = *reinterpret_cast<const float4*>(brow + 4 * q);
+            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bpsi[4 * q + 0], acc_w, 0, 0, 0);
+            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bpsi[4 * q + 1], acc_w, 0, 0, 0);
+            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bpsi[4 * q + 2], acc_w, 0, 0, 0);
+            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bpsi[4 * q + 3], acc_w, 0, 0, 0);
+          }
+          // lane holds D[4k + r][j]: slot 4k + r, feature j
 #pragma unroll
-      for (int q = 0; q < kGroup / 4; ++q) {
-        const float4 av = *reinterpret_cast<const float4*>(arow + 4 * q);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bpsi[4 * q + 0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bpsi[4 * q + 1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bpsi[4 * q + 2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bpsi[4 * q + 3], acc, 0, 0, 0);
-      }
-      }
-      // lane holds D[4k + r][j]: entry g0 + 4k + r, feature j
-      if (mj < 10) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int jj = g0 + 4 * mk + r;
-          if (jj < n) reinterpret_cast<float*>(&s_dm[jj][mj])[w] = acc[r];
+          for (int r = 0; r < 4; ++r) {
+            const int jj = __shfl(jsv, 4 * mk + r, 64);
+            if (mj < 10 && jj < BATCH) reinterpret_cast<float*>(&s_dm[jj][mj])[w] = acc_h[r] + acc_w[r];
+          }
         }
       }
     }
     __syncthreads();
-    // cross-wave pass on the waves that load nothing (see render_bwd_kernel)
+    // cross-wave pass on the waves that load nothing (see render_bwd_kernel):
+    // one thread per entry forms its ten components, then ten adjacent
+    // threads per entry issue the atomics
     constexpr int kLoadThreads = (BATCH + 63) / 64 * 64;
-    static_assert(kLoadThreads < GS_BLOCK, "some wave must be free of loads");
-    for (int q = tid - kLoadThreads; q >= 0 && q < n * 10; q += GS_BLOCK - kLoadThreads) {
-      const int jj = q / 10, c = q - jj * 10;
-      auto sm = [&](int f) {
+    static_assert(GS_BLOCK - kLoadThreads >= BATCH, "a thread per entry");
+    const int q = tid - kLoadThreads;
+    if (q >= 0 && q < n) {
+      const int jj = q;
+      float sm[10];
+#pragma unroll
+      for (int f = 0; f < 10; ++f) {
         const float4 v = s_dm[jj][f];
-        return (v.x + v.y) + (v.z + v.w);
-      };
-      const float4 A = s_a[jj];
-      const float o = A.w;
-      float gval;
-      if (c < 5) {
-        const float ux = A.x - x0, uy = A.y - y0;
-        const float S0 = sm(0), S1 = sm(1), S2 = sm(2);
-        if (c < 2) {
-          const float4 B = s_b[jj];
-          const float k1 = B.x * (-2.0f / GS_LOG2E), k2 = B.y * (-1.0f / GS_LOG2E), k3 = B.z * (-2.0f / GS_LOG2E);
-          const float mx = ux * S0 - S1, my = uy * S0 - S2;
-          gval = c == 0 ? -o * (k1 * mx + k2 * my) : -o * (k2 * mx + k3 * my);
-        } else if (c == 2) {
-          gval = -0.5f * o * (ux * (ux * S0 - 2.0f * S1) + sm(3));
-        } else if (c == 3) {
-          gval = -o * (ux * (uy * S0 - S2) - uy * S1 + sm(4));
-        } else {
-          gval = -0.5f * o * (uy * (uy * S0 - 2.0f * S2) + sm(5));
-        }
-      } else {
-        gval = sm(c == 5 ? 0 : c);
+        sm[f] = (v.x + v.y) + (v.z + v.w);
       }
+      const float4 A = s_a[jj];
+      const float4 B = s_b[jj];
+      const float o = A.w;
+      const float ux = A.x - cx, uy = A.y - cy;
+      const float S0 = sm[0], S1 = sm[1], S2 = sm[2];
+      const float m0 = ux * S0 - S1, m1 = uy * S0 - S2;
+      const float m2 = ux * (ux * S0 - 2.0f * S1) + sm[3];
+      const float m3 = ux * (uy * S0 - S2) - uy * S1 + sm[4];
+      const float m4 = uy * (uy * S0 - 2.0f * S2) + sm[5];
+      const float k1 = B.x * (-2.0f / GS_LOG2E), k2 = B.y * (-1.0f / GS_LOG2E), k3 = B.z * (-2.0f / GS_LOG2E);
+      float gv[10];
+      gv[0] = -o * (k1 * m0 + k2 * m1);
+      gv[1] = -o * (k2 * m0 + k3 * m1);
+      gv[2] = -0.5f * o * m2;
+      gv[3] = -o * m3;
+      gv[4] = -0.5f * o * m4;
+      gv[5] = S0;
+      gv[6] = sm[6];
+      gv[7] = sm[7];
+      gv[8] = sm[8];
+      gv[9] = sm[9];
+      s_dm[jj][0] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+      s_dm[jj][1] = make_float4(gv[4], gv[5], gv[6], gv[7]);
+      s_dm[jj][2] = make_float4(gv[8], gv[9], 0.f, 0.f);
+    }
+    __syncthreads();
+    for (int qq = tid - kLoadThreads; qq >= 0 && qq < n * 10; qq += GS_BLOCK - kLoadThreads) {
+      const int jj = qq / 10, c = qq - jj * 10;
+      const float gval = reinterpret_cast<const float*>(&s_dm[jj][0])[c];
       if (gval != 0.f) {
         const uint32_t r = s_r[jj];
         atomicAdd(&g2d[(int64_t)r * 10 + c], gval);
@@ -760,7 +795,7 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
   if (ctx->bwd_mfma)                                                                                           \
     GS_LAUNCH(ctx, render_bwd_mfma_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start, \
               bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
-              g2d, touched, order, ctx->bwd_copies);                                                           \
+              g2d, touched, order, ctx->bwd_copies, ctx->wave_cull);                                           \
   else                                                                                                         \
     GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,    \
               bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
