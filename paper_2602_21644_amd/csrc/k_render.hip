@@ -166,7 +166,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
             const bool ok = !done && p <= 0.f && alpha >= GS_ALPHA_MIN;
             const float Tn = T * (1.0f - alpha);
             const bool stop = ok && Tn < GS_T_MIN;
-            const bool add = ok && !stop;
+            const bool add = ok != stop;  // ok and not stop (stop implies ok)
             done = done || stop;
             const float wgt = add ? alpha * T : 0.f;
             C0 += wgt * Cc.x;
