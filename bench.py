@@ -97,7 +97,8 @@ def kernel_bytes(name, st):
     if name.startswith("bin_scatter_kernel"):
         return st["nlim"] * 16 + st["cm"] * 4 + I * 4
     if name.startswith("render_fwd_kernel"):
-        return st["loaded_fwd"] * 52 + P * 28
+        # with the loss fused in: targets read (16 B) and adjoints written (24 B) per pixel
+        return st["loaded_fwd"] * 52 + P * (28 + (40 if st.get("fused_loss") else 0))
     if name.startswith("loss_kernel"):
         return P * 68
     if name.startswith("render_bwd_kernel"):
@@ -167,8 +168,7 @@ def main():
     grs = gs.grads_struct(grads, pose)
 
     def step():
-        pipe.forward(gst)
-        pipe.loss_and_grads(tc, td)
+        pipe.forward_loss(gst, tc, td)
         pipe.backward(gst, grs)
 
     if a.profile_steps > 0:
@@ -210,7 +210,8 @@ def main():
     pairs = int(pipe.img_nlast.to(torch.int64).sum())  # (pixel, composited entry) pairs
     st = dict(n=a.n, instances=n_inst, pixels=P, tiles=views.tile_count, records=views.rec_count,
               nlim=views.rec_count, cm=views.tile_count * ((views.rec_count + chunk - 1) // chunk),
-              loaded_fwd=loaded_fwd, loaded_bwd=loaded_bwd, touched=touched, selected=selected, pairs=pairs)
+              loaded_fwd=loaded_fwd, loaded_bwd=loaded_bwd, touched=touched, selected=selected, pairs=pairs,
+              fused_loss=True)
     log(f"[bench] instances {n_inst}, touched Gaussians {touched}, entries loaded fwd {loaded_fwd}, "
         f"binning LDS limit {ctx.get_param('lds_limit')}")
 
@@ -405,8 +406,7 @@ def _batch_step(ctx, views, g_dev, tc, td, full=False):
     grs = gs.grads_struct(grads, pose)
 
     def step():
-        pipe.forward(gst)
-        pipe.loss_and_grads(tc, td)
+        pipe.forward_loss(gst, tc, td)
         pipe.backward(gst, grs)
 
     # the graph replays write these: they live as long as the step

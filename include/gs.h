@@ -10,7 +10,8 @@
  *
  * The calls, in the order one optimisation iteration uses them:
  *   gs_project    -> gs_bin_sort -> gs_render_fwd -> gs_loss -> gs_render_bwd
- * and once per frame gs_mp_update. The learned MP surrogate (not in the paper)
+ * (gs_render_fwd_loss does the middle two in one pass) and once per frame
+ * gs_mp_update. The learned MP surrogate (not in the paper)
  * adds gs_mlp_features / gs_mlp_fwd / gs_mlp_train_step.
  *
  * Conventions shared by every call
@@ -271,6 +272,18 @@ gs_status gs_render_fwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
 gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
                   const gs_loss_params* params /*[host]*/, float* loss, gs_pixel_grads* pg, void* ws,
                   size_t ws_bytes, void* stream);
+
+/* gs_render_fwd followed by gs_loss in one pass: the loss and the pixel
+ * adjoints are formed in the forward's epilogue from the values it writes to
+ * `img`, with the targets read while the tile composites. `img` and `pg` get
+ * exactly what the two calls would write; `loss` differs from gs_loss's only
+ * in the order of its float64 sum (one partial per tile instead of per 256
+ * pixels; still run-to-run identical). `ws` of
+ * gs_workspace_size(GS_OP_LOSS). Same errors as the two calls. */
+gs_status gs_render_fwd_loss(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                             const gs_bins* bins, const float* bg, gs_image* img, const gs_target* tgt,
+                             const gs_loss_params* params /*[host]*/, float* loss, gs_pixel_grads* pg, void* ws,
+                             size_t ws_bytes, void* stream);
 
 /* Adjoint of render + projection for the objective sum_v L_v, to all Gaussian
  * parameters and one pose twist per view (Sec. IV-D: Gaussians and poses are

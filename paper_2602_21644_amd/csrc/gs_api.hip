@@ -252,6 +252,13 @@ int64_t gs_pixel_count(const gs_views* views) {
   return p;
 }
 
+// Float64 partials of gs_loss (one per 256 pixels of each view) or of
+// gs_render_fwd_loss (one per tile), whichever is larger.
+static size_t loss_ws_bytes(const ViewTab& tab) {
+  const size_t a = (size_t)tab.nv * loss_blocks(tab), b = (size_t)tab.ntiles;
+  return al256((a > b ? a : b) * 8 + 8);
+}
+
 gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes) {
   if (!ctx || !bytes) return GS_E_ARG;
   ViewTab tab;
@@ -271,7 +278,7 @@ gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int6
       return GS_OK;
     }
     case GS_OP_RENDER_BWD: *bytes = bwd_ws_layout(ctx, tab).bytes; return GS_OK;
-    case GS_OP_LOSS: *bytes = al256((size_t)tab.nv * loss_blocks(tab) * 8 + 8); return GS_OK;
+    case GS_OP_LOSS: *bytes = loss_ws_bytes(tab); return GS_OK;
     case GS_OP_MP_UPDATE:
       if (tab.nv != 1) return gs_fail(ctx, GS_E_ARG, "mp_update takes one view");
       *bytes = mp_ws_bytes(tab, tab.npix);
@@ -339,9 +346,35 @@ gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const
   GS_TRY(make_tab(ctx, views, tab));
   if (!pg->dcolor || !pg->ddepth) return gs_fail(ctx, GS_E_ARG, "pixel grads NULL");
   if (lp->weight_mode != 0 && lp->weight_mode != 1) return gs_fail(ctx, GS_E_ARG, "weight_mode 0|1");
-  const size_t need = al256((size_t)tab.nv * loss_blocks(tab) * 8 + 8);
+  const size_t need = loss_ws_bytes(tab);
   if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "loss workspace %zu < %zu", ws_bytes, need);
   return launch_loss(ctx, tab, img, tgt, lp, loss, pg, (double*)ws, (hipStream_t)stream);
+}
+
+gs_status gs_render_fwd_loss(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                             const gs_bins* bins, const float* bg, gs_image* img, const gs_target* tgt,
+                             const gs_loss_params* lp, float* loss, gs_pixel_grads* pg, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!ctx || !g || !proj || !bins || !bg || !img || !tgt || !lp || !loss || !pg)
+    return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!img->color || !img->depth || !img->mp || !img->T || !img->n_last) return gs_fail(ctx, GS_E_ARG, "image NULL");
+  if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
+  if (!tgt->color || !tgt->depth) return gs_fail(ctx, GS_E_ARG, "target NULL");
+  if (!pg->dcolor || !pg->ddepth) return gs_fail(ctx, GS_E_ARG, "pixel grads NULL");
+  if (lp->weight_mode != 0 && lp->weight_mode != 1) return gs_fail(ctx, GS_E_ARG, "weight_mode 0|1");
+  const size_t need = loss_ws_bytes(tab);
+  if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "loss workspace %zu < %zu", ws_bytes, need);
+  BinTab bt;
+  bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
+  int bits = 0;
+  for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
+  const LossArgs la = loss_args(tgt, lp, pg, (double*)ws);
+  hipStream_t s = (hipStream_t)stream;
+  if (tab.ntiles == 0) return GS_OK;
+  GS_TRY(launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, s, &la));
+  return launch_loss_final_tiles(ctx, tab, (const double*)ws, loss, s);
 }
 
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,

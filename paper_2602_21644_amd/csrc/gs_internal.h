@@ -123,6 +123,63 @@ __device__ __forceinline__ double wave_sum_to_lane63_d(double x) {
   return x;
 }
 
+// Loss arguments of one call (Eq. 20-22 with the lambda1/lambda2 weights):
+// targets, weights, adjoint outputs (dM, dT nullable) and the float64
+// partials. Cg == nullptr means no loss.
+struct LossArgs {
+  const float *Cg, *Dg;
+  float lp, ld, epsA;
+  int wmode, gtw;
+  float *dC, *dD, *dM, *dT;
+  double* part;
+};
+
+__device__ __forceinline__ float loss_sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
+
+// One pixel p (planar index, P pixels in all) with rendered colour c, depth D,
+// MP m and transmittance T against target colour g and depth dg (0: none):
+// writes its adjoints and returns its loss term w * (lp |c - g|_1 +
+// ld [dg > 0] |D - dg|).
+__device__ __forceinline__ double pixel_loss(const LossArgs& la, int64_t P, int64_t p, float c0, float c1, float c2,
+                                             float D, float m, float T, float g0, float g1, float g2, float dg) {
+  const float A = 1.0f - T;
+  bool ok;
+  float w;
+  if (la.wmode == 0) {
+    ok = A > la.epsA;
+    w = ok ? 1.0f - m / A : 0.0f;
+  } else {
+    ok = true;
+    w = A - m;
+  }
+  const float r0 = c0 - g0, r1 = c1 - g1, r2 = c2 - g2;
+  const float rd = dg > 0.f ? D - dg : 0.f;
+  // one explicit fma, so that every kernel using this rounds it alike
+  const float per = fmaf(la.ld, fabsf(rd), la.lp * (fabsf(r0) + fabsf(r1) + fabsf(r2)));
+  const float lw = la.lp * w;
+  la.dC[p] = lw * loss_sgn(r0);
+  la.dC[P + p] = lw * loss_sgn(r1);
+  la.dC[2 * P + p] = lw * loss_sgn(r2);
+  la.dD[p] = la.ld * w * loss_sgn(rd);
+  if (la.dM || la.dT) {
+    float gm = 0.f, gt = 0.f;
+    if (la.gtw) {
+      if (la.wmode == 0) {
+        if (ok) {
+          gm = -per / A;
+          gt = -per * m / (A * A);
+        }
+      } else {
+        gm = -per;
+        gt = -per;
+      }
+    }
+    if (la.dM) la.dM[p] = gm;
+    if (la.dT) la.dT[p] = gt;
+  }
+  return (double)w * (double)per;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = __lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -185,8 +242,10 @@ gs_status launch_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gau
 void bin_tab_fill(const ViewTab&, int, int64_t, BinTab&);
 BinWs bin_ws_layout(const ViewTab&, const BinTab&);
 gs_status launch_bin_sort(gs_ctx*, const ViewTab&, const BinTab&, const gs_proj*, gs_bins*, char*, hipStream_t);
+// with `loss` set, the loss of Eq. (20)-(22) is fused into the forward's
+// epilogue: the pixel adjoints and one float64 partial per tile
 gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const float*, int, gs_image*,
-                            hipStream_t);
+                            hipStream_t, const LossArgs* loss = nullptr);
 gs_status launch_render_bwd_tiles(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const gs_image*,
                                   const gs_pixel_grads*, const float*, float*, uint8_t*, hipStream_t);
 gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, float*, uint8_t*,
@@ -194,6 +253,8 @@ gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs
 int bwd_pose_blocks(gs_ctx*, const ViewTab&);
 int bwd_pose_stride(gs_ctx*, const ViewTab&);  // row stride of the per-block pose partials, a multiple of 4
 int loss_blocks(const ViewTab&);
+LossArgs loss_args(const gs_target*, const gs_loss_params*, gs_pixel_grads*, double* part);
+gs_status launch_loss_final_tiles(gs_ctx*, const ViewTab&, const double* part, float* loss, hipStream_t);
 gs_status launch_loss(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_loss_params*, float*,
                       gs_pixel_grads*, double*, hipStream_t);
 size_t bin_prefix_ws_bytes(gs_ctx*, const ViewTab&, int64_t capacity);

@@ -5,15 +5,9 @@
 
 namespace {
 
-__device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
-
 __global__ __launch_bounds__(GS_BLOCK) void loss_kernel(ViewTab tab, const float* __restrict__ C,
                                                         const float* __restrict__ D, const float* __restrict__ Mm,
-                                                        const float* __restrict__ T, const float* __restrict__ Cg,
-                                                        const float* __restrict__ Dg, float lp, float ld, float epsA,
-                                                        int wmode, int gtw, float* __restrict__ dC,
-                                                        float* __restrict__ dD, float* __restrict__ dM,
-                                                        float* __restrict__ dT, double* __restrict__ part) {
+                                                        const float* __restrict__ T, LossArgs la) {
   __shared__ double s[4];
   const int v = blockIdx.y;
   const int64_t npx = (int64_t)tab.W[v] * tab.H[v];
@@ -22,48 +16,13 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_kernel(ViewTab tab, const float
   double acc = 0.0;
   if (i < npx) {
     const int64_t p = tab.px_off[v] + i;
-    const float A = 1.0f - T[p];
-    const float m = Mm[p];
-    bool ok;
-    float w;
-    if (wmode == 0) {
-      ok = A > epsA;
-      w = ok ? 1.0f - m / A : 0.0f;
-    } else {
-      ok = true;
-      w = A - m;
-    }
-    const float r0 = C[p] - Cg[p], r1 = C[P + p] - Cg[P + p], r2 = C[2 * P + p] - Cg[2 * P + p];
-    const float dg = Dg[p];
-    const float rd = dg > 0.f ? D[p] - dg : 0.f;
-    const float per = lp * (fabsf(r0) + fabsf(r1) + fabsf(r2)) + ld * fabsf(rd);
-    acc = (double)w * (double)per;
-    const float lw = lp * w;
-    dC[p] = lw * sgn(r0);
-    dC[P + p] = lw * sgn(r1);
-    dC[2 * P + p] = lw * sgn(r2);
-    dD[p] = ld * w * sgn(rd);
-    if (dM || dT) {
-      float gm = 0.f, gt = 0.f;
-      if (gtw) {
-        if (wmode == 0) {
-          if (ok) {
-            gm = -per / A;
-            gt = -per * m / (A * A);
-          }
-        } else {
-          gm = -per;
-          gt = -per;
-        }
-      }
-      if (dM) dM[p] = gm;
-      if (dT) dT[p] = gt;
-    }
+    acc = pixel_loss(la, P, p, C[p], C[P + p], C[2 * P + p], D[p], Mm[p], T[p], la.Cg[p], la.Cg[P + p],
+                     la.Cg[2 * P + p], la.Dg[p]);
   }
   acc = wave_sum_to_lane63_d(acc);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+  if (threadIdx.x == 0) la.part[(int64_t)v * gridDim.x + blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
 // Sums the per-block partials of a view in a fixed order (one workgroup per
@@ -88,7 +47,51 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_final_kernel(const double* __re
   if (threadIdx.x == 0) loss[v] = (float)(s[0] + s[1] + s[2] + s[3]);
 }
 
+// The same sum over the per-tile partials of the fused forward and loss:
+// view v's tiles are [tile_base[v], tile_base[v] + gx gy).
+__global__ __launch_bounds__(GS_BLOCK) void loss_final_tiles_kernel(ViewTab tab, const double* __restrict__ part,
+                                                                    float* __restrict__ loss) {
+  __shared__ double s[GS_BLOCK / 64];
+  const int v = blockIdx.x;
+  const int nt = tab.gx[v] * tab.gy[v];
+  const double* pv = part + tab.tile_base[v];
+  double t = 0.0;
+  for (int b0 = threadIdx.x; b0 < nt; b0 += kLossUnroll * GS_BLOCK) {
+    double x[kLossUnroll];
+#pragma unroll
+    for (int u = 0; u < kLossUnroll; ++u) x[u] = b0 + u * GS_BLOCK < nt ? pv[b0 + u * GS_BLOCK] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kLossUnroll; ++u) t += x[u];
+  }
+  t = wave_sum_to_lane63_d(t);
+  if (__lane_id() == 63) s[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) loss[v] = (float)(s[0] + s[1] + s[2] + s[3]);
+}
+
 }  // namespace
+
+LossArgs loss_args(const gs_target* tgt, const gs_loss_params* lp, gs_pixel_grads* pg, double* part) {
+  LossArgs la;
+  la.Cg = tgt->color;
+  la.Dg = tgt->depth;
+  la.lp = lp->lambda_pho;
+  la.ld = lp->lambda_depth;
+  la.epsA = lp->eps_A;
+  la.wmode = lp->weight_mode;
+  la.gtw = lp->grad_through_weight;
+  la.dC = pg->dcolor;
+  la.dD = pg->ddepth;
+  la.dM = pg->dmp;
+  la.dT = pg->dT;
+  la.part = part;
+  return la;
+}
+
+gs_status launch_loss_final_tiles(gs_ctx* ctx, const ViewTab& tab, const double* part, float* loss, hipStream_t s) {
+  GS_LAUNCH(ctx, loss_final_tiles_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, tab, part, loss);
+  return gs_check_launch(ctx, "loss (tile partials)");
+}
 
 int loss_blocks(const ViewTab& tab) {
   int64_t mx = 0;
@@ -101,8 +104,7 @@ gs_status launch_loss(gs_ctx* ctx, const ViewTab& tab, const gs_image* img, cons
   const int nb = loss_blocks(tab);
   if (nb == 0) return GS_OK;
   GS_LAUNCH(ctx, loss_kernel, dim3(nb, tab.nv), dim3(GS_BLOCK), 0, s, tab, img->color, img->depth, img->mp,
-                     img->T, tgt->color, tgt->depth, lp->lambda_pho, lp->lambda_depth, lp->eps_A, lp->weight_mode,
-                     lp->grad_through_weight, pg->dcolor, pg->ddepth, pg->dmp, pg->dT, part);
+            img->T, loss_args(tgt, lp, pg, part));
   GS_LAUNCH(ctx, loss_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, part, nb, loss);
   return gs_check_launch(ctx, "loss");
 }

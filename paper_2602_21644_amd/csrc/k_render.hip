@@ -65,12 +65,17 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, const int32_t* __restrict__ trunc,
     float bg0, float bg1, float bg2, float* __restrict__ outC, float* __restrict__ outD, float* __restrict__ outM,
     float* __restrict__ outT, uint32_t* __restrict__ nlast, uint32_t* __restrict__ tile_work,
-    int32_t* __restrict__ incomplete, int truncated_bits, int cull) {
+    int32_t* __restrict__ incomplete, int truncated_bits, int cull, LossArgs la) {
   // slot BATCH is a zero-opacity entry that pads a wave's last group of four
   __shared__ float4 s_a[BATCH + 1], s_b[BATCH + 1], s_c[BATCH + 1];
   __shared__ uint8_t s_mask[BATCH];
   __shared__ uint32_t s_wmax[GS_BLOCK / 64];
-  if (*overflow) return;
+  __shared__ double s_loss[GS_BLOCK / 64];
+  if (*overflow) {
+    // no image this time; the loss partials still hold a defined value
+    if (la.Cg && threadIdx.x == 0) la.part[blockIdx.x] = 0.0;
+    return;
+  }
   // Launch order: the one the last gs_render_bwd dealt for this tile count
   // (second half of the scheduling state, valid while its marker matches),
   // else the natural order. Any stored order is a permutation of the tiles.
@@ -91,6 +96,15 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
   const uint32_t b = tile_start[t], e = tile_start[t + 1];
   const int64_t roff = tab.r_off[tc.v];
   const float fx = (float)tc.px, fy = (float)tc.py;
+  // with the loss fused in, the pixel's targets are loaded while it composites
+  float tg0 = 0.f, tg1 = 0.f, tg2 = 0.f, tgd = 0.f;
+  if (la.Cg && tc.inside) {
+    const int64_t P = tab.npix;
+    tg0 = la.Cg[tc.pix];
+    tg1 = la.Cg[P + tc.pix];
+    tg2 = la.Cg[2 * P + tc.pix];
+    tgd = la.Dg[tc.pix];
+  }
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, Mm = 0.f;
   uint32_t last = 0;
   bool done = !tc.inside;
@@ -190,28 +204,35 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
     const int active = __syncthreads_count(!done);
     if (exhausted && active > 0 && threadIdx.x == 0) atomicOr(incomplete, 1);
   }
+  double lsum = 0.0;
   if (tc.inside) {
     const int64_t P = tab.npix;
-    outC[tc.pix] = C0 + T * bg0;
-    outC[P + tc.pix] = C1 + T * bg1;
-    outC[2 * P + tc.pix] = C2 + T * bg2;
+    const float c0 = C0 + T * bg0, c1 = C1 + T * bg1, c2 = C2 + T * bg2;
+    outC[tc.pix] = c0;
+    outC[P + tc.pix] = c1;
+    outC[2 * P + tc.pix] = c2;
     outD[tc.pix] = D;
     outM[tc.pix] = Mm;
     outT[tc.pix] = T;
     nlast[tc.pix] = last;
+    if (la.Cg) lsum = pixel_loss(la, P, tc.pix, c0, c1, c2, D, Mm, T, tg0, tg1, tg2, tgd);
   }
-  if (tile_work) {
-    // the backward's work on this tile: each wave walks to its largest n_last
+  if (tile_work || la.Cg) {
+    // the backward's work on this tile: each wave walks to its largest n_last;
+    // the tile's loss partial
     uint32_t m = last;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-    if (__lane_id() == 0) s_wmax[threadIdx.x >> 6] = m;
+    if (la.Cg) lsum = wave_sum_to_lane63_d(lsum);
+    if (lane == 0) s_wmax[w] = m;
+    if (lane == 63) s_loss[w] = lsum;
     __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t sum = 0;
 #pragma unroll
       for (int i = 0; i < GS_BLOCK / 64; ++i) sum += s_wmax[i];
-      tile_work[t] = sum;
+      if (tile_work) tile_work[t] = sum;
+      if (la.Cg) la.part[t] = s_loss[0] + s_loss[1] + s_loss[2] + s_loss[3];
     }
   }
   (void)trunc;
@@ -755,14 +776,16 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
 }  // namespace
 
 gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj, const gs_bins* bins,
-                            const float* bg, int truncated_bits, gs_image* img, hipStream_t s) {
+                            const float* bg, int truncated_bits, gs_image* img, hipStream_t s, const LossArgs* loss) {
   if (tab.ntiles == 0) return GS_OK;
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
   const float4* rec = (const float4*)proj->rec;
+  LossArgs la{};
+  if (loss) la = *loss;
 #define GS_FWD(BATCH)                                                                                         \
   GS_LAUNCH(ctx, render_fwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, nullptr, bg[0], bg[1], bg[2], img->color, img->depth, img->mp, img->T,   \
-                     img->n_last, img->tile_work, bins->incomplete, truncated_bits, ctx->wave_cull)
+                     img->n_last, img->tile_work, bins->incomplete, truncated_bits, ctx->wave_cull, la)
   switch (ctx->render_batch) {
     case 64: GS_FWD(64); break;
     case 128: GS_FWD(128); break;

@@ -149,6 +149,9 @@ def lib():
                                POINTER(Image), P], c_int32),
             "gs_loss": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(LossParams), P,
                          POINTER(PixelGrads), P, c_size_t, P], c_int32),
+            "gs_render_fwd_loss": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins),
+                                    POINTER(c_float), POINTER(Image), POINTER(Target), POINTER(LossParams), P,
+                                    POINTER(PixelGrads), P, c_size_t, P], c_int32),
             "gs_render_bwd": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins), POINTER(Image),
                                POINTER(PixelGrads), POINTER(c_float), POINTER(Grads), P, c_size_t, P], c_int32),
             "gs_bins_check": ([P, POINTER(Bins), POINTER(c_int64), POINTER(c_int32), P], c_int32),
@@ -173,8 +176,8 @@ def lib():
 
 EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error", "gs_ctx_set_param",
             "gs_ctx_get_param", "gs_ctx_kernel_times", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
-            "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_bwd",
-            "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
+            "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_fwd_loss",
+            "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
             "gs_adam_step", "gs_pose_update")
 
 
@@ -248,6 +251,14 @@ def gs_loss(ctx, views, img, tgt, params, loss, pg, ws, stream=None):
     ctx.check(lib().gs_loss(ctx.h, ctypes.byref(views), ctypes.byref(img), ctypes.byref(tgt), ctypes.byref(params),
                             ptr(loss), ctypes.byref(pg), ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
               "gs_loss")
+
+
+def gs_render_fwd_loss(ctx, views, g, proj, bins, bg, img, tgt, params, loss, pg, ws, stream=None):
+    bgv = (c_float * 3)(*[float(x) for x in bg])
+    ctx.check(lib().gs_render_fwd_loss(ctx.h, ctypes.byref(views), ctypes.byref(g), ctypes.byref(proj),
+                                       ctypes.byref(bins), bgv, ctypes.byref(img), ctypes.byref(tgt),
+                                       ctypes.byref(params), ptr(loss), ctypes.byref(pg), ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream(stream)), "gs_render_fwd_loss")
 
 
 def gs_render_bwd(ctx, views, g, proj, bins, img, pg, bg, grads, ws, stream=None):
@@ -488,6 +499,16 @@ class Pipeline:
         self._tgt_keep = (target_color, target_depth)
         tgt = Target(ptr(target_color), ptr(target_depth))
         gs_loss(self.ctx, self.views.s, self.img, tgt, self.lp, self.loss, self.pg, self.ws_loss, stream)
+
+    def forward_loss(self, g: Gaussians, target_color, target_depth, stream=None):
+        """forward and loss_and_grads in one pass (the loss fused into the
+        forward's epilogue)."""
+        self._tgt_keep = (target_color, target_depth)
+        tgt = Target(ptr(target_color), ptr(target_depth))
+        gs_project(self.ctx, self.views.s, g, self.proj, stream)
+        gs_bin_sort(self.ctx, self.views.s, g, self.proj, self.bins, self.ws_bin, stream)
+        gs_render_fwd_loss(self.ctx, self.views.s, g, self.proj, self.bins, self.bg, self.img, tgt, self.lp,
+                           self.loss, self.pg, self.ws_loss, stream)
 
     def backward(self, g: Gaussians, grads: Grads, stream=None):
         gs_render_bwd(self.ctx, self.views.s, g, self.proj, self.bins, self.img, self.pg, self.bg, grads,

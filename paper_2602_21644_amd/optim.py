@@ -53,8 +53,7 @@ class RenderLoss(torch.autograd.Function):
         g = dict(mean=mean.contiguous(), log_scale=log_scale.contiguous(), quat=quat.contiguous(),
                  opacity_logit=opacity_logit.contiguous(), color=color.contiguous(), mp=mp.contiguous())
         gst = gs.gaussians_struct(g)
-        pipe.forward(gst)
-        pipe.loss_and_grads(target_color.contiguous(), target_depth.contiguous())
+        pipe.forward_loss(gst, target_color.contiguous(), target_depth.contiguous())
         ctx.pipe, ctx.gst, ctx.keep = pipe, gst, g
         ctx.n = int(opacity_logit.shape[0])
         return pipe.loss.clone()
@@ -156,8 +155,7 @@ class Tracker:
 
     def _iteration(self):
         p = self.pipe
-        p.forward(self.gst)
-        p.loss_and_grads(self.tc, self.td)
+        p.forward_loss(self.gst, self.tc, self.td)
         torch.maximum(self.flags, p.counters[1:3], out=self.flags)
         p.backward(self.gst, self.grs)
         self.adam.step([self.dpose[:3], self.dpose[3:]])
@@ -200,8 +198,7 @@ class Tracker:
             else:
                 self._iteration()
         # loss at the final pose
-        self.pipe.forward(self.gst)
-        self.pipe.loss_and_grads(self.tc, self.td)
+        self.pipe.forward_loss(self.gst, self.tc, self.td)
         torch.maximum(self.flags, self.pipe.counters[1:3], out=self.flags)
         torch.cuda.synchronize()
         exact = int(self.flags.sum()) == 0
@@ -223,8 +220,7 @@ def map_gaussians(ctx, gaussians, cams, target_color, target_depth, iters=50, lr
     adam = Adam(ctx, [(gaussians[k], lrs[k]) for k in PARAMS])
     losses = torch.zeros(iters, dtype=torch.float32, device=gaussians["mean"].device)
     for it in range(iters):
-        pipe.forward(gst)
-        pipe.loss_and_grads(target_color, target_depth)
+        pipe.forward_loss(gst, target_color, target_depth)
         losses[it] = pipe.loss.sum()
         pipe.backward(gst, grs)
         adam.step([grads[k] for k in PARAMS])

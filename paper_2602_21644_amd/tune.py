@@ -82,8 +82,7 @@ def tune(ctx, views, gaussians, target_color, target_depth, cache=None, iters=5,
     grs = gs.grads_struct(grads, pose)
 
     def step():
-        pipe.forward(gst)
-        pipe.loss_and_grads(target_color, target_depth)
+        pipe.forward_loss(gst, target_color, target_depth)
         pipe.backward(gst, grs)
 
     space = dict(KNOBS)

@@ -441,3 +441,42 @@ def test_full_size_sampled_pixels(ctx, orc):
     ref = orc.render(orc.project(g, cam), g, cam, pixels=pix)
     sub = {k: (got[k][:, pix] if k == "C" else got[k][pix]) for k in ("C", "D", "M", "T")}
     assert_image_close(sub, ref, ref["margin"], max_excluded=0.02)
+
+
+@pytest.mark.parametrize("seed,n,W,H,weight_mode,gtw,max_rank,nviews", [
+    (21, 3000, 64, 48, 0, 0, 0, 1), (22, 60000, 333, 250, 1, 1, 0, 1), (23, 200000, 640, 480, 0, 1, 1024, 1),
+    (24, 40000, 320, 240, 0, 0, 0, 3)])
+def test_render_fwd_loss_fused(ctx, seed, n, W, H, weight_mode, gtw, max_rank, nviews):
+    """gs_render_fwd_loss writes the images and pixel adjoints of gs_render_fwd
+    followed by gs_loss bit for bit; the loss differs only in the order of its
+    float64 sum."""
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(seed, n, W, H)
+    cams = [cam, tcam, cam][:nviews]
+    views, pipe, gt, gst = make_pipeline(ctx, g, cams, max_rank=max_rank, bg=(0.1, 0.2, 0.3))
+    pipe.set_loss_params(weight_mode=weight_mode, grad_through_weight=gtw)
+    pipe.forward(gst)
+    rng = np.random.default_rng(seed)
+    tc = (pipe.img_color * 0.8 + 0.05).contiguous()
+    mask = torch.from_numpy(rng.random(pipe.P) < 0.7).cuda()
+    td = torch.where(mask, pipe.img_depth * 1.1, torch.zeros_like(pipe.img_depth)).contiguous()
+    pipe.loss_and_grads(tc, td)
+    torch.cuda.synchronize()
+    inc_ref = pipe.check()[2]
+    outs = ("img_color", "img_depth", "img_mp", "img_T", "img_nlast", "dC", "dD", "dM", "dT")
+    ref = {k: getattr(pipe, k).clone() for k in outs}
+    ref_loss = pipe.loss.clone()
+    for k in outs:  # a value no kernel writes, so a missed pixel shows
+        t = getattr(pipe, k)
+        if t.dtype == torch.float32:
+            t.fill_(float("nan"))
+        else:
+            t.fill_(0x7FFFFFFF)
+    pipe.loss.fill_(float("nan"))
+    pipe.forward_loss(gst, tc, td)
+    torch.cuda.synchronize()
+    over, n_inst, inc = pipe.check()
+    assert not over and inc == inc_ref  # same lists, same flag
+    for k in outs:
+        assert torch.equal(getattr(pipe, k), ref[k]), k
+    torch.testing.assert_close(pipe.loss, ref_loss, rtol=1e-6, atol=0)
+    assert float(ref_loss.abs().min()) > 0
