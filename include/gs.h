@@ -156,10 +156,12 @@ typedef struct gs_image {
                           gs_render_fwd, per tile the sum over its four
                           64-pixel groups (pixel rows 4i..4i+3) of the largest
                           n_last in the group. [n_tiles, 2 n_tiles]: a launch
-                          order heaviest first and a marker, written by
-                          gs_render_bwd and used by it and by the next
-                          gs_render_fwd with the same tile count (scheduling
-                          only: results do not depend on it). */
+                          order heaviest first and a marker, dealt by
+                          gs_render_fwd (and gs_render_fwd_loss) from the work
+                          it just wrote when "tile_order" is on, used by the
+                          next gs_render_bwd and gs_render_fwd with the same
+                          tile count (scheduling only: results do not depend
+                          on it). */
 } gs_image;
 
 typedef struct gs_target {
@@ -204,8 +206,8 @@ const char* gs_last_error(const gs_ctx* ctx);
 /* Tuning knobs: "render_batch" (64|128|256 list entries staged per LDS batch
  * in gs_render_fwd), "bwd_batch" (32|64|128, gs_render_bwd), "bin_chunk"
  * (256|512|1024|2048 records per binning workgroup), "tile_order" (0|1,
- * default 1: gs_render_bwd launches tiles heaviest first when the image has
- * tile_work), "bwd_copies" (1|2|4|8, default 8: accumulators of the per-record
+ * default 1: when the image has tile_work, the forward deals a launch order
+ * heaviest first and gs_render_bwd runs its tiles in it), "bwd_copies" (1|2|4|8, default 8: accumulators of the per-record
  * 2D adjoint in the gs_render_bwd scratch, one per group of XCDs, so atomics
  * from different XCDs do not contend for one address; summed in a fixed
  * order), "wave_cull" (0|1, default 1: in gs_render_fwd each 64-pixel wave
@@ -261,7 +263,8 @@ gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g,
 /* Front-to-back compositing per 16x16 tile: alpha = min(0.99, o exp(p)),
  * entries with alpha < 1/255 skipped, stop before an entry that drops T below
  * 1e-4. Writes C + T bg, D, the MP channel M, T, n_last and, when set,
- * tile_work. bg is [host] RGB. */
+ * tile_work (per-tile work, then the backward's tile order). bg is [host]
+ * RGB. */
 gs_status gs_render_fwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
                         const gs_bins* bins, const float* bg, gs_image* img, void* stream);
 
@@ -290,8 +293,8 @@ gs_status gs_render_fwd_loss(gs_ctx* ctx, const gs_views* views, const gs_gaussi
  * optimised jointly). Transmittance is recomputed back from T_final. `ws` of
  * gs_workspace_size(GS_OP_RENDER_BWD), zero-filled before first use; each
  * call leaves it zero-filled. With img->tile_work set (and "tile_order" on)
- * the tiles run heaviest first; the gradients differ only in the order of
- * their float atomics. */
+ * the tiles run in the order the forward dealt, heaviest first; the gradients
+ * differ only in the order of their float atomics. */
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
                         const gs_bins* bins, const gs_image* img, const gs_pixel_grads* pg, const float* bg,
                         gs_grads* grads, void* ws, size_t ws_bytes, void* stream);

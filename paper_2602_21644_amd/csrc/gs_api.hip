@@ -370,11 +370,8 @@ gs_status gs_render_fwd_loss(gs_ctx* ctx, const gs_views* views, const gs_gaussi
   bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
   int bits = 0;
   for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
-  const LossArgs la = loss_args(tgt, lp, pg, (double*)ws);
-  hipStream_t s = (hipStream_t)stream;
-  if (tab.ntiles == 0) return GS_OK;
-  GS_TRY(launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, s, &la));
-  return launch_loss_final_tiles(ctx, tab, (const double*)ws, loss, s);
+  const LossArgs la = loss_args(tgt, lp, pg, (double*)ws, loss);
+  return launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, (hipStream_t)stream, &la);
 }
 
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,

@@ -131,7 +131,8 @@ struct LossArgs {
   float lp, ld, epsA;
   int wmode, gtw;
   float *dC, *dD, *dM, *dT;
-  double* part;
+  double* part;  // float64 partials
+  float* loss;   // [views] totals
 };
 
 __device__ __forceinline__ float loss_sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
@@ -253,8 +254,7 @@ gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs
 int bwd_pose_blocks(gs_ctx*, const ViewTab&);
 int bwd_pose_stride(gs_ctx*, const ViewTab&);  // row stride of the per-block pose partials, a multiple of 4
 int loss_blocks(const ViewTab&);
-LossArgs loss_args(const gs_target*, const gs_loss_params*, gs_pixel_grads*, double* part);
-gs_status launch_loss_final_tiles(gs_ctx*, const ViewTab&, const double* part, float* loss, hipStream_t);
+LossArgs loss_args(const gs_target*, const gs_loss_params*, gs_pixel_grads*, double* part, float* loss);
 gs_status launch_loss(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_loss_params*, float*,
                       gs_pixel_grads*, double*, hipStream_t);
 size_t bin_prefix_ws_bytes(gs_ctx*, const ViewTab&, int64_t capacity);

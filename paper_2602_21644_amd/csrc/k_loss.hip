@@ -47,31 +47,9 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_final_kernel(const double* __re
   if (threadIdx.x == 0) loss[v] = (float)(s[0] + s[1] + s[2] + s[3]);
 }
 
-// The same sum over the per-tile partials of the fused forward and loss:
-// view v's tiles are [tile_base[v], tile_base[v] + gx gy).
-__global__ __launch_bounds__(GS_BLOCK) void loss_final_tiles_kernel(ViewTab tab, const double* __restrict__ part,
-                                                                    float* __restrict__ loss) {
-  __shared__ double s[GS_BLOCK / 64];
-  const int v = blockIdx.x;
-  const int nt = tab.gx[v] * tab.gy[v];
-  const double* pv = part + tab.tile_base[v];
-  double t = 0.0;
-  for (int b0 = threadIdx.x; b0 < nt; b0 += kLossUnroll * GS_BLOCK) {
-    double x[kLossUnroll];
-#pragma unroll
-    for (int u = 0; u < kLossUnroll; ++u) x[u] = b0 + u * GS_BLOCK < nt ? pv[b0 + u * GS_BLOCK] : 0.0;
-#pragma unroll
-    for (int u = 0; u < kLossUnroll; ++u) t += x[u];
-  }
-  t = wave_sum_to_lane63_d(t);
-  if (__lane_id() == 63) s[threadIdx.x >> 6] = t;
-  __syncthreads();
-  if (threadIdx.x == 0) loss[v] = (float)(s[0] + s[1] + s[2] + s[3]);
-}
-
 }  // namespace
 
-LossArgs loss_args(const gs_target* tgt, const gs_loss_params* lp, gs_pixel_grads* pg, double* part) {
+LossArgs loss_args(const gs_target* tgt, const gs_loss_params* lp, gs_pixel_grads* pg, double* part, float* loss) {
   LossArgs la;
   la.Cg = tgt->color;
   la.Dg = tgt->depth;
@@ -85,12 +63,8 @@ LossArgs loss_args(const gs_target* tgt, const gs_loss_params* lp, gs_pixel_grad
   la.dM = pg->dmp;
   la.dT = pg->dT;
   la.part = part;
+  la.loss = loss;
   return la;
-}
-
-gs_status launch_loss_final_tiles(gs_ctx* ctx, const ViewTab& tab, const double* part, float* loss, hipStream_t s) {
-  GS_LAUNCH(ctx, loss_final_tiles_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, tab, part, loss);
-  return gs_check_launch(ctx, "loss (tile partials)");
 }
 
 int loss_blocks(const ViewTab& tab) {
@@ -104,7 +78,7 @@ gs_status launch_loss(gs_ctx* ctx, const ViewTab& tab, const gs_image* img, cons
   const int nb = loss_blocks(tab);
   if (nb == 0) return GS_OK;
   GS_LAUNCH(ctx, loss_kernel, dim3(nb, tab.nv), dim3(GS_BLOCK), 0, s, tab, img->color, img->depth, img->mp,
-            img->T, loss_args(tgt, lp, pg, part));
+            img->T, loss_args(tgt, lp, pg, part, loss));
   GS_LAUNCH(ctx, loss_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, part, nb, loss);
   return gs_check_launch(ctx, "loss");
 }

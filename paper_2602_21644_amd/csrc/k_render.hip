@@ -253,8 +253,8 @@ __device__ __forceinline__ int order_bucket(uint32_t x) {
   const int k = (int)(__float_as_uint((float)x) >> 19) - (127 << 4) + 1;  // x = 0 -> below 0, x = 1 -> 1
   return kOrderBuckets - 1 - min(max(k, 0), kOrderBuckets - 1);
 }
-__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_t* __restrict__ work, int ntiles,
-                                                                   int ncu, uint32_t* __restrict__ order) {
+__device__ void deal_tile_order(const uint32_t* __restrict__ work, int ntiles, int ncu,
+                                uint32_t* __restrict__ order) {
   __shared__ uint32_t s_cnt[kOrderBuckets];
   __shared__ uint16_t s_bk[kOrderCached];
   __shared__ uint32_t s_wave[kOrderThreads / 64];
@@ -296,6 +296,46 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_
   if (tid == 0) order[n] = n + 1u;  // marks the order valid for n tiles
 }
 
+__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_t* __restrict__ work, int ntiles,
+                                                                   int ncu, uint32_t* __restrict__ order) {
+  deal_tile_order(work, ntiles, ncu, order);
+}
+
+// After the forward with the loss fused in: workgroup v < nv sums view v's
+// per-tile loss partials in a fixed order (float64); one more workgroup, when
+// `order` is set, deals the tile order as tile_order_kernel does.
+__global__ __launch_bounds__(kOrderThreads) void fwd_finish_kernel(ViewTab tab, const double* __restrict__ part,
+                                                                   float* __restrict__ loss,
+                                                                   const uint32_t* __restrict__ work, int ncu,
+                                                                   uint32_t* __restrict__ order) {
+  if ((int)blockIdx.x >= tab.nv) {
+    deal_tile_order(work, tab.ntiles, ncu, order);
+    return;
+  }
+  __shared__ double s_sum[kOrderThreads / 64];
+  const int v = blockIdx.x;
+  const int nt = tab.gx[v] * tab.gy[v];
+  const double* pv = part + tab.tile_base[v];
+  constexpr int kU = 4;
+  double acc = 0.0;
+  for (int b0 = threadIdx.x; b0 < nt; b0 += kU * kOrderThreads) {
+    double x[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = b0 + u * kOrderThreads < nt ? pv[b0 + u * kOrderThreads] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc += x[u];
+  }
+  acc = wave_sum_to_lane63_d(acc);
+  if (__lane_id() == 63) s_sum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kOrderThreads / 64; ++i) t += s_sum[i];
+    loss[v] = (float)t;
+  }
+}
+
 // Backward over one tile. g2d holds per record ten values
 // (u_x, u_y, k1, k2, k3, opacity, c_r, c_g, c_b, depth), [copy][record][10].
 //
@@ -320,8 +360,12 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
   __shared__ uint32_t s_r[BATCH];
   __shared__ uint32_t s_max;
   if (*overflow) return;
-  const uint32_t tu = order ? order[blockIdx.x] : blockIdx.x;
-  if (tu >= (uint32_t)tab.ntiles) return;  // never taken for a permutation
+  // the order the forward dealt, while its marker is valid for this tile count
+  uint32_t tu = blockIdx.x;
+  if (order) {
+    const uint32_t ntl = (uint32_t)tab.ntiles, cand = order[blockIdx.x];
+    if (order[ntl] == ntl + 1u && cand < ntl) tu = cand;
+  }
   const int t = (int)tu;
   const TileCtx tc = tile_ctx(tab, t);
   const uint32_t b = tile_start[t];
@@ -557,8 +601,12 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
   __shared__ float4 s_dm[BATCH][10];                  // [entry][sum]: the four waves' values
   __shared__ uint32_t s_max;
   if (*overflow) return;
-  const uint32_t tu = order ? order[blockIdx.x] : blockIdx.x;
-  if (tu >= (uint32_t)tab.ntiles) return;  // never taken for a permutation
+  // the order the forward dealt, while its marker is valid for this tile count
+  uint32_t tu = blockIdx.x;
+  if (order) {
+    const uint32_t ntl = (uint32_t)tab.ntiles, cand = order[blockIdx.x];
+    if (order[ntl] == ntl + 1u && cand < ntl) tu = cand;
+  }
   const int t = (int)tu;
   const TileCtx tc = tile_ctx(tab, t);
   const uint32_t b = tile_start[t];
@@ -775,6 +823,16 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
 
 }  // namespace
 
+// Compute units of the device, queried once per context.
+static gs_status query_n_cu(gs_ctx* ctx) {
+  if (ctx->n_cu > 0) return GS_OK;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n <= 0)
+    return gs_fail(ctx, GS_E_HIP, "cannot query the compute-unit count");
+  ctx->n_cu = n;
+  return GS_OK;
+}
+
 gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj, const gs_bins* bins,
                             const float* bg, int truncated_bits, gs_image* img, hipStream_t s, const LossArgs* loss) {
   if (tab.ntiles == 0) return GS_OK;
@@ -792,6 +850,19 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
     default: GS_FWD(256); break;
   }
 #undef GS_FWD
+  // the backward's tile order (and the per-view loss sums when fused)
+  const bool deal = img->tile_work && ctx->tile_order;
+  if (deal) {
+    const gs_status st = query_n_cu(ctx);
+    if (st != GS_OK) return st;
+  }
+  uint32_t* ord = img->tile_work ? img->tile_work + tab.ntiles : nullptr;
+  if (loss)
+    GS_LAUNCH(ctx, fwd_finish_kernel, dim3(tab.nv + (deal ? 1 : 0)), dim3(kOrderThreads), 0, s, tab, la.part,
+              la.loss, img->tile_work, ctx->n_cu, ord);
+  else if (deal)
+    GS_LAUNCH(ctx, tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, img->tile_work, (int)tab.ntiles,
+              ctx->n_cu, ord);
   return gs_check_launch(ctx, "render_fwd");
 }
 
@@ -801,19 +872,8 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
   if (tab.ntiles == 0) return GS_OK;
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
   const float4* rec = (const float4*)proj->rec;
-  const uint32_t* order = nullptr;
-  if (img->tile_work && ctx->tile_order) {
-    if (ctx->n_cu <= 0) {
-      int n = 0;
-      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n <= 0)
-        return gs_fail(ctx, GS_E_HIP, "cannot query the compute-unit count");
-      ctx->n_cu = n;
-    }
-    uint32_t* ord = img->tile_work + tab.ntiles;  // second half of the scheduling state
-    GS_LAUNCH(ctx, tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, img->tile_work, (int)tab.ntiles,
-              ctx->n_cu, ord);
-    order = ord;
-  }
+  // the order the last forward dealt (second half of the scheduling state)
+  const uint32_t* order = img->tile_work && ctx->tile_order ? img->tile_work + tab.ntiles : nullptr;
 #define GS_BWD(BATCH)                                                                                          \
   if (ctx->bwd_mfma)                                                                                           \
     GS_LAUNCH(ctx, render_bwd_mfma_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start, \

@@ -304,6 +304,19 @@ def test_backward_tile_order(ctx, orc):
     work = torch_np(pipe.img_tile_work).view(np.uint32).astype(np.int64)[:views.tile_count]
     host = np.concatenate([_host_tile_work(nl[:640 * 480], 640, 480), _host_tile_work(nl[640 * 480:], 320, 240)])
     np.testing.assert_array_equal(work, host)
+    # the forward dealt the backward's order: a permutation with its marker,
+    # heaviest first (by log-scale bucket of the work) round by round
+    T = views.tile_count
+    tw = torch_np(pipe.img_tile_work).view(np.uint32).astype(np.int64)
+    assert tw[2 * T] == T + 1
+    order = tw[T:2 * T]
+    np.testing.assert_array_equal(np.sort(order), np.arange(T))
+    k = (host.astype(np.float32).view(np.uint32).astype(np.int64) >> 19) - (127 << 4) + 1
+    bucket = 2047 - np.clip(k, 0, 2047)  # smaller = heavier
+    ncu = ctx.get_param("n_cu")
+    rounds = [bucket[order[r:r + ncu]] for r in range(0, T, ncu)]
+    for a_, b_ in zip(rounds, rounds[1:]):
+        assert a_.max() <= b_.min()
     pipe.loss_and_grads(tc, td)
     n = synth.n_gaussians(g)
     outs = []
