@@ -171,6 +171,12 @@ def test_bin_sort_all_culled_and_overflow(ctx, orc):
     pipe.forward(gst)
     over, n_inst, _ = pipe.check()
     assert over and n_inst > 100
+    # the fused forward and loss under overflow: no image, a defined zero loss
+    pipe.loss.fill_(float("nan"))
+    tgt = torch.zeros(3 * pipe.P, device="cuda")
+    pipe.forward_loss(gst, tgt, tgt[:pipe.P].contiguous())
+    over, n_inst, _ = pipe.check()
+    assert over and float(pipe.loss[0]) == 0.0
 
 
 def test_render_fwd_parity_tiny(ctx, orc):
