@@ -138,7 +138,7 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_pixel_kernel(int64_t npix, int K,
                                                             const float* __restrict__ mlp, float sigma_small,
                                                             const MpScal* __restrict__ sc, float* __restrict__ Mp,
                                                             float* __restrict__ e_copy, const float* __restrict__ Dg,
-                                                            float4* __restrict__ pk) {
+                                                            float2* __restrict__ pk) {
   const int64_t p = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
   if (p >= npix) return;
   const int r = min(max(inst[p], 0), K);
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_pixel_kernel(int64_t npix, int K,
   if (mlp) {
     const float m = mlp[p];
     Mp[p] = m;
-    pk[p] = make_float4(m, e, Dg[p], 0.f);
+    pk[p] = make_float2(m, Dg[p] > 0.f ? e : -1.f);
     return;
   }
   const float mu = sc->region[r][0], sd = sc->region[r][1], ub = sc->region[r][2], gg = sc->region[r][3];
@@ -158,8 +158,10 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_pixel_kernel(int64_t npix, int K,
   const float Kp = den > 0.f ? gg / den : 0.5f;
   const float m = (1.f - Kp) * prior[r] + Kp * geo;
   Mp[p] = m;
-  // (M_p, e, observed depth) packed for the per-Gaussian windows
-  pk[p] = make_float4(m, e, Dg[p], 0.f);
+  // (M_p, e) packed for the per-Gaussian windows, e = -1 where no depth was
+  // observed (e >= 0 elsewhere): 8 bytes per pixel, so a frame's pixels stay
+  // in one XCD's L2
+  pk[p] = make_float2(m, Dg[p] > 0.f ? e : -1.f);
 }
 
 struct GaussOut {
@@ -171,7 +173,7 @@ struct GaussOut {
 
 __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const float* __restrict__ mean2d,
                                                             const uint32_t* __restrict__ key,
-                                                            const float4* __restrict__ pk,
+                                                            const float2* __restrict__ pk,
                                                             const float* __restrict__ mp, float radius, float sigma_w,
                                                             float lambda_u, float eps, GaussOut go,
                                                             uint32_t* __restrict__ part_u) {
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const f
       // (exact zero for constant samples)
       int n = 0;
       float sw = 0.f, swm = 0.f, km = 0.f, ke = 0.f, am = 0.f, am2 = 0.f, ae = 0.f, ae2 = 0.f;
-      auto take = [&](const float4& v, float d2) {
+      auto take = [&](const float2& v, float d2) {
         const float w = __expf(-d2 * inv2);
         if (n == 0) {
           km = v.x;
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const f
         // ceil(uy-2)); its loads are issued together, visited in the same
         // row-major order as the general loop below
         const int xs = (int)ceilf(ux - 2.0f), ys = (int)ceilf(uy - 2.0f);
-        float4 v[25];
+        float2 v[25];
         float dd[25];
         bool in[25];
 #pragma unroll
@@ -234,19 +236,19 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_gauss_kernel(ViewTab tab, const f
           const float dx = __fsub_rn((float)x, ux), dy = __fsub_rn((float)y, uy);
           dd[i] = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
           in[i] = x >= x0 && x <= x1 && y >= y0 && y <= y1 && dd[i] <= r2;
-          v[i] = in[i] ? pk[(int64_t)y * W + x] : make_float4(0.f, 0.f, 0.f, 0.f);
+          v[i] = in[i] ? pk[(int64_t)y * W + x] : make_float2(0.f, -1.f);
         }
 #pragma unroll
         for (int i = 0; i < 25; ++i)
-          if (in[i] && v[i].z > 0.f) take(v[i], dd[i]);
+          if (in[i] && v[i].y >= 0.f) take(v[i], dd[i]);
       } else {
         for (int y = y0; y <= y1; ++y)
           for (int x = x0; x <= x1; ++x) {
             const float dx = __fsub_rn((float)x, ux), dy = __fsub_rn((float)y, uy);
             const float d2 = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
             if (d2 <= r2) {
-              const float4 v = pk[(int64_t)y * W + x];
-              if (v.z > 0.f) take(v, d2);
+              const float2 v = pk[(int64_t)y * W + x];
+              if (v.y >= 0.f) take(v, d2);
             }
           }
       }
@@ -542,7 +544,7 @@ MpWs mp_layout(int64_t n, int64_t P) {
   const int64_t gb = (n + GS_BLOCK - 1) / GS_BLOCK;
   L.e = o; o += al(P * 4);
   L.Mp = o; o += al(P * 4);
-  L.pk = o; o += al(P * 16);
+  L.pk = o; o += al(P * 8);
   L.part = o; o += al((size_t)(nb > 0 ? nb : 1) * (GS_BLOCK / 64) * MAXR * 3 * 8);
   L.part_u = o; o += al((size_t)(gb > 0 ? gb : 1) * 3 * 4);
   L.part_l = o; o += al((size_t)(gb > 0 ? gb : 1) * 2 * 4);
@@ -573,7 +575,7 @@ gs_status launch_mp_update(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj,
   uint32_t* part_h = (uint32_t*)(ws + L.part_h);
   MpScal* sc = (MpScal*)(ws + L.scal);
   GaussOut go{(float*)(ws + L.Mhat), (float*)(ws + L.sde), (float*)(ws + L.U), (uint8_t*)(ws + L.obs)};
-  float4* pk = (float4*)(ws + L.pk);
+  float2* pk = (float2*)(ws + L.pk);
   const int K = fr->n_inst;
   const int nb = (int)((P + REG_TILE - 1) / REG_TILE);
   if (nb > 0)
