@@ -292,7 +292,7 @@ def main():
     iter_frac = total_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     # per-frame MP update at the same scale (reported beside, not in the step)
-    mp_ms = mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td)
+    mp_ms, mp_graph_ms = mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td)
 
     out = {
         "metric": METRIC,
@@ -318,6 +318,7 @@ def main():
         "eager_ms_per_step": round(eager_ms, 4),
         "kernel_us_per_step": {k: round(1000 * v, 2) for k, v in sorted(per_step.items(), key=lambda x: -x[1])},
         "mp_update_ms": round(mp_ms, 4),
+        "mp_update_graph_ms": round(mp_graph_ms, 4),
         "wall_s_timed": round(t_wall, 3),
     }
     if not a.no_extras:
@@ -551,7 +552,8 @@ def pmc_traffic(kernel):
 
 def mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td):
     """Times gs_mp_update on the rendered frame (3 instance masks from the
-    boxes' screen rectangles), median of 20 calls."""
+    boxes' screen rectangles): median of 20 eager calls, and median of 20
+    replays of the call captured in a hip graph."""
     n = a.n
     views = gs.ViewBatch([cam], n)
     M = views.rec_count
@@ -588,7 +590,24 @@ def mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td):
         torch.cuda.synchronize()
         if i >= 2:
             times.append(e0.elapsed_time(e1))
-    return float(np.median(times))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gs.gs_mp_update(ctx, views.s, proj, pipe.img, tgt, frame, pp, mp, out, ws)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gs.gs_mp_update(ctx, views.s, proj, pipe.img, tgt, frame, pp, mp, out, ws)
+    gtimes = []
+    for i in range(22):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if i >= 2:
+            gtimes.append(e0.elapsed_time(e1))
+    return float(np.median(times)), float(np.median(gtimes))
 
 
 def cpu_baseline(g, cam, tc, td, budget_s=10.0):

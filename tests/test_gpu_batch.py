@@ -126,10 +126,12 @@ def test_uneven_scene_batch_parity(ctx, orc, max_rank):
     _batch_case(ctx, orc, scenes, views, max_rank=max_rank)
 
 
-def test_graph_replay_matches_eager(ctx):
-    """The whole iteration (project, bin, render, loss, backward) captured once
-    and replayed several times, with eager work and synchronisations between
-    replays, gives the eager results every time."""
+@pytest.mark.parametrize("fused", [False, True])
+def test_graph_replay_matches_eager(ctx, fused):
+    """The whole iteration (project, bin, render, loss, backward; the loss
+    separate or fused into the forward) captured once and replayed several
+    times, with eager work and synchronisations between replays, gives the
+    eager results every time."""
     g, views = _window(41, 20000, 160, 120, 3)
     cams = [c for _, c, _ in views]
     vb = gs.ViewBatch(cams, synth.n_gaussians(g))
@@ -144,8 +146,11 @@ def test_graph_replay_matches_eager(ctx):
     gsr = gs.grads_struct(grads, pose)
 
     def step():
-        pipe.forward(gst)
-        pipe.loss_and_grads(tcol, tdep)
+        if fused:
+            pipe.forward_loss(gst, tcol, tdep)
+        else:
+            pipe.forward(gst)
+            pipe.loss_and_grads(tcol, tdep)
         pipe.backward(gst, gsr)
 
     step()

@@ -17,6 +17,15 @@ def ctx():
 
 
 def run_gpu(ctx, inp, params=None, seg_updated=True, mlp_mp=None, want_pixels=True):
+    st = setup_gpu(ctx, inp, params, seg_updated, mlp_mp, want_pixels)
+    st["call"]()
+    torch.cuda.synchronize()
+    return st["result"]()
+
+
+def setup_gpu(ctx, inp, params=None, seg_updated=True, mlp_mp=None, want_pixels=True):
+    """Device inputs and outputs of one gs_mp_update call on `inp`; `call`
+    enqueues it on the current stream, `result` reads the outputs back."""
     W, H = inp["width"], inp["height"]
     n = inp["mp"].shape[0]
     P = W * H
@@ -55,11 +64,17 @@ def run_gpu(ctx, inp, params=None, seg_updated=True, mlp_mp=None, want_pixels=Tr
     stats = torch.zeros(8, device=dev)
     out = gs.MPOut(gs.ptr(Ut), gs.ptr(al), gs.ptr(dyn), gs.ptr(pr), gs.ptr(Mp), gs.ptr(e), gs.ptr(stats))
     ws = torch.zeros(gs.gs_workspace_size(ctx, views.s, gs.GS_OP_MP_UPDATE), dtype=torch.uint8, device=dev)
-    gs.gs_mp_update(ctx, views.s, proj, img, tgt, frame, pp, mp, out, ws)
-    torch.cuda.synchronize()
-    c = lambda x: None if x is None else x.cpu().numpy()
-    return dict(mp=c(mp), U_tilde=c(Ut), alpha=c(al), dynamic=c(dyn).astype(bool), prune=c(pr).astype(bool),
-                M_p=c(Mp), e=c(e), stats=c(stats))
+    keep = (m2d, keyd, Dd, Cd, Dg, Cg, inst, prior, conf, mlp_t)  # alive as long as the closures
+
+    def call():
+        gs.gs_mp_update(ctx, views.s, proj, img, tgt, frame, pp, mp, out, ws)
+
+    def result():
+        c = lambda x: None if x is None else x.cpu().numpy()
+        return dict(mp=c(mp), U_tilde=c(Ut), alpha=c(al), dynamic=c(dyn).astype(bool), prune=c(pr).astype(bool),
+                    M_p=c(Mp), e=c(e), stats=c(stats))
+
+    return dict(call=call, result=result, mp=mp, outs=(mp, Ut, al, dyn, pr, Mp, e, stats), keep=keep)
 
 
 def compare(orc_r, g, tol=1e-5):
@@ -118,3 +133,33 @@ def test_mp_update_full_size(ctx, orc):
     ref = orc.mp.mp_update(inp)
     got = run_gpu(ctx, inp, want_pixels=False)
     compare(ref, got)
+
+
+def test_mp_update_graph_replay(ctx):
+    """gs_mp_update captured once in a hip graph: every replay, with eager work
+    and synchronisations between replays, writes the eager call's outputs bit
+    for bit."""
+    inp = synth.mp_frame_inputs(10, 20000, 160, 120, n_inst=3)
+    st = setup_gpu(ctx, inp)
+    mp0 = st["mp"].clone()
+    st["call"]()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in st["outs"]]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        st["mp"].copy_(mp0)
+        st["call"]()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        st["call"]()
+    for rep in range(3):
+        for t in st["outs"][1:]:
+            t.zero_()  # eager work between replays
+        st["mp"].copy_(mp0)  # the update is in place: start from the same state
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(st["outs"], eager):
+            assert torch.equal(a, b), rep
