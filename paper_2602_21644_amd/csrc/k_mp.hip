@@ -11,8 +11,9 @@
 //     (Eq. 10); frame min/max of U by integer atomics on ordered bit patterns;
 //  4. per Gaussian: normalised U, rate (Eq. 11), stale-prior factor (Eq. 17)
 //     and the state update (Eq. 9, or the log-odds variant);
-//  5. lower medians of M^t and U~ over observed Gaussians by an exact 4-pass
-//     8-bit radix select on the float bit patterns (values are >= 0);
+//  5. lower medians of M^t and U~ over observed Gaussians by an exact 3-pass
+//     radix select (digits of 11, 11 and 10 bits) on the float bit patterns
+//     (values are >= 0);
 //  6. threshold tau = max(median, 0.5), labels (Eq. 12), prune flags, and the
 //     frame uncertainty (Eq. 13).
 #include "gs_internal.h"
@@ -24,6 +25,12 @@ constexpr int PIX_ITEMS = 4;     // pixels per thread in the region pass
 constexpr int REG_TILE = GS_BLOCK * PIX_ITEMS;
 constexpr int SEL_BLOCKS = 256;
 constexpr int SEL_COPIES = 8;  // histogram copies, one per XCD
+constexpr int SEL_PASSES = 3;
+constexpr int SEL_BINS = 2048;  // bins per value and pass (the last pass uses 1024)
+constexpr int SEL_HIST = 2 * SEL_BINS;  // both values' bins in one copy
+// digit of pass p: bits [sel_shift(p), sel_shift(p) + sel_width(p))
+__device__ __forceinline__ int sel_shift(int pass) { return pass == 0 ? 21 : pass == 1 ? 10 : 0; }
+__device__ __forceinline__ int sel_width(int pass) { return pass == 2 ? 10 : 11; }
 
 struct MpScal {
   uint32_t umin, umax;      // ordered-int encodings of min/max U
@@ -61,7 +68,8 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
                                                              const float* __restrict__ C,
                                                              const float* __restrict__ Cg,
                                                              const int32_t* __restrict__ inst, float beta,
-                                                             float* __restrict__ e_out, double* __restrict__ part) {
+                                                             float* __restrict__ e_out, double* __restrict__ part,
+                                                             int64_t nrows) {
   const int64_t base = (int64_t)blockIdx.x * REG_TILE;
   float ev[PIX_ITEMS];
   int rv[PIX_ITEMS];
@@ -79,7 +87,9 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
       }
     }
   }
-  // per-wave partial sums of every region (no block barrier)
+  // per-wave partial sums of every region (no block barrier), stored
+  // [region][count, sum e, sum e^2][row] so that the final pass reads each
+  // region's rows contiguously
   const int64_t row = (int64_t)blockIdx.x * (GS_BLOCK / 64) + (threadIdx.x >> 6);
   for (int r = 0; r <= K; ++r) {
     double c = 0, s1 = 0, s2 = 0;
@@ -94,10 +104,10 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
     s1 = wave_sum_to_lane63_d(s1);
     s2 = wave_sum_to_lane63_d(s2);
     if (__lane_id() == 0) {
-      double* o = part + (row * MAXR + r) * 3;
+      double* o = part + (int64_t)r * 3 * nrows + row;
       o[0] = c;
-      o[1] = s1;
-      o[2] = s2;
+      o[nrows] = s1;
+      o[2 * nrows] = s2;
     }
   }
 }
@@ -109,11 +119,24 @@ __global__ __launch_bounds__(MAXR * 64) void mp_region_final_kernel(const double
   const int r = threadIdx.x >> 6, lane = __lane_id();
   if (r > K) return;
   double c = 0, s1 = 0, s2 = 0;
-  for (int b = lane; b < nrows; b += 64) {
-    const double* o = part + ((int64_t)b * MAXR + r) * 3;
-    c += o[0];
-    s1 += o[1];
-    s2 += o[2];
+  // each lane has kRowUnroll rows' loads in flight before it adds them, in
+  // row order
+  constexpr int kRowUnroll = 8;
+  for (int b0 = lane; b0 < nrows; b0 += kRowUnroll * 64) {
+    double x[kRowUnroll][3];
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) {
+      const int b = b0 + u * 64;
+      const double* o = part + (int64_t)r * 3 * nrows + b;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) x[u][q] = b < nrows ? o[(int64_t)q * nrows] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowUnroll; ++u) {
+      c += x[u][0];
+      s1 += x[u][1];
+      s2 += x[u][2];
+    }
   }
   c = wave_sum_to_lane63_d(c);
   s1 = wave_sum_to_lane63_d(s1);
@@ -299,7 +322,7 @@ __global__ __launch_bounds__(1024) void mp_ureduce_kernel(const uint32_t* __rest
                                                           MpScal* __restrict__ sc, uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_v[3][16];
   // the selection's histogram copies start every update cleared
-  for (int i = threadIdx.x; i < SEL_COPIES * 512; i += 1024) hist[i] = 0;
+  for (int i = threadIdx.x; i < SEL_COPIES * SEL_HIST; i += 1024) hist[i] = 0;
   uint32_t mn = 0xFFFFFFFFu, mx = 0u, cnt = 0u;
   for (int b = threadIdx.x; b < nb; b += 1024) {
     mn = min(mn, part_u[3 * b + 0]);
@@ -374,87 +397,94 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_state_kernel(ViewTab tab, GaussOu
 }
 
 
-// Radix select: pass `pass` (0 = bits 31..24) histograms the digit of every
-// observed value whose higher digits match the running prefix.
+// Radix select: pass `pass` histograms the digit (bits 31..21, 20..10, 9..0)
+// of every observed value whose higher digits match the running prefix.
 __global__ __launch_bounds__(GS_BLOCK) void mp_sel_hist_kernel(int64_t n, int64_t g_off, const uint8_t* __restrict__ obs,
                                                                const float* __restrict__ v0,
                                                                const float* __restrict__ v1, int pass,
                                                                const MpScal* __restrict__ sc,
                                                                uint32_t* __restrict__ part_h) {
-  __shared__ uint32_t h[2][256];
-  h[0][threadIdx.x] = 0;
-  h[1][threadIdx.x] = 0;
+  __shared__ uint32_t h[2][SEL_BINS];
+  for (int i = threadIdx.x; i < SEL_BINS; i += GS_BLOCK) {
+    h[0][i] = 0;
+    h[1][i] = 0;
+  }
   __syncthreads();
-  const int shift = 24 - 8 * pass;
-  const uint32_t hmask = pass == 0 ? 0u : (0xFFFFFFFFu << (shift + 8));
+  const int shift = sel_shift(pass);
+  const uint32_t dmask = (1u << sel_width(pass)) - 1u;
+  const uint32_t hmask = pass == 0 ? 0u : (0xFFFFFFFFu << (shift + sel_width(pass)));
   const uint32_t p0 = pass == 0 ? 0u : sc->prefix[0], p1 = pass == 0 ? 0u : sc->prefix[1];
   for (int64_t base = (int64_t)blockIdx.x * GS_BLOCK; base < n; base += (int64_t)gridDim.x * GS_BLOCK) {
     const int64_t k = base + threadIdx.x;
     const bool o = k < n && obs[k];
     const uint32_t a = o ? __float_as_uint(v0[g_off + k]) : 0u;
     const uint32_t b = o ? __float_as_uint(v1[g_off + k]) : 0u;
-    if (o && (a & hmask) == (p0 & hmask)) atomicAdd(&h[0][(a >> shift) & 255u], 1u);
-    if (o && (b & hmask) == (p1 & hmask)) atomicAdd(&h[1][(b >> shift) & 255u], 1u);
+    if (o && (a & hmask) == (p0 & hmask)) atomicAdd(&h[0][(a >> shift) & dmask], 1u);
+    if (o && (b & hmask) == (p1 & hmask)) atomicAdd(&h[1][(b >> shift) & dmask], 1u);
   }
   __syncthreads();
   // added into the histogram copy of the XCD the workgroup runs on, so the
   // workgroups of different XCDs do not contend for one address; the pick
   // sums the copies and clears them
-  uint32_t* hc = part_h + (__builtin_amdgcn_s_getreg((31 << 11) | 20) & (SEL_COPIES - 1)) * 512;
-  if (h[0][threadIdx.x]) atomicAdd(&hc[threadIdx.x], h[0][threadIdx.x]);
-  if (h[1][threadIdx.x]) atomicAdd(&hc[256 + threadIdx.x], h[1][threadIdx.x]);
+  uint32_t* hc = part_h + (__builtin_amdgcn_s_getreg((31 << 11) | 20) & (SEL_COPIES - 1)) * SEL_HIST;
+  for (int i = threadIdx.x; i < SEL_BINS; i += GS_BLOCK) {
+    if (h[0][i]) atomicAdd(&hc[i], h[0][i]);
+    if (h[1][i]) atomicAdd(&hc[SEL_BINS + i], h[1][i]);
+  }
 }
 
 // Sums the histogram copies (and clears them) and picks the digit holding
-// the running rank (one workgroup; one wave per 64 bins of each value scans
-// them).
+// the running rank (one workgroup: 512 threads per value, 4 bins each).
 __global__ __launch_bounds__(1024) void mp_sel_pick_kernel(int pass, uint32_t* __restrict__ part_h,
                                                            MpScal* __restrict__ sc) {
-  __shared__ uint32_t s_h[512];
-  __shared__ uint32_t s_wsum[8];
+  __shared__ uint32_t s_wsum[16];
   __shared__ uint32_t s_rank[2], s_prefix[2];
   const int t = threadIdx.x;
   if (t < 2) {  // the running state, read before any thread updates it
     s_rank[t] = pass == 0 ? (sc->n_obs > 0 ? (sc->n_obs - 1) / 2 : 0) : sc->rank[t];
     s_prefix[t] = pass == 0 ? 0u : sc->prefix[t];
   }
-  uint32_t acc = 0;
-  if (t < 512) {
+  const int which = t >> 9, d0 = 4 * (t & 511);  // value, first of this thread's bins
+  uint32_t c4[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = which * SEL_BINS + d0 + q;
+    uint32_t acc = 0;
 #pragma unroll
     for (int c = 0; c < SEL_COPIES; ++c) {
-      acc += part_h[c * 512 + t];
-      part_h[c * 512 + t] = 0;
+      acc += part_h[c * SEL_HIST + i];
+      part_h[c * SEL_HIST + i] = 0;
     }
+    c4[q] = acc;
   }
-  __syncthreads();
-  // inclusive scan of each value's 256 bins: four waves per value
-  uint32_t incl = 0, cnt = 0;
+  // inclusive scan of each value's bins: this thread's four, then over the
+  // value's eight waves
+  const uint32_t own = c4[0] + c4[1] + c4[2] + c4[3];
   const int lane = __lane_id(), w = t >> 6;
-  if (t < 512) {
-    cnt = acc;
-    s_h[t] = cnt;
-    incl = cnt;
+  uint32_t incl = own;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    if (lane == 63) s_wsum[w] = incl;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+    if (lane >= o) incl += y;
   }
+  if (lane == 63) s_wsum[w] = incl;
   __syncthreads();
-  if (t < 512) {
-    const int which = t >> 8, d = t & 255;
-    for (int i = which * 4; i < w; ++i) incl += s_wsum[i];
-    const uint32_t excl = incl - cnt;
-    const uint32_t rank = s_rank[which], prefix = s_prefix[which];
-    const int shift = 24 - 8 * pass;
+  for (int i = which * 8; i < w; ++i) incl += s_wsum[i];
+  uint32_t excl = incl - own;
+  const uint32_t rank = s_rank[which], prefix = s_prefix[which];
+  const int shift = sel_shift(pass), nbins = 1 << sel_width(pass);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int d = d0 + q;
+    const uint32_t e1 = excl + c4[q];
     // the bin holding the rank; past every bin, the last one with all counted
-    const bool hit = rank >= excl && rank < incl;
-    const bool last = d == 255 && rank >= incl;
+    const bool hit = d < nbins && rank >= excl && rank < e1;
+    const bool last = d == nbins - 1 && rank >= e1;
     if (hit || last) {
-      sc->rank[which] = rank - (hit ? excl : incl);
+      sc->rank[which] = rank - (hit ? excl : e1);
       sc->prefix[which] = prefix | ((uint32_t)d << shift);
     }
+    excl = e1;
   }
 }
 
@@ -548,7 +578,7 @@ MpWs mp_layout(int64_t n, int64_t P) {
   L.part = o; o += al((size_t)(nb > 0 ? nb : 1) * (GS_BLOCK / 64) * MAXR * 3 * 8);
   L.part_u = o; o += al((size_t)(gb > 0 ? gb : 1) * 3 * 4);
   L.part_l = o; o += al((size_t)(gb > 0 ? gb : 1) * 2 * 4);
-  L.part_h = o; o += al((size_t)SEL_COPIES * 512 * 4);
+  L.part_h = o; o += al((size_t)SEL_COPIES * SEL_HIST * 4);
   L.scal = o; o += al(sizeof(MpScal));
   L.Mhat = o; o += al(n * 4);
   L.sde = o; o += al(n * 4);
@@ -580,7 +610,7 @@ gs_status launch_mp_update(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj,
   const int nb = (int)((P + REG_TILE - 1) / REG_TILE);
   if (nb > 0)
     GS_LAUNCH(ctx, mp_region_kernel, dim3(nb), dim3(GS_BLOCK), 0, s, P, P, K, img->depth, tgt->depth, img->color,
-              tgt->color, fr->instance_id, pp->beta_color, e, part);
+              tgt->color, fr->instance_id, pp->beta_color, e, part, (int64_t)nb * (GS_BLOCK / 64));
   GS_LAUNCH(ctx, mp_region_final_kernel, dim3(1), dim3(MAXR * 64), 0, s, part, nb * (GS_BLOCK / 64), K,
             pp->lambda_e, pp->e_floor, pp->sigma_g, sc);
   if (P > 0)
@@ -596,7 +626,7 @@ gs_status launch_mp_update(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj,
     GS_LAUNCH(ctx, mp_state_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, go, sc, pp->sigma_c, pp->lambda_u,
               pp->alpha_min, pp->alpha_max, pp->rho, fr->seg_updated, pp->mode, pp->u_norm, pp->logodds_eps,
               pp->logodds_max, mp, out->U_tilde, out->alpha);
-  for (int pass = 0; pass < 4; ++pass) {
+  for (int pass = 0; pass < SEL_PASSES; ++pass) {
     GS_LAUNCH(ctx, mp_sel_hist_kernel, dim3(SEL_BLOCKS), dim3(GS_BLOCK), 0, s, n, tab.g_off[0], go.obs, mp,
               out->U_tilde, pass, sc, part_h);
     GS_LAUNCH(ctx, mp_sel_pick_kernel, dim3(1), dim3(1024), 0, s, pass, part_h, sc);
