@@ -247,6 +247,19 @@ def main():
     assert not over and inc == 0, "timed steps were not exact"
     ms = e0.elapsed_time(e1) / a.steps
     log(f"[bench] {'graph' if graph is not None else 'eager'}: {ms:.4f} ms/step ({1000.0 / ms:.1f} iters/s)")
+    # distribution of single steps (events around each), beside the mean above
+    single = []
+    for _ in range(a.steps):
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record()
+        if graph is not None:
+            graph.replay()
+        else:
+            step()
+        f1.record()
+        f1.synchronize()
+        single.append(f0.elapsed_time(f1))
+    p10, p50, p90 = (float(np.percentile(single, q)) for q in (10, 50, 90))
 
     # timed region 2: eager steps with per-kernel HIP events
     ctx.kernel_times()
@@ -290,6 +303,7 @@ def main():
         if b:
             total_bytes += b * n_l / a.steps
     iter_frac = total_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    copy_gbs = copy_bandwidth_gbs(torch)
 
     # per-frame MP update at the same scale (reported beside, not in the step)
     mp_ms, mp_graph_ms = mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td)
@@ -317,6 +331,9 @@ def main():
         "iteration_hbm_frac": round(iter_frac, 4),
         "eager_ms_per_step": round(eager_ms, 4),
         "kernel_us_per_step": {k: round(1000 * v, 2) for k, v in sorted(per_step.items(), key=lambda x: -x[1])},
+        "step_ms_p10_p50_p90": [round(p10, 4), round(p50, 4), round(p90, 4)],
+        "copy_gbs": round(copy_gbs, 1),
+        "iteration_copy_frac": round(total_bytes / (ms * 1e-3) / (copy_gbs * 1e9), 4),
         "mp_update_ms": round(mp_ms, 4),
         "mp_update_graph_ms": round(mp_graph_ms, 4),
         "wall_s_timed": round(t_wall, 3),
@@ -548,6 +565,26 @@ def pmc_traffic(kernel):
     if not rec or rec["sha256"] != kernel_source_hash(kernel):
         return None
     return int(1024 * (rec["fetch_kib"] * PMC_SCALE["fetch"] + rec["write_kib"] * PMC_SCALE["write"]))
+
+
+def copy_bandwidth_gbs(torch, nbytes=256 << 20, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes per second) of a
+    256 MiB buffer, median of `reps` copies: the stream rate the byte model is
+    also held against."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2 * nbytes / (float(np.median(ts)) * 1e-3) / 1e9
 
 
 def mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td):
