@@ -344,6 +344,7 @@ def main():
         out["window_batch"] = window_batch(ctx, a, g, g_t)
         out["uneven_batch"] = uneven_batch(ctx)
         out["learned_mp"] = learned_mp(ctx, a, g, cam, tc, td)
+        out["tracking"] = tracking_run(ctx)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, cam, tc.cpu().numpy().reshape(3, -1), td.cpu().numpy())
     print(json.dumps(out), flush=True)
@@ -430,6 +431,47 @@ def _batch_step(ctx, views, g_dev, tc, td, full=False):
     # the graph replays write these: they live as long as the step
     step.outputs = (grads, pose)
     return pipe, step, R, n_inst
+
+
+def tracking_run(ctx, n=200_000, W=640, H=480, iters=100):
+    """Pose-only tracking (the tracking configuration: 200k Gaussians, one
+    640x480 view, 100 iterations of render, loss, pose gradient, Adam on the
+    twist and retraction, replayed from one captured hip graph) from a pose
+    0.5 deg and 1 cm off the one the target was rendered at."""
+    import torch
+    from paper_2602_21644_amd import gs, optim, synth
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(2, n, W, H)
+    gd = gs.to_device(g)
+    tv = gs.ViewBatch([cam], n)
+    tp = gs.Pipeline(ctx, tv, capacity=n * 128)
+    tp.forward(gs.gaussians_struct(gd))
+    over, _, _ = tp.check()
+    assert not over
+    tc = tp.img_color.clone()
+    td = torch.where(1.0 - tp.img_T >= 0.5, tp.img_depth, torch.zeros_like(tp.img_depth)).contiguous()
+    del tp
+    T0 = synth.perturbed_pose(synth.rng_for(20), deg=0.5, trans=0.01, base=cam["T_cw"])
+    trk = optim.Tracker(ctx, gd, synth.camera(W, H, T0))
+    trk.run(tc, td, iters=2, T_init=T0)  # captures the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    T, loss, exact = trk.run(tc, td, iters=iters, T_init=T0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    Tt = np.asarray(cam["T_cw"], np.float64)
+    Rr = np.asarray(T, np.float64)[:, :3] @ Tt[:, :3].T
+    ang = float(np.degrees(np.arccos(np.clip((np.trace(Rr) - 1) / 2, -1.0, 1.0))))
+    # camera centres c = -R^T t
+    c_est = -np.asarray(T, np.float64)[:, :3].T @ np.asarray(T, np.float64)[:, 3]
+    c_true = -Tt[:, :3].T @ Tt[:, 3]
+    dist = float(np.linalg.norm(c_est - c_true))
+    log(f"[bench] tracking: {ms:.4f} ms per iteration, final error {ang:.4f} deg {dist * 1e3:.3f} mm")
+    return {"n_gaussians": n, "width": W, "height": H, "iterations": iters, "prefix_rank": trk.rank,
+            "ms_per_iteration": round(ms, 4), "iters_per_s": round(1000.0 / ms, 1),
+            "start_error": [0.5, 10.0], "final_error_deg_mm": [round(ang, 4), round(dist * 1e3, 3)],
+            "exact": bool(exact)}
 
 
 def window_batch(ctx, a, g, g_t):
