@@ -41,9 +41,12 @@ constexpr int PS_CAP = 12288;                   // selected records per view
 constexpr int PS_PER = PS_CAP / PS_THREADS;
 constexpr int PS_BUCKETS = 4096;
 constexpr int PS_MAXBLK = 4096;                 // selection blocks per view (8.4M records)
-// dynamic LDS of psort: keys and ids grouped by bucket, bucket cursors, and
-// the block offsets (later the bucket starts)
-constexpr size_t PS_LDS = (size_t)PS_CAP * 8 + (size_t)PS_BUCKETS * 4 + (size_t)(PS_MAXBLK + 1) * 4;
+// dynamic LDS of psort: keys and ids grouped by bucket, bucket cursors, the
+// block offsets (later the bucket starts), and the final position of each
+// bucket slot (16 bits)
+constexpr size_t PS_LDS =
+    (size_t)PS_CAP * 8 + (size_t)PS_BUCKETS * 4 + (size_t)(PS_MAXBLK + 1) * 4 + (size_t)PS_CAP * 2;
+static_assert(PS_CAP <= 65536, "final positions are 16-bit");
 static_assert(PS_BUCKETS == 4 * PS_THREADS && PS_MAXBLK == 4 * PS_THREADS, "4 entries per thread");
 
 __device__ __forceinline__ int sel_blocks(int64_t npad) { return (int)((npad + SEL_TILE - 1) / SEL_TILE); }
@@ -172,6 +175,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
   uint32_t* gi = gk + PS_CAP;        // [PS_CAP] ids
   uint32_t* cur = gi + PS_CAP;       // [PS_BUCKETS] bucket cursors
   uint32_t* bst = cur + PS_BUCKETS;  // [PS_MAXBLK + 1] block offsets, then bucket starts
+  uint16_t* fpos = reinterpret_cast<uint16_t*>(bst + PS_MAXBLK + 1);  // [PS_CAP] final position per slot
   __shared__ uint32_t s_w[PS_THREADS / 64];
   __shared__ uint32_t s_min, s_max, s_area;
   const int v = blockIdx.x;
@@ -284,38 +288,57 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     run += c4[q];
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PS_PER; ++q) {
-    if ((uint32_t)(q * PS_THREADS + tid) < n) {
-      const uint32_t pos = atomicAdd(&cur[(kr[q] - kmin) >> sh], 1u);
-      gk[pos] = kr[q];
-      gi[pos] = ir[q];
-    }
-  }
-  __syncthreads();
-  // 4. rank inside the bucket on (key, id) gives the final position; the
-  //    sorted ids and rects are staged in LDS and written out coalesced
-  uint32_t pos[PS_PER];
+  uint32_t pos[PS_PER];  // each record's slot in bucket order, then its final position
 #pragma unroll
   for (int q = 0; q < PS_PER; ++q) {
     pos[q] = 0;
     if ((uint32_t)(q * PS_THREADS + tid) < n) {
-      const uint32_t d = (kr[q] - kmin) >> sh;
-      const uint32_t b0 = bst[d], b1 = cur[d];
-      uint32_t rank = 0;
-      for (uint32_t i = b0; i < b1; ++i) {
-        const uint32_t k2 = gk[i], i2 = gi[i];
-        rank += (k2 < kr[q] || (k2 == kr[q] && i2 < ir[q])) ? 1u : 0u;
-      }
-      pos[q] = b0 + rank;
+      pos[q] = atomicAdd(&cur[(kr[q] - kmin) >> sh], 1u);
+      gk[pos[q]] = kr[q];
+      gi[pos[q]] = ir[q];
     }
   }
   __syncthreads();
+  // 4. rank inside the bucket on (key, id) gives the final position. Slot p
+  //    is ranked by thread p mod 1024, so neighbouring lanes walk the same
+  //    bucket in step (broadcast reads): a bucket can hold hundreds of
+  //    entries (a surface facing the camera puts many Gaussians at one
+  //    depth). The sorted ids and rects are then staged in LDS and written
+  //    out coalesced.
+  for (uint32_t p = tid; p < n; p += PS_THREADS) {
+    const uint32_t kp = gk[p], ip = gi[p];
+    const uint32_t d = (kp - kmin) >> sh;
+    const uint32_t b0 = bst[d], b1 = cur[d];
+    uint32_t rank = 0, i = b0;
+    for (; i + 4 <= b1; i += 4) {  // four entries' loads in flight per step
+      uint32_t k2[4], i2[4];
 #pragma unroll
-  for (int q = 0; q < PS_PER; ++q)
-    if ((uint32_t)(q * PS_THREADS + tid) < n) gi[pos[q]] = ir[q];
+      for (int u = 0; u < 4; ++u) {
+        k2[u] = gk[i + u];
+        i2[u] = gi[i + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rank += (k2[u] < kp || (k2[u] == kp && i2[u] < ip)) ? 1u : 0u;
+    }
+    for (; i < b1; ++i) {
+      const uint32_t k2 = gk[i], i2 = gi[i];
+      rank += (k2 < kp || (k2 == kp && i2 < ip)) ? 1u : 0u;
+    }
+    fpos[p] = (uint16_t)(b0 + rank);
+  }
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += PS_THREADS) sorted_ids[roff + i] = gi[i];
+  // each record's id moves from its bucket slot (gi) to its final position
+  // in gk (the keys are no longer needed)
+#pragma unroll
+  for (int q = 0; q < PS_PER; ++q) {
+    if ((uint32_t)(q * PS_THREADS + tid) < n) {
+      const uint32_t slot = pos[q];
+      pos[q] = fpos[slot];
+      gk[pos[q]] = gi[slot];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += PS_THREADS) sorted_ids[roff + i] = gk[i];
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PS_PER; ++q) {
