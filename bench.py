@@ -111,8 +111,8 @@ def kernel_bytes(name, st):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU view sharding is "
-                                   "described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "mpsplat runs on one GPU; --gpus must be 1 (sharding the views over "
+                                   "several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
 
