@@ -210,9 +210,10 @@ const char* gs_last_error(const gs_ctx* ctx);
  * heaviest first and gs_render_bwd runs its tiles in it), "bwd_copies" (1|2|4|8, default 8: accumulators of the per-record
  * 2D adjoint in the gs_render_bwd scratch, one per group of XCDs, so atomics
  * from different XCDs do not contend for one address; summed in a fixed
- * order), "wave_cull" (0|1, default 1: in gs_render_fwd each 64-pixel wave
- * skips the entries whose alpha >= 1/255 region misses its 16x4 pixel strip;
- * the outputs are bit-identical either way), "bwd_mfma" (0|1, default 0: 1
+ * order), "wave_cull" (0|1, default 1: in gs_render_fwd and gs_render_bwd
+ * each 64-pixel wave skips the entries whose alpha >= 1/255 region misses its
+ * 16x4 pixel strip; the images are bit-identical either way, the gradients
+ * equal up to the order of their float atomics), "bwd_mfma" (0|1, default 0: 1
  * forms the backward's per-entry pixel sums with FP32 matrix instructions
  * instead of wave reductions; same gradients up to summation order), and
  * "timing" (0|1, see gs_ctx_kernel_times). Values outside the supported set

@@ -60,7 +60,7 @@ __device__ __forceinline__ uint32_t strip_mask(const float4& A, const float4& B,
 }
 
 template <int BATCH>
-__global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
+__global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void render_fwd_kernel(
     ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, const int32_t* __restrict__ trunc,
     float bg0, float bg1, float bg2, float* __restrict__ outC, float* __restrict__ outD, float* __restrict__ outM,
@@ -69,6 +69,10 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
   // slot BATCH is a zero-opacity entry that pads a wave's last group of four
   __shared__ float4 s_a[BATCH + 1], s_b[BATCH + 1], s_c[BATCH + 1];
   __shared__ uint8_t s_mask[BATCH];
+  // per wave: byte offsets of the batch entries whose mask has the wave's
+  // strip, in list order, padded to a multiple of four with the zero entry
+  __shared__ __align__(16) uint32_t s_list[GS_BLOCK / 64][BATCH + 4];
+  static_assert(BATCH % 4 == 0, "list rows stay 16-byte aligned");
   __shared__ uint32_t s_wmax[GS_BLOCK / 64];
   __shared__ double s_loss[GS_BLOCK / 64];
   if (*overflow) {
@@ -155,47 +159,52 @@ __global__ __launch_bounds__(GS_BLOCK) void render_fwd_kernel(
       const int n = (int)min((uint32_t)BATCH, e - base);
       const uint32_t idx0 = base - b + 1;
       // The wave walks only the entries whose mask has its strip, in list
-      // order, taken 64 at a time from a ballot; branch-free per entry (every
-      // lane evaluates, the predicates select), groups of four padded with
-      // the zero entry, the early exit tested once per group.
-      bool all_done = false;
-      for (int c0 = 0; c0 < n && !all_done; c0 += 64) {
+      // order: it first compacts their LDS offsets into its own list (a
+      // ballot per 64 entries), then takes them four at a time, branch-free
+      // per entry (every lane evaluates, the predicates select), the early
+      // exit tested once per group of four.
+      uint32_t* lst = s_list[w];
+      int cnt = 0;
+      for (int c0 = 0; c0 < n; c0 += 64) {
         const int jl = c0 + lane;
-        uint64_t ball = __ballot(jl < n && ((s_mask[jl < BATCH ? jl : 0] >> w) & 1u));
-        while (ball) {
-          int js[4];
+        const bool mine = jl < n && ((s_mask[jl < BATCH ? jl : 0] >> w) & 1u);
+        const uint64_t ball = __ballot(mine);
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(ball >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+        if (mine) lst[cnt + below] = (uint32_t)jl * (uint32_t)sizeof(float4);
+        cnt += __popcll(ball);
+      }
+      const int cnt4 = (cnt + 3) & ~3;
+      if (lane < cnt4 - cnt) lst[cnt + lane] = (uint32_t)BATCH * (uint32_t)sizeof(float4);
+      __builtin_amdgcn_wave_barrier();
+      const char* pa = reinterpret_cast<const char*>(s_a);
+      const char* pb = reinterpret_cast<const char*>(s_b);
+      const char* pc = reinterpret_cast<const char*>(s_c);
+      for (int k = 0; k < cnt4; k += 4) {
+        const uint4 o4 = *reinterpret_cast<const uint4*>(&lst[k]);
+        const uint32_t os[4] = {o4.x, o4.y, o4.z, o4.w};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            js[u] = ball ? c0 + __ffsll((long long)ball) - 1 : BATCH;
-            ball &= ball - 1;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int j = js[u];
-            const float4 A = s_a[j];
-            const float4 B = s_b[j];
-            const float4 Cc = s_c[j];
-            const float p = gs_power2(B.x, B.y, B.z, A.x - fx, A.y - fy);
-            const float alpha = fminf(GS_ALPHA_MAX, A.w * __builtin_amdgcn_exp2f(p));
-            const bool ok = !done && p <= 0.f && alpha >= GS_ALPHA_MIN;
-            const float Tn = T * (1.0f - alpha);
-            const bool stop = ok && Tn < GS_T_MIN;
-            const bool add = ok != stop;  // ok and not stop (stop implies ok)
-            done = done || stop;
-            const float wgt = add ? alpha * T : 0.f;
-            C0 += wgt * Cc.x;
-            C1 += wgt * Cc.y;
-            C2 += wgt * Cc.z;
-            D += wgt * A.z;
-            Mm += wgt * B.w;
-            T = add ? Tn : T;
-            last = add ? idx0 + j : last;
-          }
-          if (__all(done)) {
-            all_done = true;
-            break;
-          }
+        for (int u = 0; u < 4; ++u) {
+          const float4 A = *reinterpret_cast<const float4*>(pa + os[u]);
+          const float4 B = *reinterpret_cast<const float4*>(pb + os[u]);
+          const float4 Cc = *reinterpret_cast<const float4*>(pc + os[u]);
+          const float p = gs_power2(B.x, B.y, B.z, A.x - fx, A.y - fy);
+          const float alpha = fminf(GS_ALPHA_MAX, A.w * __builtin_amdgcn_exp2f(p));
+          const bool ok = !done && p <= 0.f && alpha >= GS_ALPHA_MIN;
+          const float Tn = T * (1.0f - alpha);
+          const bool stop = ok && Tn < GS_T_MIN;
+          const bool add = ok != stop;  // ok and not stop (stop implies ok)
+          done = done || stop;
+          const float wgt = add ? alpha * T : 0.f;
+          C0 += wgt * Cc.x;
+          C1 += wgt * Cc.y;
+          C2 += wgt * Cc.z;
+          D += wgt * A.z;
+          Mm += wgt * B.w;
+          T = add ? Tn : T;
+          last = add ? idx0 + os[u] / (uint32_t)sizeof(float4) : last;
         }
+        if (__all(done)) break;
       }
     }
   }
@@ -347,13 +356,19 @@ __global__ __launch_bounds__(kOrderThreads) void fwd_finish_kernel(ViewTab tab, 
 // (d/du = -o * conic * (sum h*d), d/dconic = -o/2 * (sum h*d d^T) off-diagonal
 // counted twice), so the per-pixel work carries no conic products.
 template <int BATCH>
-__global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
+__global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void render_bwd_kernel(
     ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
     const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
     const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
-    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies) {
+    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies,
+    int cull) {
   __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
+  __shared__ uint8_t s_mask[BATCH];
+  // per wave: the batch entries it walks (mask has its strip, inside its
+  // longest n_last), in list order
+  __shared__ int32_t s_list[GS_BLOCK / 64][BATCH];
+  __shared__ uint32_t s_wmax[GS_BLOCK / 64];
   // [entry][wave * 4 + row]: the three row totals of wave_sum10; the 17th
   // slot staggers the entries across LDS banks for the cross-wave pass
   __shared__ float4 s_red[BATCH][17];
@@ -399,7 +414,10 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
   uint32_t wmax = nl;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, o, 64));
-  if (lane == 0) atomicMax(&s_max, wmax);
+  if (lane == 0) {
+    atomicMax(&s_max, wmax);
+    s_wmax[w] = wmax;
+  }
   __syncthreads();
   const uint32_t maxl = s_max;
   // Batches walk back: [lo, hi) with hi = maxl, then hi = previous lo. As in
@@ -427,6 +445,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
       s_a[tid] = ra;
       s_b[tid] = rb;
       s_c[tid] = rc;
+      s_mask[tid] = cull ? (uint8_t)strip_mask(ra, rb, tc.tx * GS_TILE, tc.ty * GS_TILE) : (uint8_t)0xF;
     }
     __syncthreads();
     {
@@ -444,7 +463,7 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     auto entry = [&](int jj, const float4& A, const float4& B) {
       const int j = lo + jj;
       float k[3] = {0.f, 0.f, 0.f};
-      if ((uint32_t)j < wmax) {  // uniform over the wave
+      {
         const float dx = A.x - fx, dy = A.y - fy;
         const float p = gs_power2(B.x, B.y, B.z, dx, dy);
         const float G = __builtin_amdgcn_exp2f(p);
@@ -478,19 +497,31 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
       }
       if ((lane & 15) == 15) s_red[jj][w * 4 + (lane >> 4)] = make_float4(k[0], k[1], k[2], 0.f);
     };
-    float4 A0 = s_a[n - 1], B0 = s_b[n - 1], A1, B1;
-    int jj = n - 1;
-    for (; jj >= 1; jj -= 2) {
-      A1 = s_a[jj - 1];
-      B1 = s_b[jj - 1];
-      entry(jj, A0, B0);
-      if (jj >= 2) {
-        A0 = s_a[jj - 2];
-        B0 = s_b[jj - 2];
-      }
-      entry(jj - 1, A1, B1);
+    // An entry the wave does not walk has no pixel of the wave with alpha
+    // >= 1/255 (its mask misses the strip) or lies past every pixel's n_last:
+    // it adds nothing, and the cross-wave pass skips the wave's rows of it.
+    // The rest are compacted by a ballot per 64 entries and walked from the
+    // back.
+    int32_t* lst = s_list[w];
+    int cnt = 0;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int jl = c0 + lane;
+      const bool mine = jl < n && (uint32_t)(lo + jl) < wmax && ((s_mask[jl < BATCH ? jl : 0] >> w) & 1u);
+      const uint64_t ball = __ballot(mine);
+      const int below =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, 0u));
+      if (mine) lst[cnt + below] = jl;
+      cnt += __popcll(ball);
     }
-    if (jj == 0) entry(0, A0, B0);
+    __builtin_amdgcn_wave_barrier();
+    // the next entry's index is read from the list while one is processed
+    int jn = cnt > 0 ? lst[cnt - 1] : 0;
+#pragma unroll 1
+    for (int kk = cnt - 1; kk >= 0; --kk) {
+      const int j0 = jn;
+      jn = lst[kk > 0 ? kk - 1 : 0];
+      entry(j0, s_a[j0], s_b[j0]);
+    }
     __syncthreads();
     // The cross-wave pass runs on the waves that load nothing: one counter
     // tracks both loads and atomics, so the loader waves' wait for the next
@@ -503,11 +534,15 @@ __global__ __launch_bounds__(GS_BLOCK) void render_bwd_kernel(
     const int q = tid - kLoadThreads;
     if (q >= 0 && q < n) {
       const int jj = q;
+      const uint32_t msk = s_mask[jj];
       float4 rw[4][4];
 #pragma unroll
-      for (int ww = 0; ww < 4; ++ww)
+      for (int ww = 0; ww < 4; ++ww) {
+        const bool walked = ((msk >> ww) & 1u) && (uint32_t)(lo + jj) < s_wmax[ww];
 #pragma unroll
-        for (int row = 0; row < 4; ++row) rw[ww][row] = s_red[jj][ww * 4 + row];
+        for (int row = 0; row < 4; ++row)
+          rw[ww][row] = walked ? s_red[jj][ww * 4 + row] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
       float4 t0 = rw[0][0], t1 = rw[0][1], t2 = rw[0][2], t3 = rw[0][3];
 #pragma unroll
       for (int ww = 1; ww < 4; ++ww) {
@@ -882,7 +917,7 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
   else                                                                                                         \
     GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,    \
               bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
-              g2d, touched, order, ctx->bwd_copies)
+              g2d, touched, order, ctx->bwd_copies, ctx->wave_cull)
   switch (ctx->bwd_batch) {
     case 32: GS_BWD(32); break;
     case 128: GS_BWD(128); break;

@@ -353,7 +353,8 @@ def test_backward_tile_order(ctx, orc):
                                                  (23, 3000, 100, 75, 0)])
 def test_wave_cull_exact(ctx, seed, n, W, H, max_rank):
     """Skipping, per 16x4 pixel strip, the entries whose alpha >= 1/255 region
-    misses the strip leaves every output bit-identical, and so does the
+    misses the strip (forward and backward) leaves every image bit-identical,
+    and so does the
     forward's launch order (the first forward runs in natural order, the
     later ones in the order the backward dealt); the gradients agree up to
     the order of their float atomics."""
