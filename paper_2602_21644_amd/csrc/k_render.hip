@@ -35,26 +35,41 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewTab& tab, int t) {
 // Which of a tile's four 16x4 pixel strips (wave w: rows 4w .. 4w+3) an entry
 // can composite in: bit w clear only when no pixel of the strip reaches
 // alpha >= 1/255. The region where o 2^p >= 1/255, p = c1 dx^2 + c2 dx dy +
-// c3 dy^2 (the record's base-2 conic), is the ellipse Q <= tau with
-// Q = -p and tau = log2(255 o); its bounding box has half-widths
-// sqrt(4 c tau / D) and sqrt(4 a tau / D), (a, b, c) = -(c1, c2, c3),
-// D = 4ac - b^2. The box is widened by 0.1% and one pixel against rounding;
-// degenerate or non-finite cases keep every strip, o < 1/255 none.
+// c3 dy^2 (the record's base-2 conic, d = mean - pixel), is the ellipse
+// Q <= tau with Q = -p = a dx^2 + b dx dy + c dy^2, (a, b, c) = -(c1, c2, c3),
+// and tau = log2(255 o); D = 4ac - b^2. Its half-widths are
+// rx = sqrt(4 c tau / D) and ry = sqrt(4 a tau / D). For fixed dx the ellipse
+// spans dy = (-b dx +- sqrt(4 c tau - D dx^2)) / (2c); the upper branch is
+// concave with its top (dy = ry) at dx = -b ry / (2a), the lower convex with
+// its bottom at the opposite dx. So over the tile's columns (dx in an
+// interval, cut to |dx| <= rx) the ellipse's rows run from the lower branch at
+// the bottom point's dx clamped into the interval to the upper branch at the
+// top point's dx clamped into it. The strips that range meets are kept. The
+// column interval and the row range are widened by 0.1% of the half-width
+// and one pixel against rounding; degenerate or non-finite cases keep every
+// strip, o < 1/255 none.
 __device__ __forceinline__ uint32_t strip_mask(const float4& A, const float4& B, int x0, int y0) {
   const float tau = __log2f(255.0f * A.w);
   if (tau < 0.f) return 0u;
   const float a = -B.x, bq = -B.y, c = -B.z;
   const float D = 4.0f * a * c - bq * bq;
-  if (!(D > 0.f) || !(tau < 1e30f)) return 0xFu;
-  const float rx = sqrtf(4.0f * c * tau / D) * 1.001f + 1.0f;
-  const float ry = sqrtf(4.0f * a * tau / D) * 1.001f + 1.0f;
+  if (!(D > 0.f) || !(a > 0.f) || !(c > 0.f) || !(tau < 1e30f)) return 0xFu;
+  const float rx = sqrtf(4.0f * c * tau / D), ry = sqrtf(4.0f * a * tau / D);
   if (!(rx < 1e30f) || !(ry < 1e30f) || !(fabsf(A.x) < 1e30f) || !(fabsf(A.y) < 1e30f)) return 0xFu;
-  if (A.x + rx < (float)x0 || A.x - rx > (float)(x0 + 15)) return 0u;
+  const float mx = 0.001f * rx + 1.0f, my = 0.001f * ry + 1.0f;
+  const float dl = fmaxf(A.x - (float)(x0 + 15) - mx, -rx), dh = fminf(A.x - (float)x0 + mx, rx);
+  if (dl > dh) return 0u;
+  const float dxt = -bq * ry / (2.0f * a);
+  const float et = fminf(fmaxf(dxt, dl), dh), eb = fminf(fmaxf(-dxt, dl), dh);
+  const float st = sqrtf(fmaxf(0.f, 4.0f * c * tau - D * et * et));
+  const float sb = sqrtf(fmaxf(0.f, 4.0f * c * tau - D * eb * eb));
+  const float i2c = 0.5f / c;
+  const float ylo = A.y - (-bq * et + st) * i2c - my, yhi = A.y - (-bq * eb - sb) * i2c + my;
   uint32_t m = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const float ya = (float)(y0 + 4 * w), yb = (float)(y0 + 4 * w + 3);
-    if (!(A.y + ry < ya || A.y - ry > yb)) m |= 1u << w;
+    if (!(yhi < ya || ylo > yb)) m |= 1u << w;
   }
   return m;
 }
