@@ -153,9 +153,9 @@ typedef struct gs_image {
   uint32_t* tile_work; /* [2 n_tiles + 1] optional (NULL skips), zero-filled
                           before first use, then owned by the library: tile
                           scheduling state. [0, n_tiles): written by
-                          gs_render_fwd, per tile the sum over its four
-                          64-pixel groups (pixel rows 4i..4i+3) of the largest
-                          n_last in the group. [n_tiles, 2 n_tiles]: a launch
+                          gs_render_fwd, per tile the number of list entries
+                          its four 64-pixel groups (pixel rows 4i..4i+3)
+                          evaluated, summed. [n_tiles, 2 n_tiles]: a launch
                           order heaviest first and a marker, dealt by
                           gs_render_fwd (and gs_render_fwd_loss) from the work
                           it just wrote when "tile_order" is on, used by the

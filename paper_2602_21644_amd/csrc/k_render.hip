@@ -126,6 +126,7 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
   }
   float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, Mm = 0.f;
   uint32_t last = 0;
+  uint32_t walked = 0;  // entries this wave evaluated (uniform over the wave)
   bool done = !tc.inside;
   bool exhausted = true;
   // Software pipeline: while a batch is composited, the loader threads hold
@@ -195,7 +196,8 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
       const char* pa = reinterpret_cast<const char*>(s_a);
       const char* pb = reinterpret_cast<const char*>(s_b);
       const char* pc = reinterpret_cast<const char*>(s_c);
-      for (int k = 0; k < cnt4; k += 4) {
+      int k = 0;
+      for (; k < cnt4; k += 4) {
         const uint4 o4 = *reinterpret_cast<const uint4*>(&lst[k]);
         const uint32_t os[4] = {o4.x, o4.y, o4.z, o4.w};
 #pragma unroll
@@ -219,8 +221,12 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
           T = add ? Tn : T;
           last = add ? idx0 + os[u] / (uint32_t)sizeof(float4) : last;
         }
-        if (__all(done)) break;
+        if (__all(done)) {
+          k += 4;
+          break;
+        }
       }
+      walked += (uint32_t)k;
     }
   }
   // a truncated list ran out while some pixel still lets light through
@@ -242,13 +248,10 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
     if (la.Cg) lsum = pixel_loss(la, P, tc.pix, c0, c1, c2, D, Mm, T, tg0, tg1, tg2, tgd);
   }
   if (tile_work || la.Cg) {
-    // the backward's work on this tile: each wave walks to its largest n_last;
-    // the tile's loss partial
-    uint32_t m = last;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    // the tile's work: the entries its four waves evaluated; the tile's loss
+    // partial
     if (la.Cg) lsum = wave_sum_to_lane63_d(lsum);
-    if (lane == 0) s_wmax[w] = m;
+    if (lane == 0) s_wmax[w] = walked;
     if (lane == 63) s_loss[w] = lsum;
     __syncthreads();
     if (threadIdx.x == 0) {
