@@ -513,3 +513,63 @@ def test_render_fwd_loss_fused(ctx, seed, n, W, H, weight_mode, gtw, max_rank, n
         assert torch.equal(getattr(pipe, k), ref[k]), k
     torch.testing.assert_close(pipe.loss, ref_loss, rtol=1e-6, atol=0)
     assert float(ref_loss.abs().min()) > 0
+
+
+def _thin_gaussians_on_strip_edges(seed, n, W, H):
+    """Gaussians that test the strip test's edges: one long and one very short
+    axis at every angle, projected means a fraction of a pixel from 16x4 strip
+    and 16x16 tile boundaries, opacities from just below to well above
+    1/255."""
+    rng = synth.rng_for(seed)
+    fx, fy, cx, cy = synth.intrinsics(W, H)
+    gx, gy = W // 16, H // 16
+    px = rng.integers(0, gx, n) * 16 + rng.choice([-0.4, -0.01, 0.0, 0.01, 0.4, 7.5], n)
+    py = rng.integers(0, gy * 4, n) * 4 + rng.choice([-0.6, -0.02, 0.0, 0.02, 0.6, 1.5], n)
+    z = rng.uniform(1.0, 3.0, n)
+    mean = np.stack([z * (px - cx) / fx, z * (py - cy) / fy, z])
+    log_scale = np.stack([rng.uniform(-2.5, -1.0, n), rng.uniform(-7.0, -5.0, n), rng.uniform(-7.0, -5.0, n)])
+    ang = rng.uniform(0.0, np.pi, n)  # rotation about the optical axis
+    quat = np.stack([np.cos(ang / 2), np.zeros(n), np.zeros(n), np.sin(ang / 2)])
+    opl = np.log(1.0 / 255.0 / (1.0 - 1.0 / 255.0)) + rng.choice([-0.05, 0.02, 0.3, 2.0, 6.0], n)
+    g = synth._pack(mean, log_scale, quat, opl, rng.random((3, n)), rng.random(n))
+    return g, synth.camera(W, H)
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_wave_cull_exact_thin_edges(ctx, seed):
+    """The strip test keeps every strip in which some pixel reaches alpha >=
+    1/255, also for needle-like Gaussians at every angle whose means sit on
+    strip and tile edges and whose opacities straddle 1/255: the images are
+    bit-identical with and without culling, and so are the colour and opacity
+    gradients up to the order of their float atomics. (The geometry
+    gradients of needles are ill-conditioned: per-tile conic adjoints of
+    opposite sign meet in the atomic sums and the chain through the inverse
+    covariance amplifies their rounding, so that two runs with the same
+    settings already differ by percents; they are not compared here.)"""
+    n, W, H = 4000, 320, 240
+    g, cam = _thin_gaussians_on_strip_edges(seed, n, W, H)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], bg=(0.3, 0.2, 0.1))
+    outs, grads = [], []
+    tc = td = None
+    for cull in (1, 0):
+        ctx.set_param("wave_cull", cull)
+        pipe.forward(gst)
+        if tc is None:
+            tc, td = (pipe.img_color * 0.7).contiguous(), (pipe.img_depth * 1.2).contiguous()
+        pipe.loss_and_grads(tc, td)
+        gr = gs.alloc_grads(n)
+        pose = torch.zeros(6, device="cuda")
+        pipe.backward(gst, gs.grads_struct(gr, pose))
+        torch.cuda.synchronize()
+        outs.append([t.clone() for t in (pipe.img_color, pipe.img_depth, pipe.img_mp, pipe.img_T, pipe.img_nlast)])
+        grads.append((gr, pose))
+    ctx.set_param("wave_cull", 1)
+    over, n_inst, inc = pipe.check()
+    assert not over and n_inst > 0
+    assert float((1.0 - outs[0][3]).sum()) > 0.05 * W * H  # the needles cover the image
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    for k in ("color", "opacity_logit"):
+        assert_grads_close(torch_np(grads[1][0][k]), torch_np(grads[0][0][k]), rel=1e-5, name=k)
+    for k in grads[0][0]:
+        assert np.isfinite(torch_np(grads[1][0][k])).all() and np.isfinite(torch_np(grads[0][0][k])).all()
