@@ -54,7 +54,7 @@ def lib():
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         L.or_project.argtypes = [I64] + [P] * 5 + [P] * 9
-        L.or_render.argtypes = [I64] + [P] * 8 + [ctypes.c_int, ctypes.c_int, P, I64, P] + [P] * 6
+        L.or_render.argtypes = [I64] + [P] * 8 + [ctypes.c_int, ctypes.c_int, P, I64, P] + [P] * 6 + [ctypes.c_int]
         L.or_render_backward.argtypes = [I64] + [P] * 8 + [ctypes.c_int, ctypes.c_int, P, I64, P] + [P] * 5
         L.or_project_backward.argtypes = [I64] + [P] * 5 + [P] * 7
         L.or_num_threads.restype = ctypes.c_int
@@ -123,10 +123,15 @@ def tile_rect(mean2d, radius, kept, width, height, tile=16):
 
 
 # ------------------------------------------------------------------ render
-def render(proj: dict, g: dict, cam: dict, bg=(0.0, 0.0, 0.0), pixels=None) -> dict:
+def render(proj: dict, g: dict, cam: dict, bg=(0.0, 0.0, 0.0), pixels=None, order="f32") -> dict:
     """Tile-free FP64 render: every kept Gaussian per pixel in (float32 depth
     key, id) order with the alpha clamp, the 1/255 cut-off and the T < 1e-4 stop.
-    Returns C[3,P], D, M (MP channel), T (final), margin, ncontrib."""
+    Returns C[3,P], D, M (MP channel), T (final), margin, ncontrib.
+
+    order="f64" orders by the float64 camera z instead, and the margin then
+    also holds the smallest relative depth gap between consecutive Gaussians
+    that take part in the pixel (used to measure what deciding the order in
+    float32 changes)."""
     n = g["opacity_logit"].shape[0]
     W, H = cam["width"], cam["height"]
     if pixels is None:
@@ -141,7 +146,7 @@ def render(proj: dict, g: dict, cam: dict, bg=(0.0, 0.0, 0.0), pixels=None) -> d
     lib().or_render(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(proj["zkey"]),
                     _p(proj["opacity"]),
                     _p(color), _p(mp), _p(kept), W, H, _p(bgv), npix, _p(pix), _p(out["C"]), _p(out["D"]),
-                    _p(out["M"]), _p(out["T"]), _p(out["margin"]), _p(out["ncontrib"]))
+                    _p(out["M"]), _p(out["T"]), _p(out["margin"]), _p(out["ncontrib"]), 1 if order == "f64" else 0)
     return out
 
 

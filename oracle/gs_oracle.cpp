@@ -185,7 +185,9 @@ Proj project_one(const Cam& cam, const double mean[3], const double ls[3], const
   return P;
 }
 
-// Kept Gaussians in ascending (float32 depth key, id) order.
+// Kept Gaussians in ascending (depth key, id) order. The key is the float32
+// camera z of the projection (`zkey`) or, for measuring what that choice
+// changes, the float64 camera z (`depth`).
 std::vector<int64_t> depth_order(int64_t n, const double* zkey, const uint8_t* kept) {
   std::vector<int64_t> ord;
   ord.reserve(n);
@@ -204,11 +206,17 @@ struct Step {
 
 // Front-to-back compositing of one pixel. Records the contributing steps when
 // `steps` is non-null and returns the margin to the nearest discontinuity.
+// With `gap_margin` set, the margin also takes the relative depth gap between
+// consecutive Gaussians that take part in the pixel (those added, and the one
+// that stops it): where two of them are nearly level, an order decided in
+// another precision may swap them.
 double composite_pixel(int i, int j, const std::vector<int64_t>& ord, const double* mean2d, int64_t n,
                        const double* conic, const double* depth, const double* opacity, const double* color,
-                       const double* mp, double out[6], std::vector<Step>* steps, int* ncontrib) {
+                       const double* mp, double out[6], std::vector<Step>* steps, int* ncontrib,
+                       bool gap_margin = false) {
   double T = 1.0, C[3] = {0, 0, 0}, D = 0, M = 0;
   double margin = 1e30;
+  double zprev = -1.0;
   int nc = 0;
   for (size_t s = 0; s < ord.size(); ++s) {
     const int64_t k = ord[s];
@@ -225,6 +233,10 @@ double composite_pixel(int i, int j, const std::vector<int64_t>& ord, const doub
     if (alpha < 1.0 / 255.0) continue;
     const double Tn = T * (1.0 - alpha);
     margin = std::min(margin, std::fabs(std::log(Tn / 1e-4)));
+    if (gap_margin) {
+      if (zprev > 0) margin = std::min(margin, std::fabs(depth[k] - zprev) / depth[k]);
+      zprev = depth[k];
+    }
     if (Tn < 1e-4) break;
     if (steps) steps->push_back(Step{k, alpha, T, G, araw > 0.99, dx, dy});
     for (int c = 0; c < 3; ++c) C[c] += alpha * T * color[c * n + k];
@@ -287,12 +299,15 @@ int or_project(int64_t n, const double* mean, const double* log_scale, const dou
 
 // Tile-free render. If npix >= 0, only the listed pixel indices (y*W + x) are
 // rendered and outputs are indexed by position in that list; otherwise all W*H.
+// order_f64 = 1 orders by the float64 camera z instead of the float32 key
+// and adds the depth-gap term to the margin (a measurement aid; the parity
+// reference is order_f64 = 0).
 int or_render(int64_t n, const double* mean2d, const double* conic, const double* depth, const double* zkey,
               const double* opacity, const double* color, const double* mp, const uint8_t* kept, int W, int H,
               const double* bg,
               int64_t npix, const int64_t* pix, double* C, double* D, double* M, double* T, double* margin,
-              int32_t* ncontrib) {
-  const std::vector<int64_t> ord = depth_order(n, zkey, kept);
+              int32_t* ncontrib, int order_f64) {
+  const std::vector<int64_t> ord = depth_order(n, order_f64 ? depth : zkey, kept);
   const int64_t P = npix >= 0 ? npix : (int64_t)W * H;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t q = 0; q < P; ++q) {
@@ -300,7 +315,8 @@ int or_render(int64_t n, const double* mean2d, const double* conic, const double
     const int i = (int)(id % W), j = (int)(id / W);
     double out[6];
     int nc = 0;
-    const double mg = composite_pixel(i, j, ord, mean2d, n, conic, depth, opacity, color, mp, out, nullptr, &nc);
+    const double mg =
+        composite_pixel(i, j, ord, mean2d, n, conic, depth, opacity, color, mp, out, nullptr, &nc, order_f64 != 0);
     for (int c = 0; c < 3; ++c) C[c * P + q] = out[c] + out[5] * bg[c];
     D[q] = out[3];
     M[q] = out[4];
