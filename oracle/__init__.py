@@ -284,5 +284,35 @@ def bin_reference(rect, key, tile_grid, tile_base=0):
     return vals, ranges
 
 
+def bin_reference_np(rect, key, tile_grid, tile_base=0):
+    """The same per-tile lists as `bin_reference`, built with array
+    operations so that tens of millions of instances fit in seconds: every
+    non-empty record expanded over its rectangle, then numpy's stable sort of
+    the (tile << 32 | depth bits) keys."""
+    gx, gy = tile_grid
+    rect = np.asarray(rect).astype(np.int64)
+    key = np.asarray(key, np.uint32)
+    ok = key != 0xFFFFFFFF
+    rid = np.nonzero(ok)[0]
+    x0, y0, x1, y1 = (rect[rid, c] for c in range(4))
+    w = x1 - x0 + 1
+    cnt = w * (y1 - y0 + 1)
+    rec = np.repeat(rid, cnt)
+    start = np.cumsum(cnt) - cnt
+    j = np.arange(rec.size, dtype=np.int64) - np.repeat(start, cnt)  # index inside the record's rect
+    wr = np.repeat(w, cnt)
+    tx = np.repeat(x0, cnt) + j % wr
+    ty = np.repeat(y0, cnt) + j // wr
+    tiles = tile_base + ty * gx + tx
+    keys = (tiles.astype(np.uint64) << np.uint64(32)) | key[rec].astype(np.uint64)
+    order = np.argsort(keys, kind="stable")
+    vals = rec[order].astype(np.uint32)
+    st = np.sort(tiles) - tile_base
+    T = gx * gy
+    ranges = np.stack([np.searchsorted(st, np.arange(T), side="left"),
+                       np.searchsorted(st, np.arange(T), side="right")], axis=1).astype(np.int64)
+    return vals, ranges
+
+
 from . import mp as mp  # noqa: E402
 from . import mlp as mlp  # noqa: E402

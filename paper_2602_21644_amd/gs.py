@@ -486,6 +486,30 @@ class Pipeline:
         self.ws_bwd = torch.zeros(gs_workspace_size(ctx, views.s, GS_OP_RENDER_BWD), dtype=torch.uint8, device=dev)
         self.ws_loss = torch.zeros(gs_workspace_size(ctx, views.s, GS_OP_LOSS), dtype=torch.uint8, device=dev)
         self.lp = LossParams(0.9, 0.1, 1e-6, 0, 0)
+        # sticky copies of the overflow and incomplete flags, kept across
+        # iterations when `sticky` is set (the library resets its own flags
+        # in every gs_bin_sort)
+        self.sticky = False
+        self.flags = torch.zeros(2, dtype=torch.int64, device=dev)
+
+    def _note_flags(self):
+        if self.sticky:
+            torch.maximum(self.flags, self.counters[1:3], out=self.flags)
+
+    def raise_if_failed(self, stream=None):
+        """Synchronises and raises GSError when an iteration since the last
+        clear_flags() overflowed the list capacity or ran out of a truncated
+        prefix list (its images, loss and gradients are then not exact)."""
+        over, n_inst, inc = gs_bins_check(self.ctx, self.bins, stream)
+        f = self.flags.cpu().tolist() if self.sticky else [0, 0]
+        if over or f[0]:
+            raise GSError(GS_E_CAPACITY, f"list capacity {self.capacity} exceeded ({n_inst} entries needed)")
+        if inc or f[1]:
+            raise GSError(GS_E_CAPACITY, f"a tile ran out of its prefix list (max_rank {self.bins.max_rank}): "
+                                         "re-bin with a larger rank or full lists")
+
+    def clear_flags(self):
+        self.flags.zero_()
 
     def set_loss_params(self, lambda_pho=0.9, lambda_depth=0.1, eps_A=1e-6, weight_mode=0, grad_through_weight=0):
         self.lp = LossParams(lambda_pho, lambda_depth, eps_A, weight_mode, grad_through_weight)
@@ -494,6 +518,7 @@ class Pipeline:
         gs_project(self.ctx, self.views.s, g, self.proj, stream)
         gs_bin_sort(self.ctx, self.views.s, g, self.proj, self.bins, self.ws_bin, stream)
         gs_render_fwd(self.ctx, self.views.s, g, self.proj, self.bins, self.bg, self.img, stream)
+        self._note_flags()
 
     def loss_and_grads(self, target_color, target_depth, stream=None):
         self._tgt_keep = (target_color, target_depth)
@@ -509,6 +534,7 @@ class Pipeline:
         gs_bin_sort(self.ctx, self.views.s, g, self.proj, self.bins, self.ws_bin, stream)
         gs_render_fwd_loss(self.ctx, self.views.s, g, self.proj, self.bins, self.bg, self.img, tgt, self.lp,
                            self.loss, self.pg, self.ws_loss, stream)
+        self._note_flags()
 
     def backward(self, g: Gaussians, grads: Grads, stream=None):
         gs_render_bwd(self.ctx, self.views.s, g, self.proj, self.bins, self.img, self.pg, self.bg, grads,

@@ -46,14 +46,22 @@ class RenderLoss(torch.autograd.Function):
     `pipe` is a gs.Pipeline over the views; `pose` a [V, 6] zero tensor that
     stands for the left twist (rho, phi) of every view at its current pose
     (its gradient is the pose gradient). MP is a state, not a parameter: it
-    gets no gradient."""
+    gets no gradient.
+
+    A forward whose lists overflowed their capacity, or whose tiles ran out of
+    a truncated prefix list, is not exact: outside graph capture the forward
+    synchronises and raises GSError then; under capture the pipeline's sticky
+    flags record it and pipe.raise_if_failed() raises after the replays."""
 
     @staticmethod
     def forward(ctx, pipe, mp, target_color, target_depth, mean, log_scale, quat, opacity_logit, color, pose):
         g = dict(mean=mean.contiguous(), log_scale=log_scale.contiguous(), quat=quat.contiguous(),
                  opacity_logit=opacity_logit.contiguous(), color=color.contiguous(), mp=mp.contiguous())
         gst = gs.gaussians_struct(g)
+        pipe.sticky = True
         pipe.forward_loss(gst, target_color.contiguous(), target_depth.contiguous())
+        if not torch.cuda.is_current_stream_capturing():
+            pipe.raise_if_failed()
         ctx.pipe, ctx.gst, ctx.keep = pipe, gst, g
         ctx.n = int(opacity_logit.shape[0])
         return pipe.loss.clone()
@@ -208,12 +216,15 @@ class Tracker:
 def map_gaussians(ctx, gaussians, cams, target_color, target_depth, iters=50, lrs=None, max_rank=0,
                   view_scene=None, scene_begin=None):
     """Adam steps on the Gaussian parameters (in place) against a batch of
-    views at fixed poses; returns the per-iteration total loss (host)."""
+    views at fixed poses; returns the per-iteration total loss (host). Raises
+    GSError when any iteration overflowed the list capacity or ran out of a
+    truncated prefix list (max_rank > 0)."""
     lrs = lrs or dict(mean=1e-4, log_scale=5e-3, quat=1e-3, opacity_logit=2e-2, color=5e-3)
     n = int(gaussians["opacity_logit"].shape[0])
     views = gs.ViewBatch(cams, n, view_scene=view_scene, scene_begin=scene_begin)
     gst = gs.gaussians_struct(gaussians)
     pipe = gs.Pipeline(ctx, views, capacity=max(1 << 20, 64 * n * len(cams)), max_rank=max_rank)
+    pipe.sticky = True
     grads = gs.alloc_grads(n)
     pose = torch.zeros(6 * len(cams), dtype=torch.float32, device=gaussians["mean"].device)
     grs = gs.grads_struct(grads, pose)
@@ -224,7 +235,5 @@ def map_gaussians(ctx, gaussians, cams, target_color, target_depth, iters=50, lr
         losses[it] = pipe.loss.sum()
         pipe.backward(gst, grs)
         adam.step([grads[k] for k in PARAMS])
-    over, _, _ = pipe.check()
-    if over:
-        raise RuntimeError("binning capacity exceeded during mapping")
+    pipe.raise_if_failed()
     return losses.cpu().numpy().astype(np.float64)

@@ -168,3 +168,43 @@ def test_mapping_reduces_loss(ctx):
     losses = optim.map_gaussians(ctx, gpd, cams, tcol, tdep, iters=60)
     print("mapping loss", losses[0], "->", losses[-1])
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_truncated_prefix_and_overflow_raise(ctx):
+    """A forward whose tiles run out of a truncated prefix list, or whose
+    lists overflow their capacity, raises instead of returning a silently
+    wrong loss and gradients: RenderLoss at once, map_gaussians after its
+    iterations, and a pipeline's sticky flags after graph replays."""
+    g, cam, tcam = _scene(seed=9, n=30000, W=320, H=240)
+    gd = gs.to_device(g)
+    tc, td = _render_target(ctx, gd, tcam)
+    views = gs.ViewBatch([cam], synth.n_gaussians(g))
+    params = {k: gd[k].clone().requires_grad_(True) for k in optim.PARAMS}
+    pose = torch.zeros(1, 6, device="cuda", requires_grad=True)
+    args = (gd["mp"], tc.reshape(-1).contiguous(), td, *[params[k] for k in optim.PARAMS], pose)
+    short = gs.Pipeline(ctx, views, capacity=1 << 22, max_rank=64)  # far too few records to saturate
+    with pytest.raises(gs.GSError, match="prefix"):
+        optim.RenderLoss.apply(short, *args)
+    small = gs.Pipeline(ctx, views, capacity=1000)
+    with pytest.raises(gs.GSError, match="capacity"):
+        optim.RenderLoss.apply(small, *args)
+    exact = gs.Pipeline(ctx, views, capacity=1 << 22)
+    loss = optim.RenderLoss.apply(exact, *args)
+    assert float(loss[0]) > 0
+    with pytest.raises(gs.GSError, match="prefix"):
+        optim.map_gaussians(ctx, {k: v.clone() for k, v in gd.items()}, [cam], tc.reshape(-1).contiguous(), td,
+                            iters=3, max_rank=64)
+    # sticky flags: an incomplete iteration followed by exact ones still raises
+    short.sticky = True
+    short.clear_flags()
+    gst = gs.gaussians_struct(gd)
+    short.forward_loss(gst, tc.reshape(-1).contiguous(), td)
+    short.bins.max_rank = 0  # full lists from here on
+    for _ in range(2):
+        short.forward_loss(gst, tc.reshape(-1).contiguous(), td)
+    over, n_inst, inc = short.check()
+    assert not over and inc == 0
+    with pytest.raises(gs.GSError, match="prefix"):
+        short.raise_if_failed()
+    short.clear_flags()
+    short.raise_if_failed()

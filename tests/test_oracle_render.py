@@ -333,3 +333,15 @@ def test_depth_key_is_float32_camera_z(orc):
     k = pr["kept"]
     np.testing.assert_array_equal(pr["zkey"][k], z32[k].astype(np.float64))
     np.testing.assert_allclose(pr["zkey"][k], pr["depth"][k], rtol=2e-7)
+
+
+def test_bin_reference_np_matches_textbook(orc):
+    """The array form of the binning reference equals the record-by-record
+    stable sort, including ties of equal depth keys and empty records."""
+    for seed, m, W, H in ((3, 400, 64, 48), (4, 3000, 200, 150), (5, 1, 64, 48)):
+        rect, key = synth.bin_inputs(seed, m, W, H)
+        grid = ((W + 15) // 16, (H + 15) // 16)
+        a_ids, a_r = orc.bin_reference(rect, key, grid)
+        b_ids, b_r = orc.bin_reference_np(rect, key, grid)
+        np.testing.assert_array_equal(a_ids, b_ids)
+        np.testing.assert_array_equal(a_r, b_r)
