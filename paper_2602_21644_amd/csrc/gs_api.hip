@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 
 #include "gs_internal.h"
 
@@ -16,6 +17,15 @@ gs_status gs_fail(gs_ctx* ctx, gs_status s, const char* fmt, ...) {
     va_end(ap);
   }
   return s;
+}
+
+void gs_note_timer(gs_ctx* ctx, const char* name, hipEvent_t a, hipEvent_t b) {
+  try {
+    ctx->pending.push_back(GsTimer{name, a, b});
+  } catch (...) {
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+  }
 }
 
 gs_status gs_check_launch(gs_ctx* ctx, const char* what) {
@@ -39,7 +49,9 @@ const char* gs_status_str(gs_status s) {
 
 gs_status gs_ctx_create(int device, gs_ctx** out) {
   if (!out) return GS_E_ARG;
-  gs_ctx* c = new gs_ctx;
+  *out = nullptr;
+  gs_ctx* c = new (std::nothrow) gs_ctx;
+  if (!c) return GS_E_HIP;
   c->device = device;
   c->render_batch = 128;
   c->bwd_batch = 64;
@@ -75,7 +87,10 @@ gs_status gs_ctx_kernel_times(gs_ctx* ctx, char* buf, size_t len) {
     long n;
     double ms;
   };
-  std::vector<Acc> acc;
+  // at most one row per kernel name: a fixed table, no allocation
+  constexpr size_t kMaxNames = 64;
+  Acc acc_tab[kMaxNames];
+  size_t n_acc = 0;
   gs_status st = GS_OK;
   for (auto& t : ctx->pending) {
     float ms = 0.f;
@@ -84,15 +99,19 @@ gs_status gs_ctx_kernel_times(gs_ctx* ctx, char* buf, size_t len) {
     hipEventDestroy(t.a);
     hipEventDestroy(t.b);
     size_t i = 0;
-    while (i < acc.size() && strcmp(acc[i].name, t.name) != 0) ++i;
-    if (i == acc.size()) acc.push_back(Acc{t.name, 0, 0.0});
-    acc[i].n += 1;
-    acc[i].ms += ms;
+    while (i < n_acc && strcmp(acc_tab[i].name, t.name) != 0) ++i;
+    if (i == n_acc) {
+      if (n_acc == kMaxNames) continue;
+      acc_tab[n_acc++] = Acc{t.name, 0, 0.0};
+    }
+    acc_tab[i].n += 1;
+    acc_tab[i].ms += ms;
   }
   ctx->pending.clear();
   size_t o = 0;
   buf[0] = 0;
-  for (auto& a : acc) {
+  for (size_t i = 0; i < n_acc; ++i) {
+    const Acc& a = acc_tab[i];
     const int w = snprintf(buf + o, len - o, "%s %ld %.6f\n", a.name, a.n, a.ms);
     if (w < 0 || (size_t)w >= len - o) break;
     o += (size_t)w;

@@ -216,18 +216,22 @@ struct gs_ctx {
 #define GS_LAUNCH(ctx, kern, grid, block, shm, strm, ...)                   \
   do {                                                                      \
     hipEvent_t e0_ = nullptr, e1_ = nullptr;                                \
-    const bool t_ = (ctx) && (ctx)->timing;                                 \
+    const bool t_ = (ctx) && (ctx)->timing;                         \
     if (t_) {                                                               \
-      (void)hipEventCreate(&e0_);                                                 \
-      (void)hipEventCreate(&e1_);                                                 \
-      (void)hipEventRecord(e0_, strm);                                            \
+      (void)hipEventCreate(&e0_);                                           \
+      (void)hipEventCreate(&e1_);                                           \
+      (void)hipEventRecord(e0_, strm);                                      \
     }                                                                       \
     hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);          \
     if (t_) {                                                               \
-      (void)hipEventRecord(e1_, strm);                                            \
-      (ctx)->pending.push_back(GsTimer{#kern, e0_, e1_});                   \
+      (void)hipEventRecord(e1_, strm);                                      \
+      gs_note_timer(ctx, #kern, e0_, e1_);                                  \
     }                                                                       \
   } while (0)
+
+// Keeps a timed launch's events for gs_ctx_kernel_times (drops them if the
+// record cannot grow: no exception leaves the library).
+void gs_note_timer(gs_ctx* ctx, const char* name, hipEvent_t a, hipEvent_t b);
 
 gs_status gs_fail(gs_ctx* ctx, gs_status s, const char* fmt, ...);
 gs_status gs_check_launch(gs_ctx* ctx, const char* what);
