@@ -289,6 +289,22 @@ gs_status gs_render_fwd_loss(gs_ctx* ctx, const gs_views* views, const gs_gaussi
                              const gs_loss_params* params /*[host]*/, float* loss, gs_pixel_grads* pg, void* ws,
                              size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): gs_render_fwd_loss
+ * without a workspace argument, with the same results. Its per-tile float64
+ * loss partials live in a static device array of 256 KiB (32768 tiles) that
+ * each GPU the library runs on holds until the process ends; a batch with
+ * more tiles returns GS_E_UNSUPPORTED before anything is enqueued. The
+ * array's device address is resolved on the first call made with a device
+ * current. The call allocates nothing (no hipMalloc, no host allocation; the
+ * "timing" knob is ignored inside it). Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller. */
+gs_status gs_render_fwd_loss_static(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                                    const gs_bins* bins, const float* bg, gs_image* img, const gs_target* tgt,
+                                    const gs_loss_params* params /*[host]*/, float* loss, gs_pixel_grads* pg,
+                                    void* stream);
+
 /* Adjoint of render + projection for the objective sum_v L_v, to all Gaussian
  * parameters and one pose twist per view (Sec. IV-D: Gaussians and poses are
  * optimised jointly). Transmittance is recomputed back from T_final. `ws` of

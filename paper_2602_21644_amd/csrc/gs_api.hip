@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "gs_internal.h"
@@ -64,6 +65,7 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->n_cu = 0;
   c->proj_resident = 0;
   c->lds_limit = 0;
+  c->no_alloc = 0;
   c->err[0] = 0;
   *out = c;
   return GS_OK;
@@ -391,6 +393,72 @@ gs_status gs_render_fwd_loss(gs_ctx* ctx, const gs_views* views, const gs_gaussi
   for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
   const LossArgs la = loss_args(tgt, lp, pg, (double*)ws, loss);
   return launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, (hipStream_t)stream, &la);
+}
+
+}  // extern "C"
+
+// Scratch of the allocation-free forward + loss: one float64 loss partial per
+// tile. Every call overwrites the partial of each tile of its batch before
+// the per-view sums read them, so nothing needs clearing between calls.
+static constexpr int64_t kStaticLossTiles = 32768;  // 256 KiB
+static __device__ __align__(256) double scratch[kStaticLossTiles];
+
+// Device address of `scratch` on each device, resolved on the first call
+// made with that device current (hipGetSymbolAddress). The array's host-side
+// name is not a device address and is never handed to a kernel.
+static constexpr int kMaxDevices = 64;
+static double* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static gs_status static_scratch(gs_ctx* ctx, double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return gs_fail(ctx, GS_E_HIP, "no current device (or device index >= %d)", kMaxDevices);
+  try {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return gs_fail(ctx, GS_E_HIP, "resolving the static loss scratch on device %d: %s", dev,
+                       hipGetErrorString(e));
+      g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+  } catch (...) {
+    return gs_fail(ctx, GS_E_HIP, "locking the static scratch table failed");
+  }
+  return GS_OK;
+}
+
+extern "C" {
+
+gs_status gs_render_fwd_loss_static(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
+                                    const gs_bins* bins, const float* bg, gs_image* img, const gs_target* tgt,
+                                    const gs_loss_params* lp, float* loss, gs_pixel_grads* pg, void* stream) {
+  if (!ctx || !g || !proj || !bins || !bg || !img || !tgt || !lp || !loss || !pg)
+    return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!img->color || !img->depth || !img->mp || !img->T || !img->n_last) return gs_fail(ctx, GS_E_ARG, "image NULL");
+  if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
+  if (!tgt->color || !tgt->depth) return gs_fail(ctx, GS_E_ARG, "target NULL");
+  if (!pg->dcolor || !pg->ddepth) return gs_fail(ctx, GS_E_ARG, "pixel grads NULL");
+  if (lp->weight_mode != 0 && lp->weight_mode != 1) return gs_fail(ctx, GS_E_ARG, "weight_mode 0|1");
+  if (tab.ntiles > kStaticLossTiles)
+    return gs_fail(ctx, GS_E_UNSUPPORTED, "the batch has %lld tiles; gs_render_fwd_loss_static holds at most %lld",
+                   (long long)tab.ntiles, (long long)kStaticLossTiles);
+  double* part = nullptr;
+  GS_TRY(static_scratch(ctx, &part));
+  BinTab bt;
+  bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
+  int bits = 0;
+  for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
+  const LossArgs la = loss_args(tgt, lp, pg, part, loss);
+  ctx->no_alloc = 1;
+  const gs_status st = launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, (hipStream_t)stream, &la);
+  ctx->no_alloc = 0;
+  return st;
 }
 
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,

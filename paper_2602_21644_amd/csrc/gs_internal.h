@@ -207,6 +207,7 @@ struct gs_ctx {
   int n_cu;                      // compute units of the device (0: not queried yet)
   int proj_resident;             // bwd_project blocks the device holds at once (0: not queried yet)
   size_t lds_limit;              // LDS per workgroup usable by the binning scatter (0: not queried)
+  int no_alloc;                  // 1 inside an allocation-free call: launches are not timed
   std::vector<GsTimer> pending;  // launches whose events are not read yet
   char err[512];
 };
@@ -216,7 +217,7 @@ struct gs_ctx {
 #define GS_LAUNCH(ctx, kern, grid, block, shm, strm, ...)                   \
   do {                                                                      \
     hipEvent_t e0_ = nullptr, e1_ = nullptr;                                \
-    const bool t_ = (ctx) && (ctx)->timing;                         \
+    const bool t_ = (ctx) && (ctx)->timing && !(ctx)->no_alloc;             \
     if (t_) {                                                               \
       (void)hipEventCreate(&e0_);                                           \
       (void)hipEventCreate(&e1_);                                           \

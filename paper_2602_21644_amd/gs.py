@@ -152,6 +152,9 @@ def lib():
             "gs_render_fwd_loss": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins),
                                     POINTER(c_float), POINTER(Image), POINTER(Target), POINTER(LossParams), P,
                                     POINTER(PixelGrads), P, c_size_t, P], c_int32),
+            "gs_render_fwd_loss_static": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins),
+                                           POINTER(c_float), POINTER(Image), POINTER(Target), POINTER(LossParams), P,
+                                           POINTER(PixelGrads), P], c_int32),
             "gs_render_bwd": ([P, POINTER(Views), POINTER(Gaussians), POINTER(Proj), POINTER(Bins), POINTER(Image),
                                POINTER(PixelGrads), POINTER(c_float), POINTER(Grads), P, c_size_t, P], c_int32),
             "gs_bins_check": ([P, POINTER(Bins), POINTER(c_int64), POINTER(c_int32), P], c_int32),
@@ -177,6 +180,7 @@ def lib():
 EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error", "gs_ctx_set_param",
             "gs_ctx_get_param", "gs_ctx_kernel_times", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_fwd_loss",
+            "gs_render_fwd_loss_static",
             "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
             "gs_adam_step", "gs_pose_update")
 
@@ -259,6 +263,14 @@ def gs_render_fwd_loss(ctx, views, g, proj, bins, bg, img, tgt, params, loss, pg
                                        ctypes.byref(bins), bgv, ctypes.byref(img), ctypes.byref(tgt),
                                        ctypes.byref(params), ptr(loss), ctypes.byref(pg), ptr(ws),
                                        ws.numel() * ws.element_size(), _stream(stream)), "gs_render_fwd_loss")
+
+
+def gs_render_fwd_loss_static(ctx, views, g, proj, bins, bg, img, tgt, params, loss, pg, stream=None):
+    bgv = (c_float * 3)(*[float(x) for x in bg])
+    ctx.check(lib().gs_render_fwd_loss_static(ctx.h, ctypes.byref(views), ctypes.byref(g), ctypes.byref(proj),
+                                              ctypes.byref(bins), bgv, ctypes.byref(img), ctypes.byref(tgt),
+                                              ctypes.byref(params), ptr(loss), ctypes.byref(pg), _stream(stream)),
+              "gs_render_fwd_loss_static")
 
 
 def gs_render_bwd(ctx, views, g, proj, bins, img, pg, bg, grads, ws, stream=None):

@@ -112,3 +112,31 @@ def test_structs_keep_their_tensors_alive():
     del s, gst
     gc.collect()
     assert all(r() is None for r in refs + grefs)
+
+
+def test_static_forward_loss_rejects_large_batches_on_the_host():
+    """The allocation-free forward + loss holds 32768 tiles; a batch with more
+    (28 views of 640x480 = 33600 tiles) is refused before any device call,
+    so this runs without a GPU."""
+    from paper_2602_21644_amd import gs, synth
+    L = gs.lib()
+    V = 28
+    host = (gs.Camera * V)(*[gs.camera_struct(synth.camera(640, 480)) for _ in range(V)])
+    v = gs.Views()
+    v.n_views, v.n_scenes, v.n_gaussians = V, 1, 10
+    v.cams_host = ctypes.cast(host, ctypes.POINTER(gs.Camera))
+    v.cams_dev = ctypes.c_void_p(1)
+    ctx = gs.Context(0)
+    P = ctypes.c_void_p(16)  # never dereferenced: the call stops at the size check
+    g = gs.Gaussians(10, P, P, P, P, P, P)
+    proj, bins = gs.Proj(), gs.Bins()
+    img = gs.Image(P, P, P, P, P, None)
+    tgt = gs.Target(P, P)
+    pg = gs.PixelGrads(P, P, None, None)
+    lp = gs.LossParams(0.9, 0.1, 1e-6, 0, 0)
+    bg = (ctypes.c_float * 3)(0, 0, 0)
+    st = L.gs_render_fwd_loss_static(ctx.h, ctypes.byref(v), ctypes.byref(g), ctypes.byref(proj),
+                                     ctypes.byref(bins), bg, ctypes.byref(img), ctypes.byref(tgt), ctypes.byref(lp),
+                                     P, ctypes.byref(pg), None)
+    assert st == gs.GS_E_UNSUPPORTED
+    assert b"32768" in L.gs_last_error(ctx.h)
