@@ -236,9 +236,11 @@ int64_t gs_rec_count(const gs_views* views);
 int64_t gs_tile_count(const gs_views* views);
 int64_t gs_pixel_count(const gs_views* views);
 
-enum { GS_OP_BIN_SORT = 1, GS_OP_RENDER_BWD = 2, GS_OP_LOSS = 3, GS_OP_MP_UPDATE = 4, GS_OP_MLP_TRAIN = 5 };
+enum { GS_OP_BIN_SORT = 1, GS_OP_RENDER_BWD = 2, GS_OP_LOSS = 3, GS_OP_MP_UPDATE = 4, GS_OP_MLP_TRAIN = 5,
+       GS_OP_COMPACT = 6 };
 /* Scratch bytes needed by `op` for this batch; `capacity` is the list capacity
- * of gs_bins (used by GS_OP_BIN_SORT only). For GS_OP_RENDER_BWD the size
+ * of gs_bins (used by GS_OP_BIN_SORT only), or for GS_OP_COMPACT the number of
+ * elements n (views may then be NULL). For GS_OP_RENDER_BWD the size
  * grows with the context's "bwd_copies" (query it after setting the knob); the
  * scratch must be zero-filled before its first use (see gs_render_bwd). */
 gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes);
@@ -371,6 +373,28 @@ typedef struct gs_mp_out {
 gs_status gs_mp_update(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, const gs_image* img,
                        const gs_target* tgt, const gs_mp_frame* frame, const gs_mp_params* params /*[host]*/,
                        float* mp, gs_mp_out* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- pruning
+ * The mapping window prunes Gaussians whose MP after gs_mp_update exceeds a
+ * threshold (the config-3 option `prune_above` flags them; not in the paper,
+ * which suppresses and later recovers dynamic Gaussians, Sec. IV-C), and the
+ * map is then compacted. gs_compact removes the elements with drop[i] != 0
+ * from n_planes float planes of length n at once, keeping the order of the
+ * rest: dst[p][j] = src[p][i_j] for the kept indices i_0 < i_1 < ... . The
+ * planes are given as [host] arrays of device pointers (the Gaussian
+ * parameters, the MP state, optimiser moments: any per-Gaussian float plane);
+ * src and dst must not overlap. *n_out (device) gets the number kept. With
+ * seg_out set, seg_begin [host] holds the n_seg + 1 offsets of contiguous
+ * scenes (0 = seg_begin[0] <= ... <= seg_begin[n_seg] = n) and seg_out
+ * (device) gets their new offsets (the kept elements in front of each).
+ * Limits: n_planes <= GS_COMPACT_MAX_PLANES, n_seg <= GS_COMPACT_MAX_SEGS
+ * (GS_E_UNSUPPORTED beyond). ws of gs_workspace_size(GS_OP_COMPACT, n). */
+#define GS_COMPACT_MAX_PLANES 64
+#define GS_COMPACT_MAX_SEGS 32
+gs_status gs_compact(gs_ctx* ctx, const uint8_t* drop, int64_t n, int32_t n_planes,
+                     const float* const* src /*[host] n_planes*/, float* const* dst /*[host] n_planes*/,
+                     const int64_t* seg_begin /*[host] n_seg + 1, nullable*/, int32_t n_seg, int64_t* seg_out,
+                     int64_t* n_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- learned MP surrogate
  * Not in the paper: a per-pixel MLP 8 -> 32 -> 32 -> 1 (ReLU, sigmoid) that

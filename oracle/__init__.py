@@ -314,5 +314,18 @@ def bin_reference_np(rect, key, tile_grid, tile_base=0):
     return vals, ranges
 
 
+def compact(planes, drop, seg_begin=None):
+    """Removal of the Gaussians flagged in `drop` (the prune of the mapping
+    window, MP above its threshold): every plane keeps its remaining elements
+    in their order. Returns (planes, new segment offsets) where segments are
+    the contiguous scenes given by seg_begin (S + 1 offsets)."""
+    keep = ~np.asarray(drop, bool)
+    out = [np.asarray(p)[..., keep] for p in planes]
+    if seg_begin is None:
+        seg_begin = [0, keep.size]
+    before = np.concatenate([[0], np.cumsum(keep)])
+    return out, before[np.asarray(seg_begin, np.int64)]
+
+
 from . import mp as mp  # noqa: E402
 from . import mlp as mlp  # noqa: E402

@@ -282,6 +282,11 @@ static size_t loss_ws_bytes(const ViewTab& tab) {
 
 gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes) {
   if (!ctx || !bytes) return GS_E_ARG;
+  if (op == GS_OP_COMPACT) {
+    if (capacity < 0) return gs_fail(ctx, GS_E_ARG, "n < 0");
+    *bytes = compact_ws_bytes(capacity);
+    return GS_OK;
+  }
   ViewTab tab;
   GS_TRY(make_tab(ctx, views, tab));
   switch (op) {
@@ -512,6 +517,34 @@ gs_status gs_mp_update(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, 
   const size_t need = mp_ws_bytes(tab, tab.npix);
   if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "mp_update workspace %zu < %zu", ws_bytes, need);
   return launch_mp_update(ctx, tab, proj, img, tgt, fr, mp_params, mp, out, (char*)ws, (hipStream_t)stream);
+}
+
+gs_status gs_compact(gs_ctx* ctx, const uint8_t* drop, int64_t n, int32_t n_planes, const float* const* src,
+                     float* const* dst, const int64_t* seg_begin, int32_t n_seg, int64_t* seg_out, int64_t* n_out,
+                     void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !n_out || n < 0 || n_planes < 0) return gs_fail(ctx, GS_E_ARG, "bad argument");
+  if (n > 0 && !drop) return gs_fail(ctx, GS_E_ARG, "drop is NULL");
+  if (n_planes > GS_COMPACT_MAX_PLANES)
+    return gs_fail(ctx, GS_E_UNSUPPORTED, "at most %d planes per call", GS_COMPACT_MAX_PLANES);
+  if (n_planes > 0 && (!src || !dst)) return gs_fail(ctx, GS_E_ARG, "plane tables are NULL");
+  for (int p = 0; p < n_planes; ++p) {
+    if (n > 0 && (!src[p] || !dst[p])) return gs_fail(ctx, GS_E_ARG, "plane %d is NULL", p);
+    if (n > 0 && (const char*)src[p] < (const char*)(dst[p] + n) && (const char*)dst[p] < (const char*)(src[p] + n))
+      return gs_fail(ctx, GS_E_ARG, "plane %d: source and destination overlap", p);
+  }
+  if (seg_out) {
+    if (n_seg < 1 || n_seg > GS_COMPACT_MAX_SEGS)
+      return n_seg < 1 ? gs_fail(ctx, GS_E_ARG, "n_seg must be >= 1")
+                       : gs_fail(ctx, GS_E_UNSUPPORTED, "at most %d segments", GS_COMPACT_MAX_SEGS);
+    if (!seg_begin || seg_begin[0] != 0 || seg_begin[n_seg] != n)
+      return gs_fail(ctx, GS_E_ARG, "seg_begin must run from 0 to n");
+    for (int i = 0; i < n_seg; ++i)
+      if (seg_begin[i + 1] < seg_begin[i]) return gs_fail(ctx, GS_E_ARG, "seg_begin not monotone");
+  }
+  const size_t need = compact_ws_bytes(n);
+  if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "compact workspace %zu < %zu", ws_bytes, need);
+  return launch_compact(ctx, drop, n, n_planes, src, dst, seg_begin, n_seg, seg_out, n_out, (char*)ws,
+                        (hipStream_t)stream);
 }
 
 gs_status gs_mlp_features(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,

@@ -269,6 +269,10 @@ gs_status launch_bin_prefix(gs_ctx*, const ViewTab&, const gs_camera*, const gs_
 size_t mp_ws_bytes(const ViewTab&, int64_t npix);
 gs_status launch_mp_update(gs_ctx*, const ViewTab&, const gs_proj*, const gs_image*, const gs_target*,
                            const gs_mp_frame*, const gs_mp_params*, float*, gs_mp_out*, char*, hipStream_t);
+size_t compact_ws_bytes(int64_t n);
+gs_status launch_compact(gs_ctx*, const uint8_t* drop, int64_t n, int32_t n_planes, const float* const* src,
+                         float* const* dst, const int64_t* seg_begin, int32_t n_seg, int64_t* seg_out,
+                         int64_t* n_out, char* ws, hipStream_t);
 size_t mlp_ws_bytes(int64_t P);
 gs_status launch_mlp_features(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_mp_frame*, float*,
                               hipStream_t);

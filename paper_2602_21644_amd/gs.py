@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libgs.so")
 _lib = None
 
 GS_OK, GS_E_ARG, GS_E_CAPACITY, GS_E_HIP, GS_E_UNSUPPORTED = 0, 1, 2, 3, 4
-GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_LOSS, GS_OP_MP_UPDATE, GS_OP_MLP_TRAIN = 1, 2, 3, 4, 5
+GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_LOSS, GS_OP_MP_UPDATE, GS_OP_MLP_TRAIN, GS_OP_COMPACT = 1, 2, 3, 4, 5, 6
+GS_COMPACT_MAX_PLANES, GS_COMPACT_MAX_SEGS = 64, 32
 GS_MAX_VIEWS = 32
 GS_MLP_PARAMS = 1377
 GS_MLP_WEIGHTS = 1312
@@ -160,6 +161,8 @@ def lib():
             "gs_bins_check": ([P, POINTER(Bins), POINTER(c_int64), POINTER(c_int32), P], c_int32),
             "gs_mp_update": ([P, POINTER(Views), POINTER(Proj), POINTER(Image), POINTER(Target), POINTER(MPFrame),
                               POINTER(MPParams), P, POINTER(MPOut), P, c_size_t, P], c_int32),
+            "gs_compact": ([P, P, c_int64, c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int64), c_int32,
+                            P, P, P, c_size_t, P], c_int32),
             "gs_mlp_features": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(MPFrame), P, P],
                                 c_int32),
             "gs_mlp_sync": ([P, POINTER(MLP), P], c_int32),
@@ -181,7 +184,7 @@ EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error",
             "gs_ctx_get_param", "gs_ctx_kernel_times", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_fwd_loss",
             "gs_render_fwd_loss_static",
-            "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
+            "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_compact", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
             "gs_adam_step", "gs_pose_update")
 
 
@@ -298,9 +301,32 @@ def gs_bins_check(ctx, bins, stream=None):
 
 def gs_workspace_size(ctx, views, op, capacity=0):
     b = c_size_t()
-    ctx.check(lib().gs_workspace_size(ctx.h, ctypes.byref(views), op, int(capacity), ctypes.byref(b)),
+    ctx.check(lib().gs_workspace_size(ctx.h, ctypes.byref(views) if views is not None else None, op, int(capacity),
+                                      ctypes.byref(b)),
               "gs_workspace_size")
     return int(b.value)
+
+
+def gs_compact(ctx, drop, src, dst, n_out, ws, seg_begin=None, seg_out=None, stream=None):
+    """Removes the elements with drop != 0 from every plane of `src` (a list of
+    1-D float32 device tensors of one length n) into the planes of `dst`,
+    keeping their order; n_out (int64 device tensor [1]) gets the count, and
+    with seg_begin (S + 1 host offsets) seg_out (int64 device [S + 1]) the new
+    scene offsets."""
+    n = int(drop.numel())
+    k = len(src)
+    sa = (c_void_p * max(k, 1))(*[c_void_p(t.data_ptr()) for t in src])
+    da = (c_void_p * max(k, 1))(*[c_void_p(t.data_ptr()) for t in dst])
+    for t in list(src) + list(dst):
+        if t.dtype != torch.float32 or t.numel() < n or not t.is_contiguous():
+            raise GSError(GS_E_ARG, "gs_compact planes must be contiguous float32 of length >= n")
+    if seg_begin is not None:
+        S = len(seg_begin) - 1
+        sb = (c_int64 * (S + 1))(*[int(x) for x in seg_begin])
+    else:
+        S, sb = 0, None
+    ctx.check(lib().gs_compact(ctx.h, ptr(drop), n, k, sa, da, sb, S, ptr(seg_out), ptr(n_out), ptr(ws),
+                               ws.numel() * ws.element_size(), _stream(stream)), "gs_compact")
 
 
 def gs_mlp_features(ctx, views, img, tgt, frame, x, stream=None):

@@ -237,3 +237,125 @@ def map_gaussians(ctx, gaussians, cams, target_color, target_depth, iters=50, lr
         adam.step([grads[k] for k in PARAMS])
     pipe.raise_if_failed()
     return losses.cpu().numpy().astype(np.float64)
+
+
+class MappingWindow:
+    """The mapping window of one scene: V keyframes rendered and
+    back-propagated together (one call sequence over the view batch), Adam on
+    every Gaussian parameter; once per frame the MP update of the newest
+    keyframe (gs_mp_update, log-odds mode by default) whose prune flag
+    (MP > prune_above) drops Gaussians from the map: gs_compact moves the
+    parameters, the MP state and the Adam moments of the kept ones into the
+    second set of buffers. Both iterate() and frame_end() only enqueue work,
+    so a caller can capture them in one HIP graph; commit() then reads the
+    kept count (synchronising) and swaps the buffers, after which the
+    pipelines are rebuilt for the smaller map (and a graph must be captured
+    again).
+
+    Sec. IV-D (joint optimisation over keyframes), Sec. IV-A Eq. (1)-(13) and
+    Sec. IV-B Eq. (17) (the MP update); the prune and the log-odds form are
+    this library's options, not the paper's (which suppresses dynamic
+    Gaussians and recovers them later)."""
+
+    PLANES = (("mean", 3), ("log_scale", 3), ("quat", 4), ("opacity_logit", 1), ("color", 3), ("mp", 1))
+
+    def __init__(self, ctx, gaussians, cams, max_rank=-1, capacity=None, lrs=None, mp_params=None):
+        """max_rank < 0: the smallest exact prefix rank (choose_rank), chosen
+        again whenever the map changes; capacity then 1.5x its list entries."""
+        self.ctx = ctx
+        self.cams = list(cams)
+        self.lrs = lrs or dict(mean=1e-4, log_scale=5e-3, quat=1e-3, opacity_logit=2e-2, color=5e-3)
+        p = dict(gs.MP_DEFAULTS, mode=1, prune_above=0.8)
+        if mp_params:
+            p.update(mp_params)
+        self.mp_params = gs.MPParams(*[p[k] for k in gs.MP_PARAM_NAMES], int(p["mode"]), int(p["u_norm"]))
+        self.max_rank = max_rank
+        self.capacity = capacity
+        self._build(gaussians, None)
+
+    def _build(self, gaussians, adam_state):
+        ctx = self.ctx
+        self.g = gaussians
+        n = int(gaussians["opacity_logit"].shape[0])
+        self.n = n
+        dev = gaussians["mean"].device
+        self.gst = gs.gaussians_struct(gaussians)
+        self.views = gs.ViewBatch(self.cams, n)
+        if self.max_rank < 0:
+            self.rank, n_inst = choose_rank(ctx, self.views, self.gst, n)
+            cap = int(1.5 * n_inst) + (1 << 16)
+        else:
+            self.rank = self.max_rank
+            cap = self.capacity or max(1 << 20, 64 * n * len(self.cams))
+        self.pipe = gs.Pipeline(ctx, self.views, cap, max_rank=self.rank)
+        self.pipe.sticky = True
+        self.grads = gs.alloc_grads(n, device=dev)
+        self.pose = torch.zeros(6 * len(self.cams), dtype=torch.float32, device=dev)
+        self.grs = gs.grads_struct(self.grads, self.pose)
+        self.adam = Adam(ctx, [(gaussians[k], self.lrs[k]) for k in PARAMS])
+        if adam_state is not None:
+            for dst, src in zip(self.adam.m + self.adam.v, adam_state[0] + adam_state[1]):
+                dst.copy_(src)
+            self.adam.count.copy_(adam_state[2])
+        # the MP update of the newest keyframe needs its own projection with
+        # the planar means
+        self.mp_views = gs.ViewBatch([self.cams[-1]], n)
+        self.mp_pipe = gs.Pipeline(ctx, self.mp_views, max(1 << 20, 64 * n), full_proj=True)
+        self.mp_pipe.sticky = True
+        self.Ut = torch.zeros(n, device=dev)
+        self.alpha = torch.zeros(n, device=dev)
+        self.dyn = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.prune = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.stats = torch.zeros(8, device=dev)
+        self.mp_out = gs.MPOut(gs.ptr(self.Ut), gs.ptr(self.alpha), gs.ptr(self.dyn), gs.ptr(self.prune), None, None,
+                               gs.ptr(self.stats))
+        self.mp_ws = torch.zeros(gs.gs_workspace_size(ctx, self.mp_views.s, gs.GS_OP_MP_UPDATE), dtype=torch.uint8,
+                                 device=dev)
+        # compaction: every per-Gaussian plane (parameters, MP, Adam moments)
+        self.src_planes = self._planes(gaussians, self.adam)
+        self.dst = {k: torch.empty_like(v) for k, v in gaussians.items()}
+        self.dst_m = [torch.empty_like(t) for t in self.adam.m]
+        self.dst_v = [torch.empty_like(t) for t in self.adam.v]
+        self.dst_planes = self._planes(self.dst, None, self.dst_m, self.dst_v)
+        self.n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.cp_ws = torch.empty(gs.gs_workspace_size(ctx, None, gs.GS_OP_COMPACT, n), dtype=torch.uint8, device=dev)
+
+    def _planes(self, g, adam, m=None, v=None):
+        out = []
+        for k, c in self.PLANES:
+            out += [g[k].view(c, -1)[i] for i in range(c)] if c > 1 else [g[k].view(-1)]
+        for lst in ((adam.m if adam else m), (adam.v if adam else v)):
+            for t, (k, c) in zip(lst, self.PLANES[:-1]):
+                out += [t.view(c, -1)[i] for i in range(c)] if c > 1 else [t.view(-1)]
+        return out
+
+    def iterate(self, target_color, target_depth):
+        """One iteration over the window: render + loss + backward of every
+        keyframe, one Adam step on every Gaussian parameter."""
+        self.pipe.forward_loss(self.gst, target_color, target_depth)
+        self.pipe.backward(self.gst, self.grs)
+        self.adam.step([self.grads[k] for k in PARAMS])
+
+    def frame_end(self, target_color, target_depth, instance_id, prior, conf, seg_updated=True):
+        """The newest keyframe's MP update against its observed frame (colour,
+        depth, instance ids, prior and confidence tables), then the map
+        compacted by the prune flag into the second buffers."""
+        self.mp_pipe.forward(self.gst)
+        tgt = gs.Target(gs.ptr(target_color), gs.ptr(target_depth))
+        fr = gs.MPFrame(gs.ptr(instance_id), int(prior.numel()) - 1, gs.ptr(prior), gs.ptr(conf), int(seg_updated),
+                        None)
+        gs.gs_mp_update(self.ctx, self.mp_views.s, self.mp_pipe.proj, self.mp_pipe.img, tgt, fr, self.mp_params,
+                        self.g["mp"], self.mp_out, self.mp_ws)
+        gs.gs_compact(self.ctx, self.prune, self.src_planes, self.dst_planes, self.n_out, self.cp_ws)
+
+    def commit(self):
+        """Makes the compacted map current (synchronises); raises if any
+        iteration since the last commit was not exact. Returns the new count."""
+        self.pipe.raise_if_failed()
+        self.mp_pipe.raise_if_failed()
+        k = int(self.n_out.item())
+        g = {key: (t.view(-1, self.n)[:, :k] if t.dim() > 1 else t[:k]).contiguous() for key, t in self.dst.items()}
+        m = [(t.view(-1, self.n)[:, :k] if t.dim() > 1 else t[:k]).contiguous() for t in self.dst_m]
+        v = [(t.view(-1, self.n)[:, :k] if t.dim() > 1 else t[:k]).contiguous() for t in self.dst_v]
+        self._build(g, (m, v, self.adam.count.clone()))
+        return k

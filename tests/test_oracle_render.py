@@ -345,3 +345,19 @@ def test_bin_reference_np_matches_textbook(orc):
         b_ids, b_r = orc.bin_reference_np(rect, key, grid)
         np.testing.assert_array_equal(a_ids, b_ids)
         np.testing.assert_array_equal(a_r, b_r)
+
+
+def test_compact_reference(orc):
+    """Removal by a drop mask against a plain loop: kept elements in order,
+    each scene's new offset = the kept elements in front of it."""
+    rng = np.random.default_rng(4)
+    n = 257
+    drop = rng.random(n) < 0.4
+    a = rng.random((3, n))
+    b = np.arange(n, dtype=np.float32)
+    seg = [0, 100, 100, 257]
+    (ca, cb), off = orc.compact([a, b], drop, seg)
+    kept = [i for i in range(n) if not drop[i]]
+    np.testing.assert_array_equal(cb, np.array(kept, np.float32))
+    np.testing.assert_array_equal(ca, a[:, kept])
+    assert off.tolist() == [0, sum(1 for i in kept if i < 100), sum(1 for i in kept if i < 100), len(kept)]
