@@ -237,10 +237,11 @@ int64_t gs_tile_count(const gs_views* views);
 int64_t gs_pixel_count(const gs_views* views);
 
 enum { GS_OP_BIN_SORT = 1, GS_OP_RENDER_BWD = 2, GS_OP_LOSS = 3, GS_OP_MP_UPDATE = 4, GS_OP_MLP_TRAIN = 5,
-       GS_OP_COMPACT = 6 };
+       GS_OP_COMPACT = 6, GS_OP_MP_REG = 7, GS_OP_EDGE_WARP = 8 };
 /* Scratch bytes needed by `op` for this batch; `capacity` is the list capacity
- * of gs_bins (used by GS_OP_BIN_SORT only), or for GS_OP_COMPACT the number of
- * elements n (views may then be NULL). For GS_OP_RENDER_BWD the size
+ * of gs_bins (used by GS_OP_BIN_SORT only), for GS_OP_COMPACT and
+ * GS_OP_MP_REG the number of elements n (views may then be NULL), for
+ * GS_OP_EDGE_WARP the number of view pairs. For GS_OP_RENDER_BWD the size
  * grows with the context's "bwd_copies" (query it after setting the knob); the
  * scratch must be zero-filled before its first use (see gs_render_bwd). */
 gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes);
@@ -373,6 +374,51 @@ typedef struct gs_mp_out {
 gs_status gs_mp_update(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, const gs_image* img,
                        const gs_target* tgt, const gs_mp_frame* frame, const gs_mp_params* params /*[host]*/,
                        float* mp, gs_mp_out* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- the further terms of the objective
+ * With the photometric and depth terms of gs_loss they make the mapping
+ * objective L_G = l1 L_pho + l2 L_depth + l3 L_MP + l4 L_edge (Eq. (27);
+ * l3 = 500, l4 = 300 in Sec. V-A). */
+
+/* MP-based motion consistency, Eq. (23)-(24): lambda sum_k (1 - M_k)
+ * |mu_k - mu_hat_k|^2 with mu_hat_k = R mu_prev_k + t, [R | t] = T [host,
+ * row-major 3x4] the relative motion that carries the previous means into the
+ * current frame's coordinates (NULL: identity, for means kept in one world
+ * frame). Writes lambda L_MP to loss[0] (device, deterministic) and ADDS
+ * 2 lambda (1 - M_k)(mu_k - mu_hat_k) to dmean [3][n] (MP gets no gradient:
+ * it is a state). mean, mean_prev [3][n], mp [n]. ws of
+ * gs_workspace_size(GS_OP_MP_REG, n). */
+gs_status gs_mp_regularizer(gs_ctx* ctx, int64_t n, const float* mean, const float* mean_prev, const float* mp,
+                            const float* T /*[host] 12, nullable*/, float lambda, float* loss, float* dmean, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* MP-guided edge-warp term, Eq. (25)-(26), for pairs (i, j) of views of the
+ * batch (i, j < n_views, i != j): over the edge pixels u of frame i (Sobel
+ * slope |(S_x, S_y)| / 8 of the observed depth tgt->depth above edge_thresh,
+ * every pixel of the 3x3 neighbourhood observed), the observed depth lifts u
+ * into camera i, T_j T_i^-1 carries it into camera j and K_j projects it to
+ * u'; frame j's rendered depth img->depth and static weight w = 1 - M/(1 - T)
+ * (img->mp, img->T; 0 where 1 - T <= eps_A) are sampled bilinearly at u'
+ * (skipped unless the four neighbouring pixel centres are in the image and
+ * the camera-j depth exceeds z_near), and loss[k] (device) = lambda sum
+ * huber_delta(w (D_j(u') - D_i(u))) for pair k. The adjoint, with w held
+ * constant, is ADDED to ddepth [P] (frame j's pixels; the caller's depth
+ * adjoint, so gs_render_bwd carries it to the Gaussians and frame j's pose)
+ * and, through u', ADDED to dpose [V][6] (nullable) for both frames' left
+ * twists. ws of gs_workspace_size(GS_OP_EDGE_WARP, n_pairs). */
+typedef struct gs_edge_pair {
+  int32_t i, j;
+} gs_edge_pair;
+typedef struct gs_edge_params {
+  float lambda;      /* l4 (300 in Sec. V-A) */
+  float delta;       /* Huber threshold in metres */
+  float edge_thresh; /* Sobel slope threshold in metres per pixel */
+  float eps_A;       /* static weight 0 where 1 - T <= eps_A */
+} gs_edge_params;
+gs_status gs_edge_warp(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
+                       const gs_edge_pair* pairs /*[host] n_pairs*/, int32_t n_pairs,
+                       const gs_edge_params* params /*[host]*/, float* loss, float* ddepth, float* dpose, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- pruning
  * The mapping window prunes Gaussians whose MP after gs_mp_update exceeds a

@@ -282,9 +282,9 @@ static size_t loss_ws_bytes(const ViewTab& tab) {
 
 gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int64_t capacity, size_t* bytes) {
   if (!ctx || !bytes) return GS_E_ARG;
-  if (op == GS_OP_COMPACT) {
+  if (op == GS_OP_COMPACT || op == GS_OP_MP_REG) {
     if (capacity < 0) return gs_fail(ctx, GS_E_ARG, "n < 0");
-    *bytes = compact_ws_bytes(capacity);
+    *bytes = op == GS_OP_COMPACT ? compact_ws_bytes(capacity) : mp_reg_ws_bytes(capacity);
     return GS_OK;
   }
   ViewTab tab;
@@ -310,6 +310,10 @@ gs_status gs_workspace_size(gs_ctx* ctx, const gs_views* views, int32_t op, int6
       *bytes = mp_ws_bytes(tab, tab.npix);
       return GS_OK;
     case GS_OP_MLP_TRAIN: *bytes = mlp_ws_bytes(tab.npix); return GS_OK;
+    case GS_OP_EDGE_WARP:
+      if (capacity < 0 || capacity > GS_MAX_VIEWS) return gs_fail(ctx, GS_E_ARG, "n_pairs must be in [0, %d]", GS_MAX_VIEWS);
+      *bytes = edge_warp_ws_bytes(tab, (int32_t)capacity);
+      return GS_OK;
     default: return gs_fail(ctx, GS_E_ARG, "unknown op %d", op);
   }
 }
@@ -517,6 +521,36 @@ gs_status gs_mp_update(gs_ctx* ctx, const gs_views* views, const gs_proj* proj, 
   const size_t need = mp_ws_bytes(tab, tab.npix);
   if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "mp_update workspace %zu < %zu", ws_bytes, need);
   return launch_mp_update(ctx, tab, proj, img, tgt, fr, mp_params, mp, out, (char*)ws, (hipStream_t)stream);
+}
+
+gs_status gs_mp_regularizer(gs_ctx* ctx, int64_t n, const float* mean, const float* mean_prev, const float* mp,
+                            const float* T, float lambda, float* loss, float* dmean, void* ws, size_t ws_bytes,
+                            void* stream) {
+  if (!ctx || n < 0 || !loss) return gs_fail(ctx, GS_E_ARG, "bad argument");
+  if (n > 0 && (!mean || !mean_prev || !mp || !dmean)) return gs_fail(ctx, GS_E_ARG, "arrays are NULL");
+  const size_t need = mp_reg_ws_bytes(n);
+  if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "mp_regularizer workspace %zu < %zu", ws_bytes, need);
+  return launch_mp_reg(ctx, n, mean, mean_prev, mp, T, lambda, loss, dmean, (double*)ws, (hipStream_t)stream);
+}
+
+gs_status gs_edge_warp(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
+                       const gs_edge_pair* pairs, int32_t n_pairs, const gs_edge_params* ep, float* loss,
+                       float* ddepth, float* dpose, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !img || !tgt || !ep || !loss || !ddepth) return gs_fail(ctx, GS_E_ARG, "null argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (!img->depth || !img->mp || !img->T || !tgt->depth) return gs_fail(ctx, GS_E_ARG, "image or target NULL");
+  if (n_pairs < 0 || n_pairs > GS_MAX_VIEWS || (n_pairs > 0 && !pairs))
+    return gs_fail(ctx, GS_E_ARG, "n_pairs must be in [0, %d]", GS_MAX_VIEWS);
+  for (int k = 0; k < n_pairs; ++k)
+    if (pairs[k].i < 0 || pairs[k].i >= tab.nv || pairs[k].j < 0 || pairs[k].j >= tab.nv || pairs[k].i == pairs[k].j)
+      return gs_fail(ctx, GS_E_ARG, "pair %d: views (%d, %d) invalid", k, pairs[k].i, pairs[k].j);
+  if (!(ep->delta > 0.f) || !(ep->edge_thresh >= 0.f)) return gs_fail(ctx, GS_E_ARG, "delta > 0, edge_thresh >= 0");
+  const size_t need = edge_warp_ws_bytes(tab, n_pairs);
+  if (n_pairs > 0 && (!ws || ws_bytes < need))
+    return gs_fail(ctx, GS_E_ARG, "edge_warp workspace %zu < %zu", ws_bytes, need);
+  return launch_edge_warp(ctx, tab, views->cams_dev, img, tgt, pairs, n_pairs, ep, loss, ddepth, dpose, (double*)ws,
+                          (hipStream_t)stream);
 }
 
 gs_status gs_compact(gs_ctx* ctx, const uint8_t* drop, int64_t n, int32_t n_planes, const float* const* src,

@@ -269,6 +269,13 @@ gs_status launch_bin_prefix(gs_ctx*, const ViewTab&, const gs_camera*, const gs_
 size_t mp_ws_bytes(const ViewTab&, int64_t npix);
 gs_status launch_mp_update(gs_ctx*, const ViewTab&, const gs_proj*, const gs_image*, const gs_target*,
                            const gs_mp_frame*, const gs_mp_params*, float*, gs_mp_out*, char*, hipStream_t);
+size_t mp_reg_ws_bytes(int64_t n);
+gs_status launch_mp_reg(gs_ctx*, int64_t n, const float* mean, const float* prev, const float* mp, const float* T,
+                        float lam, float* loss, float* dmean, double* part, hipStream_t);
+size_t edge_warp_ws_bytes(const ViewTab&, int32_t n_pairs);
+gs_status launch_edge_warp(gs_ctx*, const ViewTab&, const gs_camera*, const gs_image*, const gs_target*,
+                           const gs_edge_pair*, int32_t, const gs_edge_params*, float* loss, float* ddepth,
+                           float* dpose, double* part, hipStream_t);
 size_t compact_ws_bytes(int64_t n);
 gs_status launch_compact(gs_ctx*, const uint8_t* drop, int64_t n, int32_t n_planes, const float* const* src,
                          float* const* dst, const int64_t* seg_begin, int32_t n_seg, int64_t* seg_out,

@@ -25,6 +25,7 @@ _lib = None
 
 GS_OK, GS_E_ARG, GS_E_CAPACITY, GS_E_HIP, GS_E_UNSUPPORTED = 0, 1, 2, 3, 4
 GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_LOSS, GS_OP_MP_UPDATE, GS_OP_MLP_TRAIN, GS_OP_COMPACT = 1, 2, 3, 4, 5, 6
+GS_OP_MP_REG, GS_OP_EDGE_WARP = 7, 8
 GS_COMPACT_MAX_PLANES, GS_COMPACT_MAX_SEGS = 64, 32
 GS_MAX_VIEWS = 32
 GS_MLP_PARAMS = 1377
@@ -113,6 +114,14 @@ class AdamParams(ctypes.Structure):
     _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("step", c_int32), ("step_dev", c_void_p)]
 
 
+class EdgePair(ctypes.Structure):
+    _fields_ = [("i", c_int32), ("j", c_int32)]
+
+
+class EdgeParams(ctypes.Structure):
+    _fields_ = [("lambda_", c_float), ("delta", c_float), ("edge_thresh", c_float), ("eps_A", c_float)]
+
+
 class MLP(ctypes.Structure):
     _fields_ = [(k, c_void_p) for k in ("master", "w_bf16", "adam_m", "adam_v")]
 
@@ -161,6 +170,9 @@ def lib():
             "gs_bins_check": ([P, POINTER(Bins), POINTER(c_int64), POINTER(c_int32), P], c_int32),
             "gs_mp_update": ([P, POINTER(Views), POINTER(Proj), POINTER(Image), POINTER(Target), POINTER(MPFrame),
                               POINTER(MPParams), P, POINTER(MPOut), P, c_size_t, P], c_int32),
+            "gs_mp_regularizer": ([P, c_int64, P, P, P, POINTER(c_float), c_float, P, P, P, c_size_t, P], c_int32),
+            "gs_edge_warp": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(EdgePair), c_int32,
+                              POINTER(EdgeParams), P, P, P, P, c_size_t, P], c_int32),
             "gs_compact": ([P, P, c_int64, c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int64), c_int32,
                             P, P, P, c_size_t, P], c_int32),
             "gs_mlp_features": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(MPFrame), P, P],
@@ -184,7 +196,8 @@ EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error",
             "gs_ctx_get_param", "gs_ctx_kernel_times", "gs_rec_offset", "gs_rec_count", "gs_tile_count", "gs_pixel_count",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_fwd_loss",
             "gs_render_fwd_loss_static",
-            "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_compact", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
+            "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_compact", "gs_mp_regularizer", "gs_edge_warp",
+            "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
             "gs_adam_step", "gs_pose_update")
 
 
@@ -305,6 +318,26 @@ def gs_workspace_size(ctx, views, op, capacity=0):
                                       ctypes.byref(b)),
               "gs_workspace_size")
     return int(b.value)
+
+
+def gs_mp_regularizer(ctx, mean, mean_prev, mp, loss, dmean, ws, T=None, lam=500.0, stream=None):
+    """loss[0] = lam L_MP; adds its gradient into dmean [3, n] (Eq. (23)-(24))."""
+    n = int(mp.numel())
+    Tp = (c_float * 12)(*[float(x) for x in np.asarray(T, np.float64).reshape(12)]) if T is not None else None
+    ctx.check(lib().gs_mp_regularizer(ctx.h, n, ptr(mean), ptr(mean_prev), ptr(mp), Tp, float(lam), ptr(loss),
+                                      ptr(dmean), ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+              "gs_mp_regularizer")
+
+
+def gs_edge_warp(ctx, views, img, tgt, pairs, loss, ddepth, dpose, ws, lam=300.0, delta=0.05, edge_thresh=0.05,
+                 eps_A=1e-6, stream=None):
+    """loss[k] = lam L_edge for view pairs (i, j) (Eq. (25)-(26)); adds the
+    adjoints into ddepth [P] and dpose [V, 6] (nullable)."""
+    arr = (EdgePair * max(len(pairs), 1))(*[EdgePair(int(i), int(j)) for i, j in pairs])
+    prm = EdgeParams(float(lam), float(delta), float(edge_thresh), float(eps_A))
+    ctx.check(lib().gs_edge_warp(ctx.h, ctypes.byref(views), ctypes.byref(img), ctypes.byref(tgt), arr, len(pairs),
+                                 ctypes.byref(prm), ptr(loss), ptr(ddepth), ptr(dpose), ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)), "gs_edge_warp")
 
 
 def gs_compact(ctx, drop, src, dst, n_out, ws, seg_begin=None, seg_out=None, stream=None):

@@ -259,9 +259,19 @@ class MappingWindow:
 
     PLANES = (("mean", 3), ("log_scale", 3), ("quat", 4), ("opacity_logit", 1), ("color", 3), ("mp", 1))
 
-    def __init__(self, ctx, gaussians, cams, max_rank=-1, capacity=None, lrs=None, mp_params=None):
+    def __init__(self, ctx, gaussians, cams, max_rank=-1, capacity=None, lrs=None, mp_params=None,
+                 full_objective=True, lambda_mp=500.0, lambda_edge=300.0, edge_params=None):
         """max_rank < 0: the smallest exact prefix rank (choose_rank), chosen
-        again whenever the map changes; capacity then 1.5x its list entries."""
+        again whenever the map changes; capacity then 1.5x its list entries.
+        full_objective: the iterations minimise the whole of Eq. (27), adding
+        lambda_mp L_MP (against the means at the end of the previous frame)
+        and lambda_edge L_edge over consecutive keyframes (i, i + 1) to the
+        photometric and depth terms."""
+        self.full = bool(full_objective)
+        self.lambda_mp, self.lambda_edge = float(lambda_mp), float(lambda_edge)
+        self.edge_params = dict(delta=0.05, edge_thresh=0.05, eps_A=1e-6)
+        if edge_params:
+            self.edge_params.update(edge_params)
         self.ctx = ctx
         self.cams = list(cams)
         self.lrs = lrs or dict(mean=1e-4, log_scale=5e-3, quat=1e-3, opacity_logit=2e-2, color=5e-3)
@@ -319,6 +329,18 @@ class MappingWindow:
         self.dst_planes = self._planes(self.dst, None, self.dst_m, self.dst_v)
         self.n_out = torch.zeros(1, dtype=torch.int64, device=dev)
         self.cp_ws = torch.empty(gs.gs_workspace_size(ctx, None, gs.GS_OP_COMPACT, n), dtype=torch.uint8, device=dev)
+        # the further terms: the means at the end of the previous frame, the
+        # keyframe pairs of the edge term, their losses and scratch
+        V = len(self.cams)
+        self.mean_prev = gaussians["mean"].clone()
+        self.pairs = [(v, v + 1) for v in range(V - 1)]
+        self.loss_mp = torch.zeros(1, device=dev)
+        self.loss_edge = torch.zeros(max(1, len(self.pairs)), device=dev)
+        self.pose_edge = torch.zeros(6 * V, device=dev)
+        self.mp_reg_ws = torch.empty(gs.gs_workspace_size(ctx, None, gs.GS_OP_MP_REG, n), dtype=torch.uint8,
+                                     device=dev)
+        self.edge_ws = torch.empty(max(1, gs.gs_workspace_size(ctx, self.views.s, gs.GS_OP_EDGE_WARP,
+                                                                len(self.pairs))), dtype=torch.uint8, device=dev)
 
     def _planes(self, g, adam, m=None, v=None):
         out = []
@@ -331,10 +353,26 @@ class MappingWindow:
 
     def iterate(self, target_color, target_depth):
         """One iteration over the window: render + loss + backward of every
-        keyframe, one Adam step on every Gaussian parameter."""
-        self.pipe.forward_loss(self.gst, target_color, target_depth)
-        self.pipe.backward(self.gst, self.grs)
+        keyframe (with the edge-warp and motion-consistency terms when the
+        full objective is on), one Adam step on every Gaussian parameter."""
+        p = self.pipe
+        p.forward_loss(self.gst, target_color, target_depth)
+        if self.full and self.pairs:
+            tgt = gs.Target(gs.ptr(target_color), gs.ptr(target_depth))
+            self._tgt_keep = (target_color, target_depth)
+            gs.gs_edge_warp(self.ctx, self.views.s, p.img, tgt, self.pairs, self.loss_edge, p.dD, self.pose_edge,
+                            self.edge_ws, lam=self.lambda_edge, **self.edge_params)
+        p.backward(self.gst, self.grs)
+        if self.full:
+            gs.gs_mp_regularizer(self.ctx, self.g["mean"], self.mean_prev, self.g["mp"], self.loss_mp,
+                                 self.grads["mean"], self.mp_reg_ws, lam=self.lambda_mp)
         self.adam.step([self.grads[k] for k in PARAMS])
+
+    def objective(self):
+        """The last iteration's L_G terms (synchronises): photometric + depth
+        per keyframe, l3 L_MP, l4 L_edge per keyframe pair."""
+        return dict(render=self.pipe.loss.cpu().numpy(), mp=float(self.loss_mp[0]),
+                    edge=self.loss_edge[:len(self.pairs)].cpu().numpy())
 
     def frame_end(self, target_color, target_depth, instance_id, prior, conf, seg_updated=True):
         """The newest keyframe's MP update against its observed frame (colour,

@@ -166,13 +166,14 @@ def tiny_scene(seed=1, n=2000, width=64, height=48):
     return g, cam, target_cam
 
 
-def moving_box_scene(seed, n, width, height, n_boxes=3, box_frac=0.05, margin=0.0):
-    """Static Gaussians plus `n_boxes` boxes that hold `box_frac` of the
-    Gaussians. Returns (gaussians, camera, target camera, target gaussians,
-    box slices); the target copy has the boxes moved, as in a new frame."""
+def moving_box_scene(seed, n, width, height, n_boxes=3, box_frac=0.05, margin=0.0, zmin=0.5, zmax=4.0):
+    """Static Gaussians (depth on [zmin, zmax]) plus `n_boxes` boxes that hold
+    `box_frac` of the Gaussians. Returns (gaussians, camera, target camera,
+    target gaussians, box slices); the target copy has the boxes moved, as in
+    a new frame."""
     rng = rng_for(seed)
     nb_total = int(round(n * box_frac)) if n_boxes > 0 else 0
-    g_static = static_gaussians(rng, n - nb_total, width, height, margin=margin)
+    g_static = static_gaussians(rng, n - nb_total, width, height, margin=margin, zmin=zmin, zmax=zmax)
     parts, slices, start = [g_static], [], n - nb_total
     boxes = random_boxes(rng, n_boxes, width, height)
     per = [nb_total // max(n_boxes, 1)] * n_boxes

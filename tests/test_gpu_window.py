@@ -5,7 +5,8 @@ one batch.
   parameter) against central finite differences of the FP64 oracle's forward
   on a 5k-Gaussian subset: 16 random directions restricted to the subset, and
   single coordinates of 64 of its Gaussians.
-* The whole chain of one frame (iterations of the window, then the MP update
+* The whole chain of one frame (iterations of the window on the full
+  objective of Eq. (27), then the MP update
   of the newest keyframe in log-odds mode, the prune flag at MP > 0.8 and the
   compaction of parameters, MP and Adam moments) captured in one HIP graph:
   the replay keeps its invariants, and the compaction equals removing the
@@ -270,10 +271,14 @@ def test_window_chain_in_one_graph(ctx, orc, window):
     torch.cuda.synchronize()
     graph.replay()
     torch.cuda.synchronize()
+    terms = mw.objective()
+    print(f"\n[window chain] L_G terms after the replay: render {terms['render'].sum():.4g}, "
+          f"l3 L_MP {terms['mp']:.4g}, l4 L_edge {terms['edge'].sum():.4g}")
+    assert terms["mp"] > 0 and np.all(np.isfinite(terms["edge"]))  # the means moved off the previous frame's
     mp = gd["mp"].cpu().numpy()
     observed = torch_np(mw.alpha) > 0
     prune = torch_np(mw.prune).astype(bool)
-    print(f"\n[window chain] observed {observed.sum()}, pruned {prune.sum()}")
+    print(f"[window chain] observed {observed.sum()}, pruned {prune.sum()}")
     assert observed.sum() > 1000 and 0 < prune.sum() < N
     np.testing.assert_array_equal(prune, mp > 0.8)
     np.testing.assert_array_equal(mp[~observed], mp0.cpu().numpy()[~observed])
