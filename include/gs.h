@@ -108,7 +108,8 @@ typedef struct gs_proj {
                         record when key_hist is NULL; with key_hist set it is
                         written by gs_bin_sort's prefix path, for the selected
                         records only (the only ones the lists reference). */
-  int16_t* rect;     /* [m][4] inclusive tile rect x0, y0, x1, y1; empty: x0 > x1 */
+  int16_t* rect;     /* [m][4] inclusive tile rect x0, y0, x1, y1; empty: x0 > x1.
+                        The full-list binning clips it to the view's tile grid. */
   uint32_t* depth_key; /* [m] IEEE bits of camera z; 0xFFFFFFFF if culled/empty */
   float* mean2d;     /* [2][m] optional */
   float* conic;      /* [3][m] optional: inverse 2D covariance (xx, xy, yy) */
@@ -117,9 +118,22 @@ typedef struct gs_proj {
   int32_t* radius;   /* [m] optional: opacity-aware support radius in pixels,
                         0 for culled records */
   uint32_t* key_hist;/* [V][4096] optional: gs_project adds the count of every
-                        non-culled record to bin (depth_key >> 20) of its view;
+                        record with a key to bin (depth_key >> 20) of its view;
                         gs_bin_sort's prefix path reads it and resets it to zero.
                         Must be zero-filled before the first gs_project. */
+  int32_t keys_only; /* [host, set by gs_project] 1 when it wrote the depth
+                        keys only: with key_hist set, no planar output asked for
+                        and the "exact_keys" knob off, gs_project runs a cheap
+                        screen test instead of the full projection (the same
+                        float32 depth key, near-plane and opacity culls, and a
+                        tile rect from a bound on the footprint, so that it
+                        never drops a Gaussian the full projection keeps);
+                        depth_key and key_hist then cover the Gaussians that
+                        pass it, and gs_bin_sort projects the records it
+                        selects exactly (rect and compositing record), dropping
+                        those the exact test culls. 0: depth_key and rect are
+                        those of the full projection (set it to 0 when filling
+                        rect and depth_key by other means). */
 } gs_proj;
 
 /* Per-tile lists. Entries are scene-local Gaussian ids; tile t's list is
@@ -213,9 +227,8 @@ const char* gs_last_error(const gs_ctx* ctx);
  * order), "wave_cull" (0|1, default 1: in gs_render_fwd and gs_render_bwd
  * each 64-pixel wave skips the entries whose alpha >= 1/255 region misses its
  * 16x4 pixel strip; the images are bit-identical either way, the gradients
- * equal up to the order of their float atomics), "bwd_mfma" (0|1, default 0: 1
- * forms the backward's per-entry pixel sums with FP32 matrix instructions
- * instead of wave reductions; same gradients up to summation order), and
+ * equal up to the order of their float atomics), "exact_keys" (0|1, default 0: 1 makes gs_project run the full projection on every Gaussian also when
+ * it could write the depth keys only, see gs_proj.keys_only), and
  * "timing" (0|1, see gs_ctx_kernel_times). Values outside the supported set
  * return GS_E_ARG. */
 gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value);
@@ -260,7 +273,11 @@ gs_status gs_project(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, 
  * (tile << 32 | depth bits) with value id, i.e. lists in (depth, id) order.
  * Sorts each view's records by depth key (LSD radix), then counts, scans and
  * scatters tile instances chunk by chunk in that order. `g` is read by the
- * prefix path only (to write proj->rec of the selected records). */
+ * prefix path only (to write proj->rec of the selected records). The path
+ * follows the projection: proj->key_hist set and bins->max_rank > 0 take the
+ * prefix path; the full lists (max_rank <= 0) need a gs_project run with
+ * key_hist NULL, and return GS_E_ARG with key_hist set (that projection wrote
+ * no compositing records, and in keys_only mode no rects). */
 gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, gs_proj* proj, gs_bins* bins,
                       void* ws, size_t ws_bytes, void* stream);
 

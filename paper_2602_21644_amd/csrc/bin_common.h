@@ -71,6 +71,18 @@ static __device__ __forceinline__ void rect_of(int2 rc, int& x0, int& y0, int& x
   y1 = (int)(int16_t)((uint32_t)rc.y >> 16);
 }
 
+// A caller's rect clipped to the view's gx x gy tile grid; false when empty
+// after clipping. The full-list binning reads rects it did not write, and a
+// rect outside the grid would index past its count arrays.
+static __device__ __forceinline__ bool rect_clip(int2 rc, int gx, int gy, int& x0, int& y0, int& x1, int& y1) {
+  rect_of(rc, x0, y0, x1, y1);
+  x0 = max(x0, 0);
+  y0 = max(y0, 0);
+  x1 = min(x1, gx - 1);
+  y1 = min(y1, gy - 1);
+  return x0 <= x1 && y0 <= y1;
+}
+
 // Chunk processed by block b: spread consecutive chunks over the same XCD
 // (blocks are dealt round-robin to the 8 XCDs) so that neighbouring count and
 // list writes meet in one L2.

@@ -61,11 +61,11 @@ gs_status gs_ctx_create(int device, gs_ctx** out) {
   c->tile_order = 1;
   c->bwd_copies = 8;
   c->wave_cull = 1;
-  c->bwd_mfma = 0;
   c->n_cu = 0;
   c->proj_resident = 0;
   c->lds_limit = 0;
   c->no_alloc = 0;
+  c->exact_keys = 0;
   c->err[0] = 0;
   *out = c;
   return GS_OK;
@@ -136,15 +136,15 @@ gs_status gs_ctx_set_param(gs_ctx* ctx, const char* name, int64_t value) {
   } else if (!strcmp(name, "bwd_copies")) {
     if (value != 1 && value != 2 && value != 4 && value != 8) return gs_fail(ctx, GS_E_ARG, "bwd_copies: 1|2|4|8");
     ctx->bwd_copies = (int)value;
-  } else if (!strcmp(name, "bwd_mfma")) {
-    if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "bwd_mfma: 0|1");
-    ctx->bwd_mfma = (int)value;
   } else if (!strcmp(name, "wave_cull")) {
     if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "wave_cull: 0|1");
     ctx->wave_cull = (int)value;
   } else if (!strcmp(name, "tile_order")) {
     if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "tile_order: 0|1");
     ctx->tile_order = (int)value;
+  } else if (!strcmp(name, "exact_keys")) {
+    if (value != 0 && value != 1) return gs_fail(ctx, GS_E_ARG, "exact_keys: 0|1");
+    ctx->exact_keys = (int)value;
   } else if (!strcmp(name, "bin_chunk")) {
     if (value != 256 && value != 512 && value != 1024 && value != 2048)
       return gs_fail(ctx, GS_E_ARG, "bin_chunk: 256|512|1024|2048");
@@ -163,8 +163,8 @@ gs_status gs_ctx_get_param(const gs_ctx* ctx, const char* name, int64_t* value) 
   else if (!strcmp(name, "timing")) *value = ctx->timing;
   else if (!strcmp(name, "tile_order")) *value = ctx->tile_order;
   else if (!strcmp(name, "wave_cull")) *value = ctx->wave_cull;
-  else if (!strcmp(name, "bwd_mfma")) *value = ctx->bwd_mfma;
   else if (!strcmp(name, "bwd_copies")) *value = ctx->bwd_copies;
+  else if (!strcmp(name, "exact_keys")) *value = ctx->exact_keys;
   else if (!strcmp(name, "n_cu")) *value = ctx->n_cu;
   else if (!strcmp(name, "lds_limit")) *value = (int64_t)ctx->lds_limit;
   else if (!strcmp(name, "prefix_cap")) *value = bin_prefix_cap();
@@ -228,14 +228,16 @@ static gs_status make_tab(gs_ctx* ctx, const gs_views* vw, ViewTab& tab) {
 }
 
 struct BwdWs {
-  size_t g2d, touched, pose, bytes;
+  size_t g2d, flag, list, counters, pose, bytes;
 };
 static BwdWs bwd_ws_layout(gs_ctx* ctx, const ViewTab& tab) {
   BwdWs L;
   size_t o = 0;
   L.g2d = o; o += al256((size_t)tab.nrec * 10 * 4 * (size_t)ctx->bwd_copies);
-  L.touched = o; o += al256((size_t)tab.nrec);
-  L.pose = o; o += al256((size_t)tab.nv * bwd_pose_stride(ctx, tab) * 6 * 4);
+  L.flag = o; o += al256((size_t)tab.ng * 4);
+  L.list = o; o += al256((size_t)tab.ng * 4);
+  L.counters = o; o += 256;
+  L.pose = o; o += al256((size_t)kChainBlocks * tab.nv * 6 * 4);
   L.bytes = o;
   return L;
 }
@@ -346,6 +348,13 @@ gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g,
     if (!g || g->n != tab.ng || !proj->rec) return gs_fail(ctx, GS_E_ARG, "prefix binning needs the gaussians and proj.rec");
     return launch_bin_prefix(ctx, tab, views->cams_dev, g, proj, bins, (char*)ws, (hipStream_t)stream);
   }
+  // the full lists read the rect and record of every Gaussian, which
+  // gs_project writes only when key_hist is NULL
+  if (proj->key_hist)
+    return gs_fail(ctx, GS_E_ARG,
+                   "full-list binning (max_rank <= 0) needs a projection run with proj.key_hist NULL: with it set, "
+                   "gs_project writes no compositing records%s",
+                   proj->keys_only ? " and no tile rects" : "");
   BinTab bt;
   bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
   const BinWs L = bin_ws_layout(tab, bt);
@@ -483,10 +492,12 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   if (!ws || ws_bytes < L.bytes) return gs_fail(ctx, GS_E_ARG, "render_bwd workspace %zu < %zu", ws_bytes, L.bytes);
   char* w = (char*)ws;
   hipStream_t s = (hipStream_t)stream;
-  GS_TRY(launch_render_bwd_tiles(ctx, tab, proj, bins, img, pg, bg, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
-                                 s));
-  return launch_bwd_project(ctx, tab, views->cams_dev, g, (float*)(w + L.g2d), (uint8_t*)(w + L.touched),
-                            (float*)(w + L.pose), gr, s);
+  TouchArgs touch;
+  touch.flag = (uint32_t*)(w + L.flag);
+  touch.list = (uint32_t*)(w + L.list);
+  touch.count = (uint32_t*)(w + L.counters);
+  GS_TRY(launch_render_bwd_tiles(ctx, tab, proj, bins, img, pg, bg, (float*)(w + L.g2d), touch, gr, s));
+  return launch_bwd_project(ctx, tab, views->cams_dev, g, (float*)(w + L.g2d), touch, (float*)(w + L.pose), gr, s);
 }
 
 gs_status gs_bins_check(gs_ctx* ctx, const gs_bins* bins, int64_t* required, int32_t* incomplete, void* stream) {

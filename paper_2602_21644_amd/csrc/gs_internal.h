@@ -203,11 +203,11 @@ struct gs_ctx {
   int tile_order;                // 1: backward tiles heaviest first when tile_work is given
   int bwd_copies;                // accumulators of the backward's 2D adjoint (1, 2, 4, 8)
   int wave_cull;                 // 1: each wave skips the entries that cannot reach its 16x4 strip
-  int bwd_mfma;                  // 1: the backward forms its per-entry sums on the matrix cores
   int n_cu;                      // compute units of the device (0: not queried yet)
   int proj_resident;             // bwd_project blocks the device holds at once (0: not queried yet)
   size_t lds_limit;              // LDS per workgroup usable by the binning scatter (0: not queried)
   int no_alloc;                  // 1 inside an allocation-free call: launches are not timed
+  int exact_keys;                // 1: the prefix path's projection runs the exact test on every Gaussian
   std::vector<GsTimer> pending;  // launches whose events are not read yet
   char err[512];
 };
@@ -252,12 +252,21 @@ gs_status launch_bin_sort(gs_ctx*, const ViewTab&, const BinTab&, const gs_proj*
 // epilogue: the pixel adjoints and one float64 partial per tile
 gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const float*, int, gs_image*,
                             hipStream_t, const LossArgs* loss = nullptr);
+// The Gaussians the backward's tile pass gave a gradient: flag[N] (0 or 1,
+// zero on entry, cleared again by the projection adjoint), the list of
+// flagged Gaussians in the order they were flagged, and its length (zero on
+// entry, reset by the pose reduction that ends the backward).
+struct TouchArgs {
+  uint32_t* flag;
+  uint32_t* list;
+  uint32_t* count;
+};
 gs_status launch_render_bwd_tiles(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const gs_image*,
-                                  const gs_pixel_grads*, const float*, float*, uint8_t*, hipStream_t);
-gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, float*, uint8_t*,
+                                  const gs_pixel_grads*, const float*, float*, TouchArgs, const gs_grads*,
+                                  hipStream_t);
+gs_status launch_bwd_project(gs_ctx*, const ViewTab&, const gs_camera*, const gs_gaussians*, float*, TouchArgs,
                              float*, gs_grads*, hipStream_t);
-int bwd_pose_blocks(gs_ctx*, const ViewTab&);
-int bwd_pose_stride(gs_ctx*, const ViewTab&);  // row stride of the per-block pose partials, a multiple of 4
+constexpr int kChainBlocks = 256;  // workgroups of the projection adjoint that walk the list
 int loss_blocks(const ViewTab&);
 LossArgs loss_args(const gs_target*, const gs_loss_params*, gs_pixel_grads*, double* part, float* loss);
 gs_status launch_loss(gs_ctx*, const ViewTab&, const gs_image*, const gs_target*, const gs_loss_params*, float*,

@@ -29,9 +29,14 @@ __device__ __forceinline__ void quat_rot(const float q[4], float R[3][3]) {
   R[2][0] = 2.f * (x * z - w * y); R[2][1] = 2.f * (y * z + w * x); R[2][2] = 1.f - 2.f * (x * x + y * y);
 }
 
-// cam: the view's camera; m, ls, q, opl: the Gaussian's parameters.
+// cam: the view's camera; m, ls, q, opl: the Gaussian's parameters. No
+// multiply-add is fused here, so every kernel that inlines this function
+// (the projection, the prefix binning, the projection adjoint) rounds the
+// record of a Gaussian alike: the full and the prefix lists then composite
+// bit-identical records.
 __device__ __forceinline__ ProjF project_f(const gs_camera& cam, const float m[3], const float ls[3],
                                            const float q[4], float opl) {
+#pragma clang fp contract(off)
   ProjF P;
   P.kept = false;
   bool fin = finitef_(m[0]) && finitef_(m[1]) && finitef_(m[2]) && finitef_(ls[0]) && finitef_(ls[1]) &&
@@ -81,6 +86,58 @@ __device__ __forceinline__ ProjF project_f(const gs_camera& cam, const float m[3
   P.extent = sqrtf(2.0f * __logf(255.0f * P.o) * lmax);
   P.kept = true;
   return P;
+}
+
+// The tile rect of a projected Gaussian: pixels floor(u) -/+ ceil(extent),
+// clipped to the view's tile grid; false when the Gaussian was culled or the
+// rect misses the grid. Gaussians whose projected mean or radius exceed 1e7 px
+// are treated as off-screen (the integer pixel arithmetic needs exact floats).
+__device__ __forceinline__ bool tile_rect_of(const ProjF& P, int gx, int gy, int2& rc, int& rr) {
+  rr = 0;
+  rc = make_int2((int)(uint16_t)1 | ((int)(uint16_t)1 << 16), 0);  // empty: x0 = 1 > x1 = 0
+  if (!P.kept) return false;
+  const float rf = ceilf(P.extent);
+  if (!(fabsf(P.ux) < 1e7f && fabsf(P.uy) < 1e7f && rf < 1e7f)) return false;
+  rr = (int)rf;
+  const int ix = (int)floorf(P.ux), iy = (int)floorf(P.uy);
+  const int x0 = max(0, (ix - rr) >> 4), x1 = min(gx - 1, (ix + rr) >> 4);
+  const int y0 = max(0, (iy - rr) >> 4), y1 = min(gy - 1, (iy + rr) >> 4);
+  if (x0 > x1 || y0 > y1) return false;
+  rc = make_int2((x0 & 0xFFFF) | (y0 << 16), (x1 & 0xFFFF) | (y1 << 16));
+  return true;
+}
+
+// A cheap test that never rejects a Gaussian the exact projection keeps: the
+// depth key (the same float32 camera z as project_f), the same near-plane and
+// opacity culls, and a tile rect from a bound on the footprint: the largest
+// eigenvalue of J R Sigma R^T J^T + 0.3 I is at most |J|_F^2 exp(2 max
+// log_scale) + 0.3, widened by 0.1% and one pixel. Returns the key, or
+// 0xFFFFFFFF when even the bound misses the view.
+__device__ __forceinline__ uint32_t screen_key(const gs_camera& cam, const float m[3], const float ls[3], float opl,
+                                               int gx, int gy) {
+  const float* T = cam.T_cw;
+  const float pz = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(T[8], m[0]), __fmul_rn(T[9], m[1])), __fmul_rn(T[10], m[2])),
+                             T[11]);
+  if (!(pz > cam.z_near)) return 0xFFFFFFFFu;  // also NaN
+  const float o = 1.0f / (1.0f + __expf(-opl));
+  if (!(o >= GS_ALPHA_MIN)) return 0xFFFFFFFFu;
+  const float px = T[0] * m[0] + T[1] * m[1] + T[2] * m[2] + T[3];
+  const float py = T[4] * m[0] + T[5] * m[1] + T[6] * m[2] + T[7];
+  const float iz = 1.0f / pz;
+  const float ux = cam.fx * px * iz + cam.cx, uy = cam.fy * py * iz + cam.cy;
+  const float ax = cam.fx * iz, ay = cam.fy * iz, bx = ax * px * iz, by = ay * py * iz;
+  const float jf2 = ax * ax + bx * bx + ay * ay + by * by;
+  const float smax = fmaxf(fmaxf(ls[0], ls[1]), ls[2]);
+  const float lb = (jf2 * __expf(2.0f * smax) + 0.3f) * 1.001f;
+  const float ext = sqrtf(2.0f * __logf(255.0f * o) * lb) * 1.001f + 1.0f;
+  const float rf = ceilf(ext);
+  // outside the integer range of the exact test: keep (never wrongly culled)
+  if (!(fabsf(ux) < 1e7f && fabsf(uy) < 1e7f && rf < 1e7f)) return __float_as_uint(pz);
+  const int r = (int)rf;
+  const int ix = (int)floorf(ux), iy = (int)floorf(uy);
+  const int x0 = max(0, (ix - r) >> 4), x1 = min(gx - 1, (ix + r) >> 4);
+  const int y0 = max(0, (iy - r) >> 4), y1 = min(gy - 1, (iy + r) >> 4);
+  return (x0 <= x1 && y0 <= y1) ? __float_as_uint(pz) : 0xFFFFFFFFu;
 }
 
 // Gaussian parameter planes, passed by value to the compositing kernels.

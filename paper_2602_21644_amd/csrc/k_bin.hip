@@ -186,7 +186,7 @@ __global__ __launch_bounds__(GS_BLOCK) void bin_count_kernel(ViewTab tab, BinTab
     const int64_t r = roff + id;
     if (key[r] == 0xFFFFFFFFu) continue;
     int x0, y0, x1, y1;
-    rect_of(rect[r], x0, y0, x1, y1);
+    if (!rect_clip(rect[r], gx, gy, x0, y0, x1, y1)) continue;
     diff_add(s_diff, gx + 1, x0, y0, x1, y1);
   }
   __syncthreads();
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(GS_BLOCK) void bin_scatter_kernel(ViewTab tab, BinT
     const int64_t r = roff + id;
     if (key[r] == 0xFFFFFFFFu) continue;
     int x0, y0, x1, y1;
-    rect_of(rect[r], x0, y0, x1, y1);
+    if (!rect_clip(rect[r], gx, gy, x0, y0, x1, y1)) continue;
     diff_add(my, stride, x0, y0, x1, y1);
   }
   __syncthreads();
@@ -297,8 +297,7 @@ __global__ __launch_bounds__(GS_BLOCK) void bin_scatter_kernel(ViewTab tab, BinT
       const int rx = __builtin_amdgcn_readlane(rc.x, j);
       const int ry = __builtin_amdgcn_readlane(rc.y, j);
       int x0, y0, x1, y1;
-      rect_of(make_int2(rx, ry), x0, y0, x1, y1);
-      if (x0 > x1) continue;
+      if (!rect_clip(make_int2(rx, ry), gx, gy, x0, y0, x1, y1)) continue;
       const int wdt = x1 - x0 + 1;
       const int n = wdt * (y1 - y0 + 1);
       for (int e = lane; e < n; e += 64) {

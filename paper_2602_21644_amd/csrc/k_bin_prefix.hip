@@ -85,7 +85,7 @@ __global__ __launch_bounds__(GS_BLOCK) void psel_kernel(ViewTab tab, const uint3
                                                         float4* __restrict__ rec, uint32_t* __restrict__ seg_key,
                                                         uint32_t* __restrict__ seg_id, int2* __restrict__ seg_rect,
                                                         uint32_t* __restrict__ cnt, int32_t* __restrict__ overflow,
-                                                        int32_t* __restrict__ incomplete) {
+                                                        int32_t* __restrict__ incomplete, int keys_only) {
   __shared__ uint32_t s_wave[4];
   __shared__ uint32_t s_n;
   __shared__ uint32_t s_sel[SEL_TILE];
@@ -130,16 +130,30 @@ __global__ __launch_bounds__(GS_BLOCK) void psel_kernel(ViewTab tab, const uint3
   __syncthreads();
   const uint32_t ns = s_n;
   if (threadIdx.x == 0) cnt[(int64_t)v * nb_max + b] = ns;
-  // rect and compositing record of every selected record, one per thread
+  // exact projection of every selected record, one per thread: its
+  // compositing record and, when gs_project wrote the depth keys only, its
+  // tile rect (empty when the exact test culls a record the screen test kept,
+  // so that it lands in no list)
   const gs_camera cam = cams[v];
+  const int64_t N = gsrc.n;
   for (uint32_t p = threadIdx.x; p < ns; p += GS_BLOCK) {
     const uint32_t j = s_sel[p];
-    seg_rect[sbase + p] = rect[roff + j];
-    float4 a, bb, cc;
-    render_record(cam, gsrc, tab.g_off[v] + j, a, bb, cc);
-    rec[3 * (roff + j) + 0] = a;
-    rec[3 * (roff + j) + 1] = bb;
-    rec[3 * (roff + j) + 2] = cc;
+    const int64_t gk = tab.g_off[v] + j;
+    const float m[3] = {gsrc.mean[gk], gsrc.mean[N + gk], gsrc.mean[2 * N + gk]};
+    const float ls[3] = {gsrc.log_scale[gk], gsrc.log_scale[N + gk], gsrc.log_scale[2 * N + gk]};
+    const float q[4] = {gsrc.quat[gk], gsrc.quat[N + gk], gsrc.quat[2 * N + gk], gsrc.quat[3 * N + gk]};
+    const ProjF P = project_f(cam, m, ls, q, gsrc.opl[gk]);
+    int2 rc;
+    int rr;
+    if (keys_only)
+      tile_rect_of(P, tab.gx[v], tab.gy[v], rc, rr);
+    else
+      rc = rect[roff + j];
+    seg_rect[sbase + p] = rc;
+    rec[3 * (roff + j) + 0] = make_float4(P.ux, P.uy, P.pz, P.o);
+    rec[3 * (roff + j) + 1] =
+        make_float4(gs_conic_scale_diag(P.k1), gs_conic_scale_off(P.k2), gs_conic_scale_diag(P.k3), gsrc.mp[gk]);
+    rec[3 * (roff + j) + 2] = make_float4(gsrc.color[gk], gsrc.color[N + gk], gsrc.color[2 * N + gk], 0.f);
   }
 }
 
@@ -565,7 +579,7 @@ gs_status launch_bin_prefix(gs_ctx* ctx, const ViewTab& tab, const gs_camera* ca
   uint32_t* nsel = (uint32_t*)(ws + L.nsel);
   GS_LAUNCH(ctx, psel_kernel, dim3(L.nb_max, tab.nv), dim3(GS_BLOCK), 0, s, tab, proj->depth_key, proj->key_hist,
             (const int2*)proj->rect, bins->max_rank, L.nb_max, cams, gsrc, (float4*)proj->rec, seg_key, seg_id,
-            seg_rect, cnt, bins->overflow, bins->incomplete);
+            seg_rect, cnt, bins->overflow, bins->incomplete, proj->keys_only ? 1 : 0);
   GS_LAUNCH(ctx, psort_kernel, dim3(tab.nv), dim3(PS_THREADS), PS_LDS, s, tab, L.nb_max, cnt, seg_key, seg_id,
             seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete);
   int nblk = 1;

@@ -1,19 +1,17 @@
 // Second part of gs_render_bwd: per-Gaussian adjoint of the projection.
 //
-// One thread per Gaussian (all scenes); it visits every view of its scene,
-// reads the 2D adjoint the tile pass accumulated for that (view, Gaussian)
-// record (the sum of its per-XCD copies, gathered by the whole wave) only
-// when the record was touched, chains it through the projection in float32
-// and sums the parameter gradients over views in registers. Read records are
-// reset to zero so the scratch stays zero-filled between calls.
-// The grid is as many blocks as the device holds at once; block b takes the
-// groups of GS_BLOCK Gaussians b, b + grid, ... Most Gaussians of a large
-// scene are never composited, so a wave loads the touched flags of its next
-// group while it works on the current one, and a wave without any touched
-// record only stores zero gradients (nothing at all when accumulating), with
-// no block barrier. Pose-twist partials are summed per wave into LDS, then
-// per block, and the block partials in a fixed order by a second kernel
-// (deterministic).
+// The tile pass lists every Gaussian it gave a gradient (once per call) and
+// clears the dense gradient outputs (each of its workgroups a slice, after
+// its tile). kChainBlocks workgroups then walk the list, one thread per listed
+// Gaussian: for every view of its scene it gathers the record's 2D adjoint
+// (the sum of its per-XCD copies in a fixed order, every load in flight at
+// once, the copies reset to zero so the scratch stays zero-filled), chains it
+// through the projection in float32, sums the parameter gradients over the
+// views in registers, stores them (or adds them when accumulating) and clears
+// the Gaussian's flag; the pose-twist terms are summed per wave and per
+// workgroup.
+// A second, one-wave-per-view kernel sums the chain workgroups' pose
+// partials in a fixed order and resets the list length.
 //
 // The chain works with the camera-space square root T1 = R Rq diag(S) of the
 // covariance (cov2D = (J T1)(J T1)^T + 0.3 I), a different route from the
@@ -24,101 +22,84 @@ namespace {
 
 constexpr int kMaxCopies = 8;  // largest "bwd_copies"
 
-// Views of the scene in which Gaussian gk has a touched record, as a bit mask.
-__device__ __forceinline__ uint32_t touched_views(const ViewTab& tab, const uint8_t* __restrict__ touched,
-                                                  int64_t gk) {
-  uint32_t h = 0u;
-  for (int v = 0; v < tab.nv; ++v) {
-    const int64_t k = gk - tab.g_off[v];
-    if (gk < tab.ng && k >= 0 && k < tab.n[v] && touched[tab.r_off[v] + k] != 0) h |= 1u << v;
-  }
-  return h;
-}
-
-// The 2D adjoint of record r, summed over its `copies` accumulators (layout
-// [copy][record][10]) and reset to zero, for every lane with hit set. The
-// whole wave gathers one record at a time: lane 5 x + k loads float2 k of
-// copy x, a fixed shuffle tree sums the copies, and the owning lane takes the
-// five sums. Wave-uniform control flow; lanes without a hit get zeros.
-__device__ __forceinline__ void gather_adjoint(bool hit, int64_t r, int64_t M, int copies, float* __restrict__ g2d,
-                                               float (&a)[10]) {
-  const int lane = __lane_id();
-#pragma unroll
-  for (int c = 0; c < 10; ++c) a[c] = 0.f;
-  uint64_t m = __ballot(hit);
-  const int cp = lane / 5, kk = lane - 5 * (lane / 5);
-  while (m) {
-    const int src = __ffsll((long long)m) - 1;
-    m &= m - 1;
-    const int64_t rs = __shfl(r, src, 64);
-    float2 t = make_float2(0.f, 0.f);
-    if (cp < copies) {
-      float2* p = reinterpret_cast<float2*>(g2d + ((int64_t)cp * M + rs) * 10) + kk;
-      t = *p;
-      *p = make_float2(0.f, 0.f);
-    }
-    // copies x and x + 4, then x + 2, then x + 1 (zeros past `copies`)
-#pragma unroll
-    for (int off = 20; off >= 5; off >>= 1) {
-      t.x += __shfl_down(t.x, off, 64);
-      t.y += __shfl_down(t.y, off, 64);
-    }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const float x = __shfl(t.x, k, 64), y = __shfl(t.y, k, 64);
-      if (lane == src) {
-        a[2 * k] = x;
-        a[2 * k + 1] = y;
-      }
-    }
-  }
-}
-
 __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
     ViewTab tab, const gs_camera* __restrict__ cams, const float* __restrict__ mean,
     const float* __restrict__ log_scale, const float* __restrict__ quat, const float* __restrict__ opl,
-    float* __restrict__ g2d, uint8_t* __restrict__ touched, float* __restrict__ d_mean,
-    float* __restrict__ d_ls, float* __restrict__ d_quat, float* __restrict__ d_opl, float* __restrict__ d_color,
-    float* __restrict__ pose_part, int pstride, int pose_only, int accumulate, int copies) {
-  __shared__ float s_pose[GS_BLOCK / 64][GS_MAX_VIEWS * 6];  // per-wave pose sums
-  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    float* __restrict__ g2d, TouchArgs touch, float* __restrict__ d_mean, float* __restrict__ d_ls,
+    float* __restrict__ d_quat, float* __restrict__ d_opl, float* __restrict__ d_color, float* __restrict__ pose_part,
+    float* __restrict__ pose, int pose_only, int accumulate, int copies, int clear_all) {
   const int64_t N = tab.ng;
   const int64_t M = tab.nrec;
-  for (int i = lane; i < tab.nv * 6; i += 64) s_pose[wv][i] = 0.f;
-  __syncthreads();
-  const int64_t ngroups = (N + GS_BLOCK - 1) / GS_BLOCK;
-  uint32_t hnext = touched_views(tab, touched, (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x);
-#pragma unroll 1
-  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    const uint32_t hg = hnext;
-    hnext = touched_views(tab, touched, (grp + gridDim.x) * GS_BLOCK + threadIdx.x);
-    const int64_t gk = grp * GS_BLOCK + threadIdx.x;
-    const bool valid = gk < N;
-    float gm[3] = {0, 0, 0}, gl[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
-    if (__ballot(hg != 0u) != 0) {
-      // parameters of touched Gaussians, in flight during the adjoint gather
-      float m[3] = {0, 0, 0}, ls[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, op = 0.f;
-      if (hg != 0u) {
-        for (int c = 0; c < 3; ++c) {
-          m[c] = mean[c * N + gk];
-          ls[c] = log_scale[c * N + gk];
-        }
-        for (int c = 0; c < 4; ++c) q[c] = quat[c * N + gk];
-        op = opl[gk];
+  if (clear_all) {
+    // no tile pass ran (no tiles), so nothing is listed and no gradient was
+    // cleared: every Gaussian gets zeros
+    for (int64_t gk = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x; gk < N; gk += (int64_t)gridDim.x * GS_BLOCK) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        d_mean[c * N + gk] = 0.f;
+        d_ls[c * N + gk] = 0.f;
+        d_color[c * N + gk] = 0.f;
       }
-      for (int v = 0; v < tab.nv; ++v) {
-        float pv[6] = {0, 0, 0, 0, 0, 0};
-        bool has = false;
-        const int64_t k = gk - tab.g_off[v];
-        const bool in = valid && k >= 0 && k < tab.n[v];
-        const int64_t r = in ? tab.r_off[v] + k : 0;
-        const bool hit = ((hg >> v) & 1u) != 0u;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) d_quat[c * N + gk] = 0.f;
+      d_opl[gk] = 0.f;
+    }
+  }
+  __shared__ float s_pose[GS_BLOCK / 64][GS_MAX_VIEWS * 6];  // per-wave pose sums
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  for (int i = lane; i < tab.nv * 6; i += 64) s_pose[wv][i] = 0.f;
+  const uint32_t cnt = *touch.count;
+#pragma unroll 1
+  for (uint32_t i0 = blockIdx.x * GS_BLOCK; i0 < cnt; i0 += kChainBlocks * GS_BLOCK) {  // uniform per block
+    const uint32_t li = i0 + threadIdx.x;
+    const bool valid = li < cnt;
+    const int64_t gk = valid ? (int64_t)touch.list[li] : 0;
+    if (valid) touch.list[li] = 0u;  // the scratch is left zero-filled
+    float gm[3] = {0, 0, 0}, gl[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
+    float m[3] = {0, 0, 0}, ls[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, op = 0.f;
+    if (valid) {
+      for (int c = 0; c < 3; ++c) {
+        m[c] = mean[c * N + gk];
+        ls[c] = log_scale[c * N + gk];
+      }
+      for (int c = 0; c < 4; ++c) q[c] = quat[c * N + gk];
+      op = opl[gk];
+    }
+    for (int v = 0; v < tab.nv; ++v) {
+      float pv[6] = {0, 0, 0, 0, 0, 0};
+      bool has = false;
+      const int64_t k = gk - tab.g_off[v];
+      const bool hit = valid && k >= 0 && k < tab.n[v];
+      if (hit) {
+        // the record's adjoint: its copies summed in a fixed order, then reset
+        const int64_t r = tab.r_off[v] + k;
+        float2 t[kMaxCopies][5];
+#pragma unroll
+        for (int cp = 0; cp < kMaxCopies; ++cp)
+#pragma unroll
+          for (int u = 0; u < 5; ++u)
+            t[cp][u] = cp < copies ? reinterpret_cast<const float2*>(g2d + ((int64_t)cp * M + r) * 10)[u]
+                                   : make_float2(0.f, 0.f);
         float a[10];
-        gather_adjoint(hit, r, M, copies, g2d, a);
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+          float x = 0.f, y = 0.f;
+#pragma unroll
+          for (int cp = 0; cp < kMaxCopies; ++cp) {
+            x += t[cp][u].x;
+            y += t[cp][u].y;
+          }
+          a[2 * u] = x;
+          a[2 * u + 1] = y;
+        }
+#pragma unroll
+        for (int cp = 0; cp < kMaxCopies; ++cp)
+          if (cp < copies)
+#pragma unroll
+            for (int u = 0; u < 5; ++u)
+              reinterpret_cast<float2*>(g2d + ((int64_t)cp * M + r) * 10)[u] = make_float2(0.f, 0.f);
         {
-          if (hit) {
             has = true;
-            touched[r] = 0;
             const gs_camera cam = cams[v];
             const ProjF P = project_f(cam, m, ls, q, op);
             gc[0] += a[6];
@@ -198,120 +179,93 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
             }
           }
         }
-        if (__ballot(has) != 0) {
+      if (__ballot(has) != 0) {
 #pragma unroll
-          for (int c = 0; c < 6; ++c) {
-            const float x = wave_sum_to_lane63(pv[c]);
-            if (lane == 63) s_pose[wv][v * 6 + c] += x;
-          }
+        for (int c = 0; c < 6; ++c) {
+          const float x = wave_sum_to_lane63(pv[c]);
+          if (lane == 63) s_pose[wv][v * 6 + c] += x;
         }
       }
     }
-    if (valid && !pose_only) {
-      if (accumulate) {
-        if (hg == 0u) continue;  // zero gradients leave the sums as they are
-        for (int c = 0; c < 3; ++c) {
-          d_mean[c * N + gk] += gm[c];
-          d_ls[c * N + gk] += gl[c];
-          d_color[c * N + gk] += gc[c];
+    if (valid) {
+      if (!pose_only) {
+        if (accumulate) {
+          for (int c = 0; c < 3; ++c) {
+            d_mean[c * N + gk] += gm[c];
+            d_ls[c * N + gk] += gl[c];
+            d_color[c * N + gk] += gc[c];
+          }
+          for (int c = 0; c < 4; ++c) d_quat[c * N + gk] += gq[c];
+          d_opl[gk] += go;
+        } else {
+          for (int c = 0; c < 3; ++c) {
+            d_mean[c * N + gk] = gm[c];
+            d_ls[c * N + gk] = gl[c];
+            d_color[c * N + gk] = gc[c];
+          }
+          for (int c = 0; c < 4; ++c) d_quat[c * N + gk] = gq[c];
+          d_opl[gk] = go;
         }
-        for (int c = 0; c < 4; ++c) d_quat[c * N + gk] += gq[c];
-        d_opl[gk] += go;
-      } else {
-        for (int c = 0; c < 3; ++c) {
-          d_mean[c * N + gk] = gm[c];
-          d_ls[c * N + gk] = gl[c];
-          d_color[c * N + gk] = gc[c];
-        }
-        for (int c = 0; c < 4; ++c) d_quat[c * N + gk] = gq[c];
-        d_opl[gk] = go;
       }
+      touch.flag[gk] = 0u;
     }
   }
-  // block partials [view][component][pstride]: the four wave sums in order
+  // this workgroup's pose partials: the four wave sums in order
   __syncthreads();
-  for (int i = threadIdx.x; i < tab.nv * 6; i += GS_BLOCK)
-    pose_part[(int64_t)i * pstride + blockIdx.x] = s_pose[0][i] + s_pose[1][i] + s_pose[2][i] + s_pose[3][i];
+  const int nvp = tab.nv * 6;
+  for (int i = threadIdx.x; i < nvp; i += GS_BLOCK)
+    pose_part[(int64_t)blockIdx.x * nvp + i] = s_pose[0][i] + s_pose[1][i] + s_pose[2][i] + s_pose[3][i];
 }
 
-// Sums one view's per-block pose partials in a fixed order (one workgroup per
-// view, float64) and resets them to zero, so the scratch stays zero-filled.
-// The partials are stored per component with a row stride that is a multiple
-// of four, so each thread has 6 x kPoseGroup float4 loads in flight.
-constexpr int kPoseGroup = 4;
-__global__ __launch_bounds__(GS_BLOCK) void pose_final_kernel(float* __restrict__ part, int pstride,
-                                                              float* __restrict__ pose, int accumulate) {
-  __shared__ double s_red[GS_BLOCK / 64][6];
-  const int v = blockIdx.x, lane = __lane_id(), w = threadIdx.x >> 6;
-  float4* pv = reinterpret_cast<float4*>(part + (int64_t)v * 6 * pstride);
-  const int n4 = pstride >> 2;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int j0 = threadIdx.x; j0 < n4; j0 += kPoseGroup * GS_BLOCK) {
-    float4 x[6][kPoseGroup];
+// One wave per view: the chain workgroups' pose partials of its six twist
+// components summed in double in a fixed order (each lane the partials of
+// workgroups lane, lane + 64, ..., then a butterfly over the lanes), the
+// partials zeroed and the list length reset for the next call. A kernel of
+// its own: a fence inside the projection adjoint would have to write back
+// the gradients it streams through L2.
+__global__ __launch_bounds__(64) void pose_final_kernel(int nv, float* __restrict__ pose_part,
+                                                        float* __restrict__ pose, int accumulate,
+                                                        uint32_t* __restrict__ count) {
+  const int v = blockIdx.x, lane = threadIdx.x;
+  const int nvp = nv * 6;
+  static_assert(kChainBlocks % 64 == 0, "whole waves of partials");
+  constexpr int kPer = kChainBlocks / 64;
+  float x[kPer][6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+  for (int j = 0; j < kPer; ++j)  // every load in flight before the first add
 #pragma unroll
-      for (int u = 0; u < kPoseGroup; ++u) {
-        const int j = j0 + u * GS_BLOCK;
-        x[c][u] = j < n4 ? pv[c * n4 + j] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
+    for (int c = 0; c < 6; ++c) x[j][c] = pose_part[(int64_t)(lane + 64 * j) * nvp + v * 6 + c];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+  for (int j = 0; j < kPer; ++j)
 #pragma unroll
-      for (int u = 0; u < kPoseGroup; ++u) {
-        acc[c] += (double)x[c][u].x;
-        acc[c] += (double)x[c][u].y;
-        acc[c] += (double)x[c][u].z;
-        acc[c] += (double)x[c][u].w;
-        const int j = j0 + u * GS_BLOCK;
-        if (j < n4) pv[c * n4 + j] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-  }
-  for (int c = 0; c < 6; ++c) {
-    acc[c] = wave_sum_to_lane63_d(acc[c]);
-    if (lane == 63) s_red[w][c] = acc[c];
-  }
-  __syncthreads();
-  if (threadIdx.x < 6 && pose) {
-    const int c = threadIdx.x;
-    const double t = s_red[0][c] + s_red[1][c] + s_red[2][c] + s_red[3][c];
-    pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + t : t);
+    for (int c = 0; c < 6; ++c) pose_part[(int64_t)(lane + 64 * j) * nvp + v * 6 + c] = 0.f;
+  double t[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < kPer; ++j)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t[c] += (double)x[j][c];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) t[c] = wave_sum_to_lane63_d(t[c]);
+  if (lane == 0) {
+    if (pose)
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + t[c] : t[c]);
+    if (v == 0) *count = 0u;
   }
 }
 
 }  // namespace
 
 gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams, const gs_gaussians* g,
-                             float* g2d, uint8_t* touched, float* pose_part, gs_grads* gr, hipStream_t s) {
-  const int nblk = bwd_pose_blocks(ctx, tab);
-  {
-    GS_LAUNCH(ctx, bwd_project_kernel, dim3(nblk), dim3(GS_BLOCK), 0, s, tab, cams, g->mean, g->log_scale,
-                       g->quat, g->opacity_logit, g2d, touched, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
-                       gr->color, pose_part, bwd_pose_stride(ctx, tab), gr->pose_only, gr->accumulate,
-                       ctx->bwd_copies);
-  }
-  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(GS_BLOCK), 0, s, pose_part, bwd_pose_stride(ctx, tab), gr->pose,
-            gr->accumulate);
-  return gs_check_launch(ctx, "render_bwd_project");
+                             float* g2d, TouchArgs touch, float* pose_part, gs_grads* gr, hipStream_t s) {
+  GS_LAUNCH(ctx, bwd_project_kernel, dim3(kChainBlocks), dim3(GS_BLOCK), 0, s, tab, cams, g->mean,
+            g->log_scale, g->quat, g->opacity_logit, g2d, touch, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
+            gr->color, pose_part, gr->pose, gr->pose_only, gr->accumulate, ctx->bwd_copies,
+            tab.ntiles == 0 && !gr->pose_only && !gr->accumulate ? 1 : 0);
+  const gs_status st = gs_check_launch(ctx, "render_bwd_project");
+  if (st != GS_OK) return st;
+  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(64), 0, s, tab.nv, pose_part, gr->pose, gr->accumulate,
+            touch.count);
+  return gs_check_launch(ctx, "render_bwd_pose");
 }
-
-// Blocks of bwd_project: one per group of GS_BLOCK Gaussians, at most as
-// many as the device holds at once (queried once per context).
-int bwd_pose_blocks(gs_ctx* ctx, const ViewTab& tab) {
-  if (ctx->proj_resident <= 0) {
-    int n = ctx->n_cu, per = 0;
-    if (n <= 0 && (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess))
-      n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)bwd_project_kernel, GS_BLOCK, 0) !=
-        hipSuccess)
-      per = 0;
-    (void)hipGetLastError();
-    ctx->proj_resident = n > 0 && per > 0 ? n * per : 1024;
-  }
-  const int64_t groups = (tab.ng + GS_BLOCK - 1) / GS_BLOCK;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(groups, ctx->proj_resident));
-}
-
-int bwd_pose_stride(gs_ctx* ctx, const ViewTab& tab) { return (bwd_pose_blocks(ctx, tab) + 3) & ~3; }

@@ -36,24 +36,8 @@ __device__ __forceinline__ uint32_t project_one(const ViewTab& tab, const gs_cam
   const float q[4] = {quat[gk], quat[N + gk], quat[2 * N + gk], quat[3 * N + gk]};
   const ProjF P = project_f(cam, m, ls, q, opl[gk]);
   int rr = 0;
-  bool nonempty = false;
-  int2 rc = empty_rect;
-  if (P.kept) {
-    const float rf = ceilf(P.extent);
-    // Gaussians whose projected mean or radius exceed 1e7 px are treated as
-    // off-screen (integer pixel arithmetic below needs exact floats).
-    if (fabsf(P.ux) < 1e7f && fabsf(P.uy) < 1e7f && rf < 1e7f) {
-      rr = (int)rf;
-      const int ix = (int)floorf(P.ux), iy = (int)floorf(P.uy);
-      const int gx = tab.gx[v], gy = tab.gy[v];
-      const int x0 = max(0, (ix - rr) >> 4), x1 = min(gx - 1, (ix + rr) >> 4);
-      const int y0 = max(0, (iy - rr) >> 4), y1 = min(gy - 1, (iy + rr) >> 4);
-      if (x0 <= x1 && y0 <= y1) {
-        nonempty = true;
-        rc = make_int2((x0 & 0xFFFF) | (y0 << 16), (x1 & 0xFFFF) | (y1 << 16));
-      }
-    }
-  }
+  int2 rc;
+  const bool nonempty = tile_rect_of(P, tab.gx[v], tab.gy[v], rc, rr);
   rect[r] = rc;
   const uint32_t kout = nonempty ? __float_as_uint(P.pz) : 0xFFFFFFFFu;
   key[r] = kout;
@@ -119,6 +103,56 @@ __global__ __launch_bounds__(PBLOCK) void project_kernel(ViewTab tab, const gs_c
   }
 }
 
+// The prefix path's projection when no planar output is asked for: only the
+// depth key of every Gaussian (from the cheap screen test, which never drops
+// a Gaussian the exact projection keeps) and the key histogram. gs_bin_sort
+// then projects the few selected Gaussians exactly, writes their rects and
+// compositing records and drops those the exact test culls. Reads 28 bytes
+// per Gaussian (mean, log-scale, opacity logit) and writes 4.
+__global__ __launch_bounds__(PBLOCK) void project_key_kernel(ViewTab tab, const gs_camera* __restrict__ cams,
+                                                             const float* __restrict__ mean,
+                                                             const float* __restrict__ log_scale,
+                                                             const float* __restrict__ opl, uint32_t* __restrict__ key,
+                                                             uint32_t* __restrict__ key_hist) {
+  __shared__ uint32_t s_hist[4096];
+  const int v = blockIdx.y;
+  const int64_t npad = tab.npad[v];
+  const int64_t base = (int64_t)blockIdx.x * PBLOCK * PITEMS;
+  if (base >= npad) return;  // uniform per workgroup
+  for (int i = threadIdx.x; i < 4096; i += PBLOCK) s_hist[i] = 0;
+  const gs_camera cam = cams[v];
+  const int64_t N = tab.ng, nv = tab.n[v], goff = tab.g_off[v], roff = tab.r_off[v];
+  const int gx = tab.gx[v], gy = tab.gy[v];
+  // every load of the workgroup's records in flight before the first is used
+  float m[PITEMS][3], ls[PITEMS][3], ol[PITEMS];
+#pragma unroll
+  for (int it = 0; it < PITEMS; ++it) {
+    const int64_t k = base + it * PBLOCK + threadIdx.x;
+    const int64_t gk = goff + (k < nv ? k : 0);
+    m[it][0] = mean[gk];
+    m[it][1] = mean[N + gk];
+    m[it][2] = mean[2 * N + gk];
+    ls[it][0] = log_scale[gk];
+    ls[it][1] = log_scale[N + gk];
+    ls[it][2] = log_scale[2 * N + gk];
+    ol[it] = opl[gk];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < PITEMS; ++it) {
+    const int64_t k = base + it * PBLOCK + threadIdx.x;
+    if (k >= npad) continue;
+    const uint32_t kv = k < nv ? screen_key(cam, m[it], ls[it], ol[it], gx, gy) : 0xFFFFFFFFu;
+    key[roff + k] = kv;
+    if (kv != 0xFFFFFFFFu) atomicAdd(&s_hist[kv >> 20], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4096; i += PBLOCK) {
+    const uint32_t c = s_hist[i];
+    if (c) atomicAdd(&key_hist[(int64_t)v * 4096 + i], c);
+  }
+}
+
 }  // namespace
 
 gs_status launch_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams, const gs_gaussians* g,
@@ -127,6 +161,13 @@ gs_status launch_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* cams,
   for (int v = 0; v < tab.nv; ++v) maxn = tab.npad[v] > maxn ? tab.npad[v] : maxn;
   if (maxn == 0) return GS_OK;
   dim3 grid((unsigned)((maxn + PBLOCK * PITEMS - 1) / (PBLOCK * PITEMS)), tab.nv);
+  const bool planar = p->mean2d || p->conic || p->depth || p->opacity || p->radius;
+  p->keys_only = p->key_hist && !planar && !ctx->exact_keys ? 1 : 0;
+  if (p->keys_only) {
+    GS_LAUNCH(ctx, project_key_kernel, grid, dim3(PBLOCK), 0, s, tab, cams, g->mean, g->log_scale, g->opacity_logit,
+              p->depth_key, p->key_hist);
+    return gs_check_launch(ctx, "project");
+  }
   GS_LAUNCH(ctx, project_kernel, grid, dim3(PBLOCK), p->key_hist ? 4096 * 4 : 0, s, tab, cams, g->mean,
             g->log_scale, g->quat, g->opacity_logit, g->color, g->mp, p->key_hist ? nullptr : (float4*)p->rec,
             (int2*)p->rect, p->depth_key, p->mean2d, p->conic, p->depth, p->opacity, p->radius, p->key_hist);

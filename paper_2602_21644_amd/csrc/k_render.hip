@@ -373,14 +373,38 @@ __global__ __launch_bounds__(kOrderThreads) void fwd_finish_kernel(ViewTab tab, 
 // into the 2D gradients with the entry's opacity and conic
 // (d/du = -o * conic * (sum h*d), d/dconic = -o/2 * (sum h*d d^T) off-diagonal
 // counted twice), so the per-pixel work carries no conic products.
+// The dense gradient outputs, zeroed by the tile pass: workgroup b clears
+// Gaussians [b chunk, (b + 1) chunk) of all fourteen planes once its tile is
+// done, so the stores overlap the other workgroups' compositing; the
+// projection adjoint then writes the listed Gaussians over the zeros.
+struct GradZero {
+  float* plane[14];  // NULL first plane: nothing to clear (pose only, or accumulating)
+  int64_t n, chunk;  // chunk: a multiple of 4
+  int vec4;          // n % 4 == 0 and every plane 16-byte aligned
+};
+
+__device__ __forceinline__ void zero_grad_slice(const GradZero& z, int blk) {
+  if (!z.plane[0]) return;
+  const int64_t lo = (int64_t)blk * z.chunk, hi = min(lo + z.chunk, z.n);
+  if (z.vec4) {
+    for (int64_t i = (lo >> 2) + threadIdx.x; i < (hi >> 2); i += GS_BLOCK)
+#pragma unroll
+      for (int q = 0; q < 14; ++q) reinterpret_cast<float4*>(z.plane[q])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    for (int64_t k = lo + threadIdx.x; k < hi; k += GS_BLOCK)
+#pragma unroll
+      for (int q = 0; q < 14; ++q) z.plane[q][k] = 0.f;
+  }
+}
+
 template <int BATCH>
 __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void render_bwd_kernel(
     ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
     const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
     const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
-    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies,
-    int cull) {
+    float* __restrict__ g2d, TouchArgs touch, const uint32_t* __restrict__ order, int copies, int cull,
+    GradZero zg) {
   __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
   __shared__ uint8_t s_mask[BATCH];
   // per wave: the batch entries it walks (mask has its strip, inside its
@@ -392,7 +416,10 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) v
   __shared__ float4 s_red[BATCH][17];
   __shared__ uint32_t s_r[BATCH];
   __shared__ uint32_t s_max;
-  if (*overflow) return;
+  if (*overflow) {
+    zero_grad_slice(zg, blockIdx.x);
+    return;
+  }
   // the order the forward dealt, while its marker is valid for this tile count
   uint32_t tu = blockIdx.x;
   if (order) {
@@ -591,288 +618,27 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) v
       s_red[jj][0] = make_float4(gv[0], gv[1], gv[2], gv[3]);
       s_red[jj][1] = make_float4(gv[4], gv[5], gv[6], gv[7]);
       s_red[jj][2] = make_float4(gv[8], gv[9], 0.f, 0.f);
+      // the first tile that gives a Gaussian a gradient lists it (once per
+      // call) for the projection adjoint
+      bool any = false;
+#pragma unroll
+      for (int c = 0; c < 10; ++c) any = any || gv[c] != 0.f;
+      if (any) {
+        const uint32_t gk = (uint32_t)(tab.g_off[tc.v] + ((int64_t)s_r[jj] - roff));
+        if (touch.flag[gk] == 0u && atomicExch(&touch.flag[gk], 1u) == 0u) touch.list[atomicAdd(touch.count, 1u)] = gk;
+      }
     }
     __syncthreads();
     // ten adjacent threads per entry: a wave's atomics fall on few lines
     for (int qq = tid - kLoadThreads; qq >= 0 && qq < n * 10; qq += GS_BLOCK - kLoadThreads) {
       const int jj = qq / 10, c = qq - jj * 10;
       const float gval = reinterpret_cast<const float*>(&s_red[jj][0])[c];
-      if (gval != 0.f) {
-        const uint32_t r = s_r[jj];
-        atomicAdd(&g2d[(int64_t)r * 10 + c], gval);
-        touched[r] = 1;
-      }
+      if (gval != 0.f) atomicAdd(&g2d[(int64_t)s_r[jj] * 10 + c], gval);
     }
   }
+  zero_grad_slice(zg, blockIdx.x);
 }
 
-
-// The same backward with the per-entry moment sums on the matrix cores.
-//
-// The ten sums over a wave's 64 pixels are a product (entries x pixels) x
-// (pixels x features). With pixel coordinates (lx, ly) relative to the tile
-// centre and the entry's mean u relative to it, d = u - (lx, ly), so
-//   sum h d_x   = u_x S0 - S1,   sum h d_y = u_y S0 - S2,
-//   sum h d_x^2 = u_x^2 S0 - 2 u_x S1 + S3,
-//   sum h d_x d_y = u_x u_y S0 - u_x S2 - u_y S1 + S4,
-//   sum h d_y^2 = u_y^2 S0 - 2 u_y S2 + S5,
-// where S = sum_p h_p (1, lx, ly, lx^2, lx ly, ly^2); the colour and depth
-// sums are sum_p w_p (g_r, g_g, g_b, g_D). Each wave takes, back to front,
-// the batch's entries below its largest n_last whose alpha >= 1/255 box meets
-// its 16x4 strip (the forward's strip test; the others composite none of its
-// pixels), gathered 16 at a time from a ballot. Every lane runs the
-// transmittance recursion of its pixel over the group branch-free (slots past
-// the last entry read a zero record; invalid entries leave T and the suffix
-// term unchanged),
-// storing h and w to two LDS tiles [entry][pixel]; then 16
-// v_mfma_f32_16x16x4f32 steps multiply the h tile by the per-pixel features
-// (step s, lane group k: pixel 16k + s of the wave) and 16 more the w tile
-// by the colour and depth features, skipped when no entry of the group
-// composites a pixel of the wave. The accumulators hold D[slot][feature];
-// the per-entry sums start at zero each batch, so entries a wave skips count
-// zero for it; the cross-wave pass adds the four waves, expands the sums
-// into moments about the entry's mean and applies opacity and conic as the
-// wave reduction path does.
-typedef float gs_floatx4 __attribute__((ext_vector_type(4)));
-constexpr int kGroup = 16;
-constexpr int kRow = 64 + 4;  // pixels per LDS row, padded across banks
-
-template <int BATCH>
-__global__ __launch_bounds__(GS_BLOCK) void render_bwd_mfma_kernel(
-    ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
-    const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
-    const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
-    const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
-    float* __restrict__ g2d, uint8_t* __restrict__ touched, const uint32_t* __restrict__ order, int copies,
-    int cull) {
-  static_assert(BATCH % 64 == 0 || BATCH < 64, "entries are gathered in windows of 64");
-  // slot BATCH is a zero record for the slots past the last entry
-  __shared__ float4 s_a[BATCH + 1], s_b[BATCH + 1], s_c[BATCH + 1];
-  __shared__ uint32_t s_r[BATCH];
-  __shared__ uint8_t s_mask[BATCH];
-  __shared__ float s_t[GS_BLOCK / 64][2][kGroup][kRow];  // per wave: the h and w tiles of a group
-  __shared__ float4 s_dm[BATCH][10];                  // [entry][sum]: the four waves' values
-  __shared__ uint32_t s_max;
-  if (*overflow) return;
-  // the order the forward dealt, while its marker is valid for this tile count
-  uint32_t tu = blockIdx.x;
-  if (order) {
-    const uint32_t ntl = (uint32_t)tab.ntiles, cand = order[blockIdx.x];
-    if (order[ntl] == ntl + 1u && cand < ntl) tu = cand;
-  }
-  const int t = (int)tu;
-  const TileCtx tc = tile_ctx(tab, t);
-  const uint32_t b = tile_start[t];
-  const int64_t roff = tab.r_off[tc.v];
-  const int64_t P = tab.npix;
-  const int64_t M = tab.nrec;
-  const int w = threadIdx.x >> 6, lane = __lane_id();
-  // accumulator of the XCD the workgroup runs on, as in render_bwd_kernel
-  if (copies > 1) g2d += (int64_t)(__builtin_amdgcn_s_getreg((31 << 11) | 20) & (uint32_t)(copies - 1)) * 10 * M;
-  const float fx = (float)tc.px, fy = (float)tc.py;
-  constexpr float kHalf = 0.5f * (GS_TILE - 1);  // tile centre in pixel units from its first pixel
-  const float cx = (float)(tc.tx * GS_TILE) + kHalf, cy = (float)(tc.ty * GS_TILE) + kHalf;
-  float T = 1.f, gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gd = 0.f, gm = 0.f, Tbar = 0.f;
-  uint32_t nl = 0;
-  if (threadIdx.x == 0) {
-    s_max = 0;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    s_a[BATCH] = z;
-    s_b[BATCH] = z;
-    s_c[BATCH] = z;
-  }
-  __syncthreads();
-  if (tc.inside) {
-    T = imgT[tc.pix];
-    nl = nlast[tc.pix];
-    gc0 = dC[tc.pix];
-    gc1 = dC[P + tc.pix];
-    gc2 = dC[2 * P + tc.pix];
-    gd = dD[tc.pix];
-    gm = dM ? dM[tc.pix] : 0.f;
-    const float gt = dT ? dT[tc.pix] : 0.f;
-    Tbar = gt + gc0 * bg0 + gc1 * bg1 + gc2 * bg2;
-  }
-  uint32_t wmax = nl;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, o, 64));
-  if (lane == 0) atomicMax(&s_max, wmax);
-  // B operands: lane (k = lane >> 4, j = lane & 15) at step s supplies feature
-  // j of the wave's pixel 16k + s (lx = s, ly = 4w + k, both from the centre)
-  const int mk = lane >> 4, mj = lane & 15;
-  float bphi[kGroup], bpsi[kGroup];
-  {
-    const float ly = (float)(4 * w + mk) - kHalf;
-#pragma unroll
-    for (int st = 0; st < kGroup; ++st) {
-      const float lx = (float)st - kHalf;
-      bphi[st] = mj == 0 ? 1.f : mj == 1 ? lx : mj == 2 ? ly : mj == 3 ? lx * lx : mj == 4 ? lx * ly
-                 : mj == 5 ? ly * ly : 0.f;
-      const int src = 16 * mk + st;
-      const float q0 = __shfl(gc0, src, 64), q1 = __shfl(gc1, src, 64), q2 = __shfl(gc2, src, 64),
-                  q3 = __shfl(gd, src, 64);
-      bpsi[st] = mj == 6 ? q0 : mj == 7 ? q1 : mj == 8 ? q2 : mj == 9 ? q3 : 0.f;
-    }
-  }
-  __syncthreads();
-  const uint32_t maxl = s_max;
-  const int tid = (int)threadIdx.x;
-  float4 ra, rb, rc;
-  uint32_t rn = 0, idn = 0;
-  {
-    const int lo0 = max(0, (int)maxl - BATCH), lo1 = max(0, lo0 - BATCH);
-    if (tid < (int)maxl - lo0) {
-      rn = (uint32_t)(roff + ids[b + lo0 + tid]);
-      ra = rec[3 * (int64_t)rn + 0];
-      rb = rec[3 * (int64_t)rn + 1];
-      rc = rec[3 * (int64_t)rn + 2];
-    }
-    if (tid < lo0 - lo1) idn = ids[b + lo1 + tid];
-  }
-  float* rowh = &s_t[w][0][0][0];
-  float* roww = &s_t[w][1][0][0];
-  const float* arow = rowh + mj * kRow + 16 * mk;
-  const float* brow = roww + mj * kRow + 16 * mk;
-  for (int hi = (int)maxl; hi > 0; hi -= BATCH) {
-    const int lo = max(0, hi - BATCH);
-    const int n = hi - lo;
-    __syncthreads();
-    if (tid < n) {
-      s_r[tid] = rn;
-      s_a[tid] = ra;
-      s_b[tid] = rb;
-      s_c[tid] = rc;
-      s_mask[tid] = cull ? (uint8_t)strip_mask(ra, rb, tc.tx * GS_TILE, tc.ty * GS_TILE) : (uint8_t)0xF;
-    }
-    for (int i = tid; i < BATCH * 10; i += GS_BLOCK) (&s_dm[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    __syncthreads();
-    {
-      const int lo1 = max(0, lo - BATCH), lo2 = max(0, lo1 - BATCH);
-      if (tid < lo - lo1) {
-        rn = (uint32_t)(roff + idn);
-        ra = rec[3 * (int64_t)rn + 0];
-        rb = rec[3 * (int64_t)rn + 1];
-        rc = rec[3 * (int64_t)rn + 2];
-      }
-      if (tid < lo1 - lo2) idn = ids[b + lo2 + tid];
-    }
-    // entries that can reach a pixel of this wave: below its largest n_last
-    const int jtop = (uint32_t)lo < wmax ? min(n, (int)(wmax - (uint32_t)lo)) : 0;
-    for (int c0 = ((jtop - 1) >> 6) << 6; c0 >= 0; c0 -= 64) {
-      const int jl = c0 + lane;
-      uint64_t ball = __ballot(jl < jtop && ((s_mask[jl < BATCH ? jl : 0] >> w) & 1u));
-      while (ball) {
-        // the next 16 of them from the top; slot e takes entry jj (lane e
-        // keeps it), slots past the last entry the zero record
-        gs_floatx4 acc_h = {0.f, 0.f, 0.f, 0.f}, acc_w = {0.f, 0.f, 0.f, 0.f};
-        bool anyv = false;
-        int jsv = BATCH;
-#pragma unroll 4
-        for (int e = 0; e < kGroup; ++e) {
-          const int hb = 63 - __builtin_clzll(ball | 1ull);
-          const int jj = ball ? c0 + hb : BATCH;
-          ball &= ~(1ull << hb);
-          jsv = lane == e ? jj : jsv;
-          const int js_ = jj;
-          const float4 A = s_a[js_];
-          const float4 B = s_b[js_];
-          const float4 Cc = s_c[js_];
-          const float dx = A.x - fx, dy = A.y - fy;
-          const float p = gs_power2(B.x, B.y, B.z, dx, dy);
-          const float G = __builtin_amdgcn_exp2f(p);
-          const float araw = A.w * G;
-          const float alpha = fminf(GS_ALPHA_MAX, araw);
-          const bool valid = (uint32_t)(lo + jj) < nl && p <= 0.f && alpha >= GS_ALPHA_MIN;
-          anyv = anyv || valid;
-          const float a = valid ? alpha : 0.f;
-          const float one_m = 1.0f - a;
-          const float Tj = T * __builtin_amdgcn_rcpf(one_m);
-          const float vdot = gc0 * Cc.x + gc1 * Cc.y + gc2 * Cc.z + gd * A.z + gm * B.w;
-          const float abar = Tj * (vdot - Tbar);
-          const float h = (valid && araw < GS_ALPHA_MAX) ? abar * G : 0.f;
-          rowh[e * kRow + lane] = h;
-          roww[e * kRow + lane] = a * Tj;
-          Tbar = vdot * a + Tbar * one_m;
-          T = Tj;
-        }
-        if (__ballot(anyv)) {  // uniform
-#pragma unroll
-          for (int q = 0; q < kGroup / 4; ++q) {
-            const float4 av = *reinterpret_cast<const float4*>(arow + 4 * q);
-            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bphi[4 * q + 0], acc_h, 0, 0, 0);
-            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bphi[4 * q + 1], acc_h, 0, 0, 0);
-            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bphi[4 * q + 2], acc_h, 0, 0, 0);
-            acc_h = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bphi[4 * q + 3], acc_h, 0, 0, 0);
-          }
-#pragma unroll
-          for (int q = 0; q < kGroup / 4; ++q) {
-            const float4 av = *reinterpret_cast<const float4*>(brow + 4 * q);
-            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bpsi[4 * q + 0], acc_w, 0, 0, 0);
-            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bpsi[4 * q + 1], acc_w, 0, 0, 0);
-            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bpsi[4 * q + 2], acc_w, 0, 0, 0);
-            acc_w = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bpsi[4 * q + 3], acc_w, 0, 0, 0);
-          }
-          // lane holds D[4k + r][j]: slot 4k + r, feature j
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int jj = __shfl(jsv, 4 * mk + r, 64);
-            if (mj < 10 && jj < BATCH) reinterpret_cast<float*>(&s_dm[jj][mj])[w] = acc_h[r] + acc_w[r];
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // cross-wave pass on the waves that load nothing (see render_bwd_kernel):
-    // one thread per entry forms its ten components, then ten adjacent
-    // threads per entry issue the atomics
-    constexpr int kLoadThreads = (BATCH + 63) / 64 * 64;
-    static_assert(GS_BLOCK - kLoadThreads >= BATCH, "a thread per entry");
-    const int q = tid - kLoadThreads;
-    if (q >= 0 && q < n) {
-      const int jj = q;
-      float sm[10];
-#pragma unroll
-      for (int f = 0; f < 10; ++f) {
-        const float4 v = s_dm[jj][f];
-        sm[f] = (v.x + v.y) + (v.z + v.w);
-      }
-      const float4 A = s_a[jj];
-      const float4 B = s_b[jj];
-      const float o = A.w;
-      const float ux = A.x - cx, uy = A.y - cy;
-      const float S0 = sm[0], S1 = sm[1], S2 = sm[2];
-      const float m0 = ux * S0 - S1, m1 = uy * S0 - S2;
-      const float m2 = ux * (ux * S0 - 2.0f * S1) + sm[3];
-      const float m3 = ux * (uy * S0 - S2) - uy * S1 + sm[4];
-      const float m4 = uy * (uy * S0 - 2.0f * S2) + sm[5];
-      const float k1 = B.x * (-2.0f / GS_LOG2E), k2 = B.y * (-1.0f / GS_LOG2E), k3 = B.z * (-2.0f / GS_LOG2E);
-      float gv[10];
-      gv[0] = -o * (k1 * m0 + k2 * m1);
-      gv[1] = -o * (k2 * m0 + k3 * m1);
-      gv[2] = -0.5f * o * m2;
-      gv[3] = -o * m3;
-      gv[4] = -0.5f * o * m4;
-      gv[5] = S0;
-      gv[6] = sm[6];
-      gv[7] = sm[7];
-      gv[8] = sm[8];
-      gv[9] = sm[9];
-      s_dm[jj][0] = make_float4(gv[0], gv[1], gv[2], gv[3]);
-      s_dm[jj][1] = make_float4(gv[4], gv[5], gv[6], gv[7]);
-      s_dm[jj][2] = make_float4(gv[8], gv[9], 0.f, 0.f);
-    }
-    __syncthreads();
-    for (int qq = tid - kLoadThreads; qq >= 0 && qq < n * 10; qq += GS_BLOCK - kLoadThreads) {
-      const int jj = qq / 10, c = qq - jj * 10;
-      const float gval = reinterpret_cast<const float*>(&s_dm[jj][0])[c];
-      if (gval != 0.f) {
-        const uint32_t r = s_r[jj];
-        atomicAdd(&g2d[(int64_t)r * 10 + c], gval);
-        touched[r] = 1;
-      }
-    }
-  }
-}
 
 }  // namespace
 
@@ -921,21 +687,32 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
 
 gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj, const gs_bins* bins,
                                   const gs_image* img, const gs_pixel_grads* pg, const float* bg, float* g2d,
-                                  uint8_t* touched, hipStream_t s) {
-  if (tab.ntiles == 0) return GS_OK;
+                                  TouchArgs touch, const gs_grads* gr, hipStream_t s) {
+  if (tab.ntiles == 0) return GS_OK;  // the projection adjoint then clears the gradients itself
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
+  GradZero zg{};
+  if (!gr->pose_only && !gr->accumulate && tab.ng > 0) {
+    const int64_t n = tab.ng;
+    float* const pl[14] = {gr->mean,          gr->mean + n,      gr->mean + 2 * n, gr->log_scale,
+                           gr->log_scale + n, gr->log_scale + 2 * n, gr->quat,     gr->quat + n,
+                           gr->quat + 2 * n,  gr->quat + 3 * n,  gr->opacity_logit, gr->color,
+                           gr->color + n,     gr->color + 2 * n};
+    bool vec4 = (n & 3) == 0;
+    for (int q = 0; q < 14; ++q) {
+      zg.plane[q] = pl[q];
+      vec4 = vec4 && ((uintptr_t)pl[q] & 15) == 0;
+    }
+    zg.n = n;
+    zg.chunk = ((n + tab.ntiles - 1) / tab.ntiles + 3) & ~(int64_t)3;
+    zg.vec4 = vec4 ? 1 : 0;
+  }
   const float4* rec = (const float4*)proj->rec;
   // the order the last forward dealt (second half of the scheduling state)
   const uint32_t* order = img->tile_work && ctx->tile_order ? img->tile_work + tab.ntiles : nullptr;
-#define GS_BWD(BATCH)                                                                                          \
-  if (ctx->bwd_mfma)                                                                                           \
-    GS_LAUNCH(ctx, render_bwd_mfma_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start, \
-              bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
-              g2d, touched, order, ctx->bwd_copies, ctx->wave_cull);                                           \
-  else                                                                                                         \
-    GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,    \
-              bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
-              g2d, touched, order, ctx->bwd_copies, ctx->wave_cull)
+#define GS_BWD(BATCH)                                                                                        \
+  GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,    \
+            bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
+            g2d, touch, order, ctx->bwd_copies, ctx->wave_cull, zg)
   switch (ctx->bwd_batch) {
     case 32: GS_BWD(32); break;
     case 128: GS_BWD(128); break;

@@ -56,7 +56,7 @@ class Gaussians(ctypes.Structure):
 
 class Proj(ctypes.Structure):
     _fields_ = [("m", c_int64)] + [(k, c_void_p) for k in ("rec", "rect", "depth_key", "mean2d", "conic", "depth",
-                                                          "opacity", "radius", "key_hist")]
+                                                          "opacity", "radius", "key_hist")] + [("keys_only", c_int32)]
 
 
 class Bins(ctypes.Structure):
@@ -517,8 +517,6 @@ class Pipeline:
         self.proj.m = M
         self.proj.rec, self.proj.rect, self.proj.depth_key = ptr(self.rec), ptr(self.rect), ptr(self.key)
         self.key_hist = torch.zeros(views.V * 4096, dtype=i32, device=dev)
-        if max_rank > 0:
-            self.proj.key_hist = ptr(self.key_hist)
         if full_proj:
             for k in ("mean2d", "conic", "depth", "opacity", "radius"):
                 setattr(self.proj, k, ptr(getattr(self, k)))
@@ -535,7 +533,7 @@ class Pipeline:
         self.bins.n_instances = c_void_p(base)
         self.bins.overflow = c_void_p(base + 8)
         self.bins.incomplete = c_void_p(base + 16)
-        self.bins.max_rank = int(max_rank)
+        self.set_max_rank(max_rank)
         self.img_color = torch.empty(3 * P, dtype=f32, device=dev)
         self.img_depth = torch.empty(P, dtype=f32, device=dev)
         self.img_mp = torch.empty(P, dtype=f32, device=dev)
@@ -581,6 +579,14 @@ class Pipeline:
 
     def clear_flags(self):
         self.flags.zero_()
+
+    def set_max_rank(self, max_rank: int):
+        """Switches between the prefix lists (max_rank > 0: gs_project fills
+        the key histogram and gs_bin_sort projects the selected records) and
+        the full lists (max_rank <= 0: gs_project writes every record)."""
+        self.bins.max_rank = int(max_rank)
+        self.key_hist.zero_()
+        self.proj.key_hist = ptr(self.key_hist) if max_rank > 0 else None
 
     def set_loss_params(self, lambda_pho=0.9, lambda_depth=0.1, eps_A=1e-6, weight_mode=0, grad_through_weight=0):
         self.lp = LossParams(lambda_pho, lambda_depth, eps_A, weight_mode, grad_through_weight)

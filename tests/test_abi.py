@@ -47,7 +47,8 @@ def test_status_strings_and_param_validation():
     assert ctx.get_param("n_cu") == 0  # queried by the first backward on a GPU
     assert ctx.get_param("bwd_copies") == 8
     assert ctx.get_param("wave_cull") == 1
-    assert ctx.get_param("bwd_mfma") == 0
+    with pytest.raises(gs.GSError):
+        ctx.get_param("bwd_mfma")  # the matrix-core backward was removed
     with pytest.raises(gs.GSError):
         ctx.set_param("bwd_copies", 3)
 

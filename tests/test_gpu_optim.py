@@ -199,7 +199,11 @@ def test_truncated_prefix_and_overflow_raise(ctx):
     short.clear_flags()
     gst = gs.gaussians_struct(gd)
     short.forward_loss(gst, tc.reshape(-1).contiguous(), td)
-    short.bins.max_rank = 0  # full lists from here on
+    # full lists from here on: the binning path must follow the projection
+    short.bins.max_rank = 0
+    with pytest.raises(gs.GSError, match="key_hist NULL"):
+        gs.gs_bin_sort(ctx, views.s, gst, short.proj, short.bins, short.ws_bin)
+    short.set_max_rank(0)
     for _ in range(2):
         short.forward_loss(gst, tc.reshape(-1).contiguous(), td)
     over, n_inst, inc = short.check()

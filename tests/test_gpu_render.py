@@ -401,34 +401,6 @@ def test_wave_cull_exact(ctx, seed, n, W, H, max_rank):
         assert_grads_close(torch_np(other[1]), torch_np(grads[0][1]), rel=1e-4, name="pose")
 
 
-@pytest.mark.parametrize("seed,n,W,H,batch", [(31, 20000, 640, 480, 64), (32, 3000, 100, 75, 32),
-                                              (33, 60000, 320, 240, 128)])
-def test_bwd_mfma_matches_vector_path(ctx, seed, n, W, H, batch):
-    """The matrix-core form of the backward's per-entry sums gives the
-    gradients of the vector-reduction form (only summation order differs)."""
-    g, cam, tcam, g_t, sl = synth.moving_box_scene(seed, n, W, H)
-    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], bg=(0.1, 0.1, 0.1))
-    pipe.forward(gst)
-    tc, td = (pipe.img_color * 0.7).contiguous(), (pipe.img_depth * 1.2).contiguous()
-    pipe.loss_and_grads(tc, td)
-    ctx.set_param("bwd_batch", batch)
-    res = []
-    for mf in (1, 0):
-        ctx.set_param("bwd_mfma", mf)
-        gr = gs.alloc_grads(n)
-        pose = torch.zeros(6, device="cuda")
-        pipe.backward(gst, gs.grads_struct(gr, pose))
-        torch.cuda.synchronize()
-        res.append((gr, pose))
-        assert torch.count_nonzero(bwd_zero_part(pipe, views)) == 0
-    ctx.set_param("bwd_mfma", 0)
-    ctx.set_param("bwd_batch", 64)
-    for k in res[0][0]:
-        assert_grads_close(torch_np(res[0][0][k]), torch_np(res[1][0][k]), rel=1e-4, name=k)
-    assert_grads_close(torch_np(res[0][1]), torch_np(res[1][1]), rel=1e-4, name="pose")
-    assert float(res[0][0]["mean"].abs().sum()) > 0
-
-
 def test_max_rank_prefix_lists(ctx, orc):
     """Binning only the records in front of the rank-R threshold gives exact
     prefixes of the full lists (every tile checked). At the smallest exact
@@ -595,3 +567,44 @@ def test_wave_cull_exact_thin_edges(ctx, seed):
         assert_grads_close(torch_np(grads[1][0][k]), torch_np(grads[0][0][k]), rel=1e-5, name=k)
     for k in grads[0][0]:
         assert np.isfinite(torch_np(grads[1][0][k])).all() and np.isfinite(torch_np(grads[0][0][k])).all()
+
+
+@pytest.mark.parametrize("seed,n,W,H", [(71, 200000, 320, 240), (72, 1_000_000, 640, 480), (73, 3000, 64, 48)])
+def test_keys_only_projection(ctx, orc, seed, n, W, H):
+    """On the prefix path without planar outputs gs_project writes depth keys
+    from its cheap screen test: every Gaussian the full projection keys gets
+    the same key (the test never drops one it keeps), and the lists binned
+    from those keys are exact prefixes of the full lists; at an exact rank the
+    images equal the full-list images bit for bit."""
+    from paper_2602_21644_amd import optim
+    g, cam, tcam, g_t, sl = synth.moving_box_scene(seed, n, W, H)
+    for c in (cam, tcam):
+        views, full, gt, gst = make_pipeline(ctx, g, [c], capacity=max(1 << 16, 60 * n))
+        full.forward(gst)
+        over, _, _ = full.check()
+        assert not over
+        ex_key = torch_np(full.key).view(np.uint32)[:n].copy()
+        full_ids = torch_np(full.ids).view(np.uint32).copy()
+        full_ts = torch_np(full.tile_start).view(np.uint32).astype(np.int64)
+        R, _ = optim.choose_rank(ctx, views, gst, n)
+        if R == 0:
+            R = 256  # sparse scene: a truncated prefix still has to be exact
+        ko = gs.Pipeline(ctx, views, capacity=max(1 << 16, 60 * n), max_rank=R)
+        ko.forward(gst)
+        assert ko.proj.keys_only == 1
+        over, n_inst, inc = ko.check()
+        assert not over
+        sk = torch_np(ko.key).view(np.uint32)[:n]
+        kept = ex_key != 0xFFFFFFFF
+        np.testing.assert_array_equal(sk[kept], ex_key[kept])
+        print(f"\n[keys only] {kept.sum()} keyed exactly, {int((sk != 0xFFFFFFFF).sum())} by the screen test, "
+              f"rank {R}, incomplete {inc}")
+        ts = torch_np(ko.tile_start).view(np.uint32).astype(np.int64)
+        ids = torch_np(ko.ids).view(np.uint32)
+        for t in range(len(ts) - 1):
+            mine = ids[ts[t]:ts[t + 1]]
+            np.testing.assert_array_equal(mine, full_ids[full_ts[t]:full_ts[t] + len(mine)])
+        if inc == 0:
+            for a, b in zip((full.img_color, full.img_depth, full.img_mp, full.img_T, full.img_nlast),
+                            (ko.img_color, ko.img_depth, ko.img_mp, ko.img_T, ko.img_nlast)):
+                assert torch.equal(a, b)
