@@ -496,6 +496,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   touch.flag = (uint32_t*)(w + L.flag);
   touch.list = (uint32_t*)(w + L.list);
   touch.count = (uint32_t*)(w + L.counters);
+  touch.ticket = touch.count + 1;
   GS_TRY(launch_render_bwd_tiles(ctx, tab, proj, bins, img, pg, bg, (float*)(w + L.g2d), touch, gr, s));
   return launch_bwd_project(ctx, tab, views->cams_dev, g, (float*)(w + L.g2d), touch, (float*)(w + L.pose), gr, s);
 }

@@ -254,12 +254,14 @@ gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bi
                             hipStream_t, const LossArgs* loss = nullptr);
 // The Gaussians the backward's tile pass gave a gradient: flag[N] (0 or 1,
 // zero on entry, cleared again by the projection adjoint), the list of
-// flagged Gaussians in the order they were flagged, and its length (zero on
-// entry, reset by the pose reduction that ends the backward).
+// flagged Gaussians in the order they were flagged, its length, and the
+// ticket that finds the projection adjoint's last working workgroup (both
+// zero on entry and reset by that workgroup).
 struct TouchArgs {
   uint32_t* flag;
   uint32_t* list;
   uint32_t* count;
+  uint32_t* ticket;
 };
 gs_status launch_render_bwd_tiles(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const gs_image*,
                                   const gs_pixel_grads*, const float*, float*, TouchArgs, const gs_grads*,

@@ -10,8 +10,9 @@
 // views in registers, stores them (or adds them when accumulating) and clears
 // the Gaussian's flag; the pose-twist terms are summed per wave and per
 // workgroup.
-// A second, one-wave-per-view kernel sums the chain workgroups' pose
-// partials in a fixed order and resets the list length.
+// The last workgroup with list entries to finish (a ticket counter with
+// device-scope fences) sums the workgroups' pose partials in a fixed order
+// and resets the list length and the ticket.
 //
 // The chain works with the camera-space square root T1 = R Rq diag(S) of the
 // covariance (cov2D = (J T1)(J T1)^T + 0.3 I), a different route from the
@@ -46,9 +47,21 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
     }
   }
   __shared__ float s_pose[GS_BLOCK / 64][GS_MAX_VIEWS * 6];  // per-wave pose sums
+  __shared__ uint32_t s_last;
   const int lane = __lane_id(), wv = threadIdx.x >> 6;
-  for (int i = lane; i < tab.nv * 6; i += 64) s_pose[wv][i] = 0.f;
+  const int nvp = tab.nv * 6;
+  // every workgroup reads the same length: the last working workgroup resets
+  // it only after all working workgroups have taken their ticket
   const uint32_t cnt = *touch.count;
+  const uint32_t nwork = min((cnt + GS_BLOCK - 1) / GS_BLOCK, (uint32_t)kChainBlocks);
+  if (nwork == 0) {
+    // nothing listed: the pose gradient is zero
+    if (blockIdx.x == 0 && pose && !accumulate)
+      for (int i = threadIdx.x; i < nvp; i += GS_BLOCK) pose[i] = 0.f;
+    return;
+  }
+  if (blockIdx.x >= nwork) return;
+  for (int i = lane; i < nvp; i += 64) s_pose[wv][i] = 0.f;
 #pragma unroll 1
   for (uint32_t i0 = blockIdx.x * GS_BLOCK; i0 < cnt; i0 += kChainBlocks * GS_BLOCK) {  // uniform per block
     const uint32_t li = i0 + threadIdx.x;
@@ -210,48 +223,33 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
       touch.flag[gk] = 0u;
     }
   }
-  // this workgroup's pose partials: the four wave sums in order
+  // this workgroup's pose partials (the four wave sums in order), then a
+  // ticket: the last working workgroup sums the partials in a fixed order.
+  // Only the workgroups with list entries take part, and they store little,
+  // so the device-scope fences stay cheap.
   __syncthreads();
-  const int nvp = tab.nv * 6;
   for (int i = threadIdx.x; i < nvp; i += GS_BLOCK)
     pose_part[(int64_t)blockIdx.x * nvp + i] = s_pose[0][i] + s_pose[1][i] + s_pose[2][i] + s_pose[3][i];
-}
-
-// One wave per view: the chain workgroups' pose partials of its six twist
-// components summed in double in a fixed order (each lane the partials of
-// workgroups lane, lane + 64, ..., then a butterfly over the lanes), the
-// partials zeroed and the list length reset for the next call. A kernel of
-// its own: a fence inside the projection adjoint would have to write back
-// the gradients it streams through L2.
-__global__ __launch_bounds__(64) void pose_final_kernel(int nv, float* __restrict__ pose_part,
-                                                        float* __restrict__ pose, int accumulate,
-                                                        uint32_t* __restrict__ count) {
-  const int v = blockIdx.x, lane = threadIdx.x;
-  const int nvp = nv * 6;
-  static_assert(kChainBlocks % 64 == 0, "whole waves of partials");
-  constexpr int kPer = kChainBlocks / 64;
-  float x[kPer][6];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j)  // every load in flight before the first add
-#pragma unroll
-    for (int c = 0; c < 6; ++c) x[j][c] = pose_part[(int64_t)(lane + 64 * j) * nvp + v * 6 + c];
-#pragma unroll
-  for (int j = 0; j < kPer; ++j)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) pose_part[(int64_t)(lane + 64 * j) * nvp + v * 6 + c] = 0.f;
-  double t[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int j = 0; j < kPer; ++j)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) t[c] += (double)x[j][c];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) t[c] = wave_sum_to_lane63_d(t[c]);
-  if (lane == 0) {
-    if (pose)
-#pragma unroll
-      for (int c = 0; c < 6; ++c)
-        pose[v * 6 + c] = (float)(accumulate ? (double)pose[v * 6 + c] + t[c] : t[c]);
-    if (v == 0) *count = 0u;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(touch.ticket, 1u) == nwork - 1u ? 1u : 0u;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // wave w sums components w, w + 4, ...: each lane the partials of
+  // workgroups lane, lane + 64, ... in double, then a fixed butterfly
+  for (int i = wv; i < nvp; i += GS_BLOCK / 64) {
+    double t = 0.0;
+    for (uint32_t b = lane; b < nwork; b += 64) {
+      t += (double)pose_part[(int64_t)b * nvp + i];
+      pose_part[(int64_t)b * nvp + i] = 0.f;
+    }
+    t = wave_sum_to_lane63_d(t);
+    if (lane == 0 && pose) pose[i] = (float)(accumulate ? (double)pose[i] + t : t);
+  }
+  if (threadIdx.x == 0) {
+    *touch.count = 0u;
+    *touch.ticket = 0u;
   }
 }
 
@@ -263,9 +261,5 @@ gs_status launch_bwd_project(gs_ctx* ctx, const ViewTab& tab, const gs_camera* c
             g->log_scale, g->quat, g->opacity_logit, g2d, touch, gr->mean, gr->log_scale, gr->quat, gr->opacity_logit,
             gr->color, pose_part, gr->pose, gr->pose_only, gr->accumulate, ctx->bwd_copies,
             tab.ntiles == 0 && !gr->pose_only && !gr->accumulate ? 1 : 0);
-  const gs_status st = gs_check_launch(ctx, "render_bwd_project");
-  if (st != GS_OK) return st;
-  GS_LAUNCH(ctx, pose_final_kernel, dim3(tab.nv), dim3(64), 0, s, tab.nv, pose_part, gr->pose, gr->accumulate,
-            touch.count);
-  return gs_check_launch(ctx, "render_bwd_pose");
+  return gs_check_launch(ctx, "render_bwd_project");
 }

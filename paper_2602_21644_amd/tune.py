@@ -24,7 +24,7 @@ import torch
 from . import gs
 from .optim import choose_rank
 
-KNOBS = dict(render_batch=(64, 128, 256), bwd_batch=(32, 64, 128))
+KNOBS = dict(render_batch=(64, 128, 256), bwd_batch=(32, 64, 128), bwd_copies=(1, 8))
 FULL_KNOBS = dict(bin_chunk=(256, 512, 1024, 2048))
 
 
