@@ -345,6 +345,7 @@ def main():
         out["uneven_batch"] = uneven_batch(ctx)
         out["learned_mp"] = learned_mp(ctx, a, g, cam, tc, td)
         out["tracking"] = tracking_run(ctx)
+        out["epipolar"] = epipolar_run(ctx)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, cam, tc.cpu().numpy().reshape(3, -1), td.cpu().numpy())
     print(json.dumps(out), flush=True)
@@ -472,6 +473,59 @@ def tracking_run(ctx, n=200_000, W=640, H=480, iters=100):
             "ms_per_iteration": round(ms, 4), "iters_per_s": round(1000.0 / ms, 1),
             "start_error": [0.5, 10.0], "final_error_deg_mm": [round(ang, 4), round(dist * 1e3, 3)],
             "exact": bool(exact)}
+
+
+def epipolar_run(ctx, n=1_000_000, W=640, H=480, n_cand=50000):
+    """Epipolar verification and static recovery (Eq. (18)-(19)) of 50k
+    candidate Gaussians of a 1M-Gaussian map, 4-28 synthetic matches each,
+    between two keyframes 5 frames apart: median of 20 calls (HIP events),
+    and the select kernel's duration against its algorithmic HBM bytes."""
+    import torch
+    from paper_2602_21644_amd import gs, synth
+    c = synth.epipolar_case(7, n, W, H, n_cand, per=(4, 28))
+    views = gs.ViewBatch([c["cam1"], c["cam2"]], n)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    p1, p2, ids, seg = dev(c["p1"]), dev(c["p2"]), dev(c["ids"]), dev(c["seg"])
+    m, K = int(c["p1"].shape[1]), int(c["ids"].size)
+    mp0 = dev(c["mp"])
+    mp = mp0.clone()
+    d = torch.empty(m, device="cuda")
+    dbar = torch.empty(K, device="cuda")
+    state = torch.empty(K, dtype=torch.uint8, device="cuda")
+
+    def call():
+        gs.gs_epipolar_verify(ctx, views.s, 0, 1, p1, p2, ids, seg, mp, d, dbar, state)
+
+    times = []
+    for i in range(22):
+        mp.copy_(mp0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        e1.synchronize()
+        if i >= 2:
+            times.append(e0.elapsed_time(e1))
+    ctx.kernel_times()
+    ctx.set_param("timing", 1)
+    for _ in range(10):
+        call()
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times()
+    ctx.set_param("timing", 0)
+    mp.copy_(mp0)
+    call()
+    torch.cuda.synchronize()
+    sel_us = 1000.0 * kt["epi_select_kernel"][1] / kt["epi_select_kernel"][0]
+    nbytes = m * 20 + K * 21  # p1, p2 read and d written per match; id, range, mp, dbar, state per candidate
+    ms = float(np.median(times))
+    restored = int((state == gs.GS_EPI_RESTORED).sum())
+    log(f"[bench] epipolar: {K} candidates, {m} matches, {ms:.4f} ms per call, select kernel {sel_us:.1f} us, "
+        f"{restored} restored")
+    return {"n_gaussians": n, "candidates": K, "matches": m, "ms_per_call": round(ms, 4),
+            "matches_per_s": round(m / (ms * 1e-3), 1), "select_kernel_us": round(sel_us, 2),
+            "select_hbm_gbs": round(nbytes / (sel_us * 1e-6) / 1e9, 1),
+            "select_hbm_frac": round(nbytes / (sel_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "restored": restored}
 
 
 def window_batch(ctx, a, g, g_t):

@@ -437,6 +437,38 @@ gs_status gs_edge_warp(gs_ctx* ctx, const gs_views* views, const gs_image* img, 
                        const gs_edge_params* params /*[host]*/, float* loss, float* ddepth, float* dpose, void* ws,
                        size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- epipolar verification
+ * Static recovery near motion boundaries, Sec. IV-C, Eq. (18)-(19). For the
+ * view pair (view1, view2) of the batch, F = K2^-T [t]_x R K1^-1 with R =
+ * R2 R1^T, t = t2 - R t1 from the cameras in device memory (a relative
+ * translation shorter than 1e-6 has no baseline: F = 0 and every distance is
+ * NaN). Match j of frame-1 pixel (p1[j], p1[m + j]) and frame-2 pixel
+ * (p2[j], p2[m + j]) has the epipolar distance d[j] = |p2^T F p1| / |(a, b)|,
+ * (a, b, c) = F p1 (Eq. (18)), computed in double and stored as float32
+ * (NaN as the positive quiet NaN, bits 0x7FC00000). Candidate i is Gaussian
+ * ids[i] (an index into the packed Gaussians of `views`) with the matches
+ * seg[i] .. seg[i + 1] - 1; dbar[i] is their lower median (Eq. (19)), taken
+ * over the float32 bit patterns (NaN orders above +inf; NaN when there are
+ * none), and state[i] one of GS_EPI_*: RESTORED when mp[ids[i]] > tau (MP
+ * suppresses it) and dbar[i] < eps (1 px in Sec. V-A), KEPT when suppressed
+ * but not consistent, NOT_SUPPRESSED when mp <= tau, NO_MATCHES, or INVALID
+ * (id outside [0, n_gaussians), a match range outside [0, m], or 2^31 matches
+ * or more). d is written for the matches of valid candidates only; the rest
+ * of d is left as it was. Every decision reads mp as it was before the call; then mp of
+ * each restored candidate is set to mp_restore. p1, p2 [2][m], ids [k],
+ * seg [k + 1], d [m], dbar [k], state [k] (outputs), mp [n_gaussians]
+ * (in/out). No workspace. */
+typedef struct gs_epi_params {
+  float eps;        /* restore when dbar < eps pixels */
+  float tau;        /* MP suppresses a Gaussian when mp > tau */
+  float mp_restore; /* the MP a restored Gaussian gets (0: fully static) */
+} gs_epi_params;
+enum { GS_EPI_KEPT = 0, GS_EPI_RESTORED = 1, GS_EPI_NOT_SUPPRESSED = 2, GS_EPI_NO_MATCHES = 3, GS_EPI_INVALID = 4 };
+gs_status gs_epipolar_verify(gs_ctx* ctx, const gs_views* views, int32_t view1, int32_t view2, const float* p1,
+                             const float* p2, int64_t m, const int32_t* ids, const int64_t* seg, int64_t k,
+                             const gs_epi_params* params /*[host]*/, float* d, float* dbar, uint8_t* state,
+                             float* mp, void* stream);
+
 /* ---------------------------------------------------------------- pruning
  * The mapping window prunes Gaussians whose MP after gs_mp_update exceeds a
  * threshold (the config-3 option `prune_above` flags them; not in the paper,

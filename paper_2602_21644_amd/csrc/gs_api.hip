@@ -565,6 +565,23 @@ gs_status gs_edge_warp(gs_ctx* ctx, const gs_views* views, const gs_image* img, 
                           (hipStream_t)stream);
 }
 
+gs_status gs_epipolar_verify(gs_ctx* ctx, const gs_views* views, int32_t view1, int32_t view2, const float* p1,
+                             const float* p2, int64_t m, const int32_t* ids, const int64_t* seg, int64_t k,
+                             const gs_epi_params* prm, float* d, float* dbar, uint8_t* state, float* mp,
+                             void* stream) {
+  if (!ctx || !prm || m < 0 || k < 0) return gs_fail(ctx, GS_E_ARG, "bad argument");
+  ViewTab tab;
+  GS_TRY(make_tab(ctx, views, tab));
+  if (view1 < 0 || view1 >= tab.nv || view2 < 0 || view2 >= tab.nv || view1 == view2)
+    return gs_fail(ctx, GS_E_ARG, "views (%d, %d) invalid", view1, view2);
+  if (m > 0 && (!p1 || !p2 || !d)) return gs_fail(ctx, GS_E_ARG, "match arrays are NULL");
+  if (k > 0 && (!ids || !seg || !dbar || !state || (tab.ng > 0 && !mp)))
+    return gs_fail(ctx, GS_E_ARG, "candidate arrays are NULL");
+  if (!(prm->eps >= 0.f) || prm->tau != prm->tau) return gs_fail(ctx, GS_E_ARG, "eps >= 0 and tau not NaN");
+  return launch_epipolar(ctx, views->cams_dev, view1, view2, p1, p2, m, ids, seg, k, tab.ng, prm->eps, prm->tau,
+                         prm->mp_restore, d, dbar, state, mp, (hipStream_t)stream);
+}
+
 gs_status gs_compact(gs_ctx* ctx, const uint8_t* drop, int64_t n, int32_t n_planes, const float* const* src,
                      float* const* dst, const int64_t* seg_begin, int32_t n_seg, int64_t* seg_out, int64_t* n_out,
                      void* ws, size_t ws_bytes, void* stream) {

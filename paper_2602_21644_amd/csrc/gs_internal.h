@@ -284,6 +284,10 @@ size_t mp_reg_ws_bytes(int64_t n);
 gs_status launch_mp_reg(gs_ctx*, int64_t n, const float* mean, const float* prev, const float* mp, const float* T,
                         float lam, float* loss, float* dmean, double* part, hipStream_t);
 size_t edge_warp_ws_bytes(const ViewTab&, int32_t n_pairs);
+gs_status launch_epipolar(gs_ctx*, const gs_camera* cams, int v1, int v2, const float* p1, const float* p2,
+                          int64_t m, const int32_t* ids, const int64_t* seg, int64_t K, int64_t n, float eps,
+                          float tau, float mp_restore, float* d, float* dbar, uint8_t* state, float* mp,
+                          hipStream_t s);
 gs_status launch_edge_warp(gs_ctx*, const ViewTab&, const gs_camera*, const gs_image*, const gs_target*,
                            const gs_edge_pair*, int32_t, const gs_edge_params*, float* loss, float* ddepth,
                            float* dpose, double* part, hipStream_t);

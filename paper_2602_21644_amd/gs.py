@@ -122,6 +122,13 @@ class EdgeParams(ctypes.Structure):
     _fields_ = [("lambda_", c_float), ("delta", c_float), ("edge_thresh", c_float), ("eps_A", c_float)]
 
 
+class EpiParams(ctypes.Structure):
+    _fields_ = [("eps", c_float), ("tau", c_float), ("mp_restore", c_float)]
+
+
+GS_EPI_KEPT, GS_EPI_RESTORED, GS_EPI_NOT_SUPPRESSED, GS_EPI_NO_MATCHES, GS_EPI_INVALID = 0, 1, 2, 3, 4
+
+
 class MLP(ctypes.Structure):
     _fields_ = [(k, c_void_p) for k in ("master", "w_bf16", "adam_m", "adam_v")]
 
@@ -173,6 +180,8 @@ def lib():
             "gs_mp_regularizer": ([P, c_int64, P, P, P, POINTER(c_float), c_float, P, P, P, c_size_t, P], c_int32),
             "gs_edge_warp": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(EdgePair), c_int32,
                               POINTER(EdgeParams), P, P, P, P, c_size_t, P], c_int32),
+            "gs_epipolar_verify": ([P, POINTER(Views), c_int32, c_int32, P, P, c_int64, P, P, c_int64,
+                                    POINTER(EpiParams), P, P, P, P, P], c_int32),
             "gs_compact": ([P, P, c_int64, c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int64), c_int32,
                             P, P, P, c_size_t, P], c_int32),
             "gs_mlp_features": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(MPFrame), P, P],
@@ -197,7 +206,7 @@ EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_fwd_loss",
             "gs_render_fwd_loss_static",
             "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_compact", "gs_mp_regularizer", "gs_edge_warp",
-            "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
+            "gs_epipolar_verify", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
             "gs_adam_step", "gs_pose_update")
 
 
@@ -338,6 +347,20 @@ def gs_edge_warp(ctx, views, img, tgt, pairs, loss, ddepth, dpose, ws, lam=300.0
     ctx.check(lib().gs_edge_warp(ctx.h, ctypes.byref(views), ctypes.byref(img), ctypes.byref(tgt), arr, len(pairs),
                                  ctypes.byref(prm), ptr(loss), ptr(ddepth), ptr(dpose), ptr(ws),
                                  ws.numel() * ws.element_size(), _stream(stream)), "gs_edge_warp")
+
+
+def gs_epipolar_verify(ctx, views, view1, view2, p1, p2, ids, seg, mp, d, dbar, state, eps=1.0, tau=0.5,
+                       mp_restore=0.0, stream=None):
+    """Epipolar verification and static recovery (Eq. (18)-(19)) of candidate
+    Gaussians ids (int32 [K]) with matches seg[k] .. seg[k + 1] (int64 [K + 1])
+    of pixels p1, p2 (float32 [2, m]) between views view1 and view2: writes the
+    distances d [m], the medians dbar [K] and the states state (uint8 [K],
+    GS_EPI_*), and sets mp (in/out) of restored candidates to mp_restore."""
+    m = int(p1.shape[-1]) if p1.numel() else 0
+    prm = EpiParams(float(eps), float(tau), float(mp_restore))
+    ctx.check(lib().gs_epipolar_verify(ctx.h, ctypes.byref(views), int(view1), int(view2), ptr(p1), ptr(p2), m,
+                                       ptr(ids), ptr(seg), int(ids.numel()), ctypes.byref(prm), ptr(d), ptr(dbar),
+                                       ptr(state), ptr(mp), _stream(stream)), "gs_epipolar_verify")
 
 
 def gs_compact(ctx, drop, src, dst, n_out, ws, seg_begin=None, seg_out=None, stream=None):

@@ -329,3 +329,53 @@ def mlp_inputs(seed, P, hidden=32, n_in=8):
     W3 = (rng.normal(0, 1, (1, hidden)) * np.sqrt(1.0 / hidden)).astype(np.float32)
     b3 = np.zeros(1, np.float32)
     return x, label, dict(W1=W1, b1=b1, W2=W2, b2=b2, W3=W3, b3=b3)
+
+
+# ---------------------------------------------------------------- epipolar matches
+def _pixels(cam, X):
+    """Pinhole pixels of world points X [3][m] (any depth sign)."""
+    T = np.asarray(cam["T_cw"], dtype=np.float64)
+    Xc = T[:, :3] @ X + T[:, 3:4]
+    return np.stack([cam["fx"] * Xc[0] / Xc[2] + cam["cx"], cam["fy"] * Xc[1] / Xc[2] + cam["cy"]])
+
+
+def epipolar_case(seed, n, width, height, n_cand, per=(0, 24), noise_px=0.3, outlier_frac=0.1, spacing=5,
+                  n_boxes=3, box_frac=0.05, suppressed_frac=0.6):
+    """Feature matches of candidate Gaussians between two keyframes `spacing`
+    frames apart (1 cm / 0.5 degree per frame), in a moving-box scene whose
+    boxes move U[0.05, 0.20] m between them. Candidates: a third box
+    Gaussians, two thirds static ones; MP is U[0.6, 1] for box candidates and
+    for a `suppressed_frac` share of the static candidates (those MP wrongly
+    suppresses), U[0, 0.4] otherwise. Each candidate has k ~ U{per[0] ..
+    per[1]} matches: points drawn around its mean (normal, its largest scale)
+    carried by the Gaussian's own motion and seen by both pinholes; frame-2
+    pixels get N(0, noise_px^2) noise and a share `outlier_frac` of them is
+    replaced by uniform pixels. Returns dict(cam1, cam2, ids int32 [K], seg
+    int64 [K+1], p1, p2 float32 [2][m], mp float32 [n], dynamic bool [n])."""
+    rng = rng_for(seed)
+    seq = box_sequence(seed, n, width, height, 1, n_boxes=n_boxes, box_frac=box_frac, spacing=spacing)
+    cam2 = seq["cams"][0]
+    cam1 = camera(width, height)
+    g0, g1, dyn = seq["map"], seq["obs"][0], seq["dynamic"]
+    nb = int(min(n_cand // 3, dyn.sum()))
+    box_ids = rng.choice(np.nonzero(dyn)[0], size=nb, replace=False)
+    st_ids = rng.choice(np.nonzero(~dyn)[0], size=n_cand - nb, replace=False)
+    ids = rng.permutation(np.concatenate([box_ids, st_ids])).astype(np.int32)
+    mp = rng.uniform(0.0, 0.4, n).astype(np.float32)
+    hi = dyn.copy()
+    hi[st_ids[rng.random(st_ids.size) < suppressed_frac]] = True
+    mp[hi] = rng.uniform(0.6, 1.0, int(hi.sum())).astype(np.float32)
+    counts = rng.integers(per[0], per[1] + 1, size=ids.size)
+    seg = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    owner = np.repeat(ids.astype(np.int64), counts)
+    m = owner.size
+    sig = np.exp(g0["log_scale"][:, owner].astype(np.float64).max(axis=0))
+    X0 = g0["mean"][:, owner].astype(np.float64) + rng.normal(size=(3, m)) * sig
+    X1 = X0 + (g1["mean"][:, owner].astype(np.float64) - g0["mean"][:, owner].astype(np.float64))
+    p1 = _pixels(cam1, X0)
+    p2 = _pixels(cam2, X1) + rng.normal(0.0, noise_px, size=(2, m))
+    out = rng.random(m) < outlier_frac
+    p2[0, out] = rng.uniform(0, width, int(out.sum()))
+    p2[1, out] = rng.uniform(0, height, int(out.sum()))
+    return dict(cam1=cam1, cam2=cam2, ids=ids, seg=seg, p1=p1.astype(np.float32), p2=p2.astype(np.float32),
+                mp=mp, dynamic=dyn)
