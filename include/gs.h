@@ -469,6 +469,36 @@ gs_status gs_epipolar_verify(gs_ctx* ctx, const gs_views* views, int32_t view1, 
                              const gs_epi_params* params /*[host]*/, float* d, float* dbar, uint8_t* state,
                              float* mp, void* stream);
 
+/* ---------------------------------------------------------------- semantic-on-demand scheduling
+ * Sec. IV-B, Eq. (13)-(17): whether to refresh the instance prior at a frame.
+ * Host logic only (no device work, no stream): the inputs are the frame
+ * uncertainty U_bar (Eq. (13), stats[0] of the most recent gs_mp_update) and
+ * the candidates of the frame's epipolar verification (dbar and state of
+ * gs_epipolar_verify, copied to the host). The verified correspondences are
+ * the candidates MP labels static (state GS_EPI_NOT_SUPPRESSED) with a finite
+ * median; e_bar is the mean of their medians (0 when there are none),
+ * R = clip(e_bar / e_ref, 0, 1) (Eq. (14)), S = w_u U_bar + w_r R (Eq. (15)),
+ * and the prior is refreshed when S > theta or dt >= n_max (Eq. (16)), dt
+ * being the frames since the last refresh including this one. The caller
+ * passes refresh as gs_mp_frame.seg_updated of this frame's update (Eq.
+ * (17)) and reuses the last refreshed instance masks otherwise. GS_E_ARG for
+ * negative weights, weights that do not sum to 1 (within 1e-6), e_ref <= 0,
+ * n_max < 1. */
+typedef struct gs_sched_params {
+  float w_u, w_r;  /* Eq. (15); 0.5 each */
+  float theta;     /* Eq. (16); 0.5 */
+  float e_ref;     /* Eq. (14) in pixels; 2 */
+  int32_t n_max;   /* Eq. (16); 10 */
+} gs_sched_params;
+typedef struct gs_sched_state {
+  int32_t dt;        /* frames since the last refresh; start at n_max so the first frame refreshes */
+  int32_t n_refresh; /* refreshes so far */
+  float S, R, e_bar; /* the last decision's score and inputs */
+} gs_sched_state;
+gs_status gs_sched_decide(const gs_sched_params* params, gs_sched_state* state /*[host] in/out*/, float U_bar,
+                          const float* dbar /*[host] k*/, const uint8_t* epi_state /*[host] k*/, int64_t k,
+                          int32_t* refresh /*[host] out*/);
+
 /* ---------------------------------------------------------------- pruning
  * The mapping window prunes Gaussians whose MP after gs_mp_update exceeds a
  * threshold (the config-3 option `prune_above` flags them; not in the paper,

@@ -1,5 +1,6 @@
 // Host side of the C ABI: argument validation, batch tables, workspace
 // layout and kernel dispatch. Nothing here allocates device memory.
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -580,6 +581,41 @@ gs_status gs_epipolar_verify(gs_ctx* ctx, const gs_views* views, int32_t view1, 
   if (!(prm->eps >= 0.f) || prm->tau != prm->tau) return gs_fail(ctx, GS_E_ARG, "eps >= 0 and tau not NaN");
   return launch_epipolar(ctx, views->cams_dev, view1, view2, p1, p2, m, ids, seg, k, tab.ng, prm->eps, prm->tau,
                          prm->mp_restore, d, dbar, state, mp, (hipStream_t)stream);
+}
+
+gs_status gs_sched_decide(const gs_sched_params* p, gs_sched_state* st, float U_bar, const float* dbar,
+                          const uint8_t* epi_state, int64_t k, int32_t* refresh) {
+  if (!p || !st || !refresh || k < 0 || (k > 0 && (!dbar || !epi_state))) return GS_E_ARG;
+  if (!(p->w_u >= 0.f) || !(p->w_r >= 0.f) || !(fabs((double)p->w_u + p->w_r - 1.0) <= 1e-6) || !(p->e_ref > 0.f) ||
+      p->n_max < 1)
+    return GS_E_ARG;
+  // e_bar: mean of the finite medians of the candidates MP labels static,
+  // summed in candidate order in double
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < k; ++i)
+    if (epi_state[i] == GS_EPI_NOT_SUPPRESSED && std::isfinite(dbar[i])) {
+      sum += dbar[i];
+      ++cnt;
+    }
+  const float e_bar = cnt ? (float)(sum / (double)cnt) : 0.f;
+  float R = e_bar / p->e_ref;
+  R = R < 0.f ? 0.f : (R > 1.f ? 1.f : R);
+  const float U = U_bar != U_bar ? 0.f : U_bar;
+  const float S = p->w_u * U + p->w_r * R;
+  const int32_t dt = st->dt < 0 ? 0 : st->dt;
+  const bool go = S > p->theta || dt >= p->n_max;
+  st->S = S;
+  st->R = R;
+  st->e_bar = e_bar;
+  if (go) {
+    st->dt = 1;
+    st->n_refresh += 1;
+  } else {
+    st->dt = dt + 1;
+  }
+  *refresh = go ? 1 : 0;
+  return GS_OK;
 }
 
 gs_status gs_compact(gs_ctx* ctx, const uint8_t* drop, int64_t n, int32_t n_planes, const float* const* src,

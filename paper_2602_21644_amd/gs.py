@@ -129,6 +129,17 @@ class EpiParams(ctypes.Structure):
 GS_EPI_KEPT, GS_EPI_RESTORED, GS_EPI_NOT_SUPPRESSED, GS_EPI_NO_MATCHES, GS_EPI_INVALID = 0, 1, 2, 3, 4
 
 
+class SchedParams(ctypes.Structure):
+    _fields_ = [("w_u", c_float), ("w_r", c_float), ("theta", c_float), ("e_ref", c_float), ("n_max", c_int32)]
+
+
+class SchedState(ctypes.Structure):
+    _fields_ = [("dt", c_int32), ("n_refresh", c_int32), ("S", c_float), ("R", c_float), ("e_bar", c_float)]
+
+
+SCHED_DEFAULTS = dict(w_u=0.5, w_r=0.5, theta=0.5, e_ref=2.0, n_max=10)
+
+
 class MLP(ctypes.Structure):
     _fields_ = [(k, c_void_p) for k in ("master", "w_bf16", "adam_m", "adam_v")]
 
@@ -182,6 +193,8 @@ def lib():
                               POINTER(EdgeParams), P, P, P, P, c_size_t, P], c_int32),
             "gs_epipolar_verify": ([P, POINTER(Views), c_int32, c_int32, P, P, c_int64, P, P, c_int64,
                                     POINTER(EpiParams), P, P, P, P, P], c_int32),
+            "gs_sched_decide": ([POINTER(SchedParams), POINTER(SchedState), c_float, P, P, c_int64,
+                                 POINTER(c_int32)], c_int32),
             "gs_compact": ([P, P, c_int64, c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int64), c_int32,
                             P, P, P, c_size_t, P], c_int32),
             "gs_mlp_features": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(MPFrame), P, P],
@@ -206,7 +219,7 @@ EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_fwd_loss",
             "gs_render_fwd_loss_static",
             "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_compact", "gs_mp_regularizer", "gs_edge_warp",
-            "gs_epipolar_verify", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
+            "gs_epipolar_verify", "gs_sched_decide", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
             "gs_adam_step", "gs_pose_update")
 
 
@@ -361,6 +374,38 @@ def gs_epipolar_verify(ctx, views, view1, view2, p1, p2, ids, seg, mp, d, dbar, 
     ctx.check(lib().gs_epipolar_verify(ctx.h, ctypes.byref(views), int(view1), int(view2), ptr(p1), ptr(p2), m,
                                        ptr(ids), ptr(seg), int(ids.numel()), ctypes.byref(prm), ptr(d), ptr(dbar),
                                        ptr(state), ptr(mp), _stream(stream)), "gs_epipolar_verify")
+
+
+def gs_sched_decide(params, state, U_bar, dbar=None, epi_state=None):
+    """Eq. (14)-(16) on the host: whether to refresh the instance prior at this
+    frame, from the latest frame uncertainty U_bar and the frame's epipolar
+    candidates (numpy dbar float32 [K], epi_state uint8 [K]); updates
+    `state` (SchedState) in place and returns the decision."""
+    import numpy as np
+    if dbar is None:
+        dbar = np.zeros(0, np.float32)
+        epi_state = np.zeros(0, np.uint8)
+    dbar = np.ascontiguousarray(dbar, dtype=np.float32)
+    epi_state = np.ascontiguousarray(epi_state, dtype=np.uint8)
+    if dbar.size != epi_state.size:
+        raise ValueError("dbar and epi_state differ in length")
+    out = c_int32(0)
+    st = lib().gs_sched_decide(ctypes.byref(params), ctypes.byref(state), float(U_bar),
+                               dbar.ctypes.data_as(c_void_p), epi_state.ctypes.data_as(c_void_p), int(dbar.size),
+                               ctypes.byref(out))
+    if st != 0:
+        raise GSError(st, "gs_sched_decide: invalid parameters")
+    return bool(out.value)
+
+
+def sched_params(**kw):
+    p = dict(SCHED_DEFAULTS)
+    p.update(kw)
+    return SchedParams(float(p["w_u"]), float(p["w_r"]), float(p["theta"]), float(p["e_ref"]), int(p["n_max"]))
+
+
+def sched_state(params):
+    return SchedState(int(params.n_max), 0, 0.0, 0.0, 0.0)
 
 
 def gs_compact(ctx, drop, src, dst, n_out, ws, seg_begin=None, seg_out=None, stream=None):

@@ -365,17 +365,107 @@ def epipolar_case(seed, n, width, height, n_cand, per=(0, 24), noise_px=0.3, out
     hi = dyn.copy()
     hi[st_ids[rng.random(st_ids.size) < suppressed_frac]] = True
     mp[hi] = rng.uniform(0.6, 1.0, int(hi.sum())).astype(np.float32)
-    counts = rng.integers(per[0], per[1] + 1, size=ids.size)
+    p1, p2, seg = frame_matches(rng, g0, g1, cam1, cam2, ids, per, noise_px, outlier_frac)
+    return dict(cam1=cam1, cam2=cam2, ids=ids, seg=seg, p1=p1, p2=p2, mp=mp, dynamic=dyn)
+
+
+def frame_matches(rng, g_a, g_b, cam_a, cam_b, ids, per=(4, 16), noise_px=0.3, outlier_frac=0.1):
+    """Feature matches of Gaussians `ids` between frames a and b: k ~ U{per[0]
+    .. per[1]} points each, drawn around the Gaussian's mean in g_a (normal,
+    its largest scale) and carried by its motion to g_b, seen by both
+    pinholes; frame-b pixels get N(0, noise_px^2) noise and a share
+    `outlier_frac` is replaced by uniform pixels. Returns p1, p2 float32
+    [2][m] and the segment offsets int64 [K + 1]."""
+    counts = rng.integers(per[0], per[1] + 1, size=len(ids))
     seg = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
-    owner = np.repeat(ids.astype(np.int64), counts)
+    owner = np.repeat(np.asarray(ids, np.int64), counts)
     m = owner.size
-    sig = np.exp(g0["log_scale"][:, owner].astype(np.float64).max(axis=0))
-    X0 = g0["mean"][:, owner].astype(np.float64) + rng.normal(size=(3, m)) * sig
-    X1 = X0 + (g1["mean"][:, owner].astype(np.float64) - g0["mean"][:, owner].astype(np.float64))
-    p1 = _pixels(cam1, X0)
-    p2 = _pixels(cam2, X1) + rng.normal(0.0, noise_px, size=(2, m))
+    sig = np.exp(g_a["log_scale"][:, owner].astype(np.float64).max(axis=0))
+    Xa = g_a["mean"][:, owner].astype(np.float64) + rng.normal(size=(3, m)) * sig
+    Xb = Xa + (g_b["mean"][:, owner].astype(np.float64) - g_a["mean"][:, owner].astype(np.float64))
+    p1 = _pixels(cam_a, Xa)
+    p2 = _pixels(cam_b, Xb) + rng.normal(0.0, noise_px, size=(2, m))
     out = rng.random(m) < outlier_frac
-    p2[0, out] = rng.uniform(0, width, int(out.sum()))
-    p2[1, out] = rng.uniform(0, height, int(out.sum()))
-    return dict(cam1=cam1, cam2=cam2, ids=ids, seg=seg, p1=p1.astype(np.float32), p2=p2.astype(np.float32),
-                mp=mp, dynamic=dyn)
+    p2[0, out] = rng.uniform(0, cam_b["width"], int(out.sum()))
+    p2[1, out] = rng.uniform(0, cam_b["height"], int(out.sum()))
+    return p1.astype(np.float32), p2.astype(np.float32), seg
+
+
+def box_masks(cam, g, slices, margin_px=2):
+    """Instance-id map of a synthetic detector: box k is the axis-aligned
+    rectangle of its Gaussians' pixels (those in front of the camera), grown
+    by `margin_px` and clipped to the image; later boxes overwrite earlier
+    ones. int32 [H * W]."""
+    W, H = cam["width"], cam["height"]
+    out = np.zeros((H, W), np.int32)
+    T = np.asarray(cam["T_cw"], dtype=np.float64)
+    for k, sl in enumerate(slices, start=1):
+        X = g["mean"][:, sl].astype(np.float64)
+        Xc = T[:, :3] @ X + T[:, 3:4]
+        ok = Xc[2] > cam["z_near"]
+        if not ok.any():
+            continue
+        u = cam["fx"] * Xc[0, ok] / Xc[2, ok] + cam["cx"]
+        v = cam["fy"] * Xc[1, ok] / Xc[2, ok] + cam["cy"]
+        x0, x1 = int(np.floor(u.min())) - margin_px, int(np.ceil(u.max())) + margin_px
+        y0, y1 = int(np.floor(v.min())) - margin_px, int(np.ceil(v.max())) + margin_px
+        x0, y0, x1, y1 = max(x0, 0), max(y0, 0), min(x1, W - 1), min(y1, H - 1)
+        if x0 <= x1 and y0 <= y1:
+            out[y0:y1 + 1, x0:x1 + 1] = k
+    return out.reshape(-1)
+
+
+def mp_sequence_inputs(seed, n, width, height, frames, n_inst=3, speed_px=3.0, k_cand=400, burst=(4, 5, 11)):
+    """A sequence of MP-update inputs: one background depth/colour, `n_inst`
+    rectangular objects that move `speed_px` pixels per frame (the observed
+    depth differs from the render inside their current rectangles, which are
+    also the frame's fresh instance masks), projected means that drift by a
+    small camera motion, and per frame the median epipolar distances and
+    states of `k_cand` verification candidates (distances |N(0, 0.3^2)| px,
+    |N(0, 6^2)| px at the frames in `burst`, a tenth without matches). The
+    first frame carries the starting MP state."""
+    rng = rng_for(seed)
+    P = width * height
+    yy, xx = np.mgrid[0:height, 0:width]
+    depth = (1.0 + 2.0 * rng.random()) + 0.3 * np.sin(xx / 7.0 + rng.random() * 6) * np.cos(yy / 5.0)
+    color = rng.random((3, height, width))
+    boxes = []
+    for _ in range(n_inst):
+        w = int(rng.integers(max(2, width // 8), max(3, width // 3)))
+        h = int(rng.integers(max(2, height // 8), max(3, height // 3)))
+        boxes.append(dict(x=float(rng.uniform(0, width - w)), y=float(rng.uniform(0, height - h)), w=w, h=h,
+                          vx=float(rng.choice([-1, 1]) * speed_px), vy=float(rng.uniform(-1, 1) * speed_px),
+                          dz=float(rng.uniform(0.05, 0.2))))
+    prior = np.concatenate([[0.05], rng.uniform(0.6, 0.95, size=n_inst)]).astype(np.float32)
+    conf = np.concatenate([[0.1], rng.uniform(0.5, 0.95, size=n_inst)]).astype(np.float32)
+    mean0 = np.stack([rng.uniform(-3, width + 3, size=n), rng.uniform(-3, height + 3, size=n)])
+    culled = rng.random(n) < 0.05
+    mp0 = rng.random(n).astype(np.float32)
+    drift = rng.normal(0, 0.5, size=2)
+    out = []
+    f = np.float32
+    for t in range(frames):
+        r = depth + rng.normal(0, 0.01, size=depth.shape)
+        obs = r + rng.normal(0, 0.01, size=depth.shape)
+        inst = np.zeros((height, width), np.int32)
+        for k, b in enumerate(boxes, start=1):
+            x0 = int(np.clip(round(b["x"] + b["vx"] * t), 0, width - b["w"]))
+            y0 = int(np.clip(round(b["y"] + b["vy"] * t), 0, height - b["h"]))
+            inst[y0:y0 + b["h"], x0:x0 + b["w"]] = k
+            obs[y0:y0 + b["h"], x0:x0 + b["w"]] += b["dz"]
+        obs[rng.random(depth.shape) < 0.05] = 0.0
+        tcolor = np.clip(color + rng.normal(0, 0.05, size=color.shape), 0, 1)
+        sd = 6.0 if t in burst else 0.3
+        dbar = np.abs(rng.normal(0, sd, size=k_cand)).astype(f)
+        est = rng.choice([2, 2, 2, 2, 2, 2, 0, 1, 3, 2], size=k_cand).astype(np.uint8)
+        dbar[est == 3] = np.nan
+        out.append(dict(width=width, height=height,
+                        depth=np.ascontiguousarray(r.reshape(P), f),
+                        color=np.ascontiguousarray(color.reshape(3, P), f),
+                        target_depth=np.ascontiguousarray(obs.reshape(P), f),
+                        target_color=np.ascontiguousarray(tcolor.reshape(3, P), f),
+                        instance_id=np.ascontiguousarray(inst.reshape(P), np.int32),
+                        inst_prior=prior, inst_conf=conf,
+                        mean2d=np.ascontiguousarray(mean0 + drift[:, None] * t, f),
+                        culled=culled, mp=mp0, dbar=dbar, epi_state=est))
+    return out
