@@ -6,13 +6,16 @@ volume; 5% on three moving boxes), one 640x480 view, full gradients to every
 Gaussian parameter and the pose twist. The target RGB-D frame is rendered by
 the same library at a camera 0.5 degree / 1 cm away with the boxes moved.
 
-A step is gs_project -> gs_bin_sort -> gs_render_fwd -> gs_loss ->
-gs_render_bwd (one optimisation iteration; the per-frame MP update is timed
-beside it). The prefix rank is the smallest exact one and the launch knobs
-are autotuned first. The timed region replays a hip graph of the step K
-times (inputs resident in HBM); a second timed region runs K eager steps with
-every kernel bracketed by HIP events, which gives per-kernel durations for
-the roofline entry. The oracle is timed on the host on a pixel sample.
+A step is gs_project -> gs_bin_sort -> gs_render_fwd_loss (the MP-weighted
+loss fused into the forward) -> gs_render_bwd: one optimisation iteration
+(the per-frame MP update is timed beside it). The prefix rank is the smallest
+exact one and the launch knobs are autotuned first. The timed region replays
+a hip graph of the step K times (inputs resident in HBM); a second timed
+region runs K eager steps with every kernel bracketed by HIP events, which
+gives per-kernel durations for the roofline entries: `roofline` for the
+kernel that takes the most time, `roofline_iteration` for the whole step's
+algorithmic HBM bytes against the HBM peak. The oracle is timed on the host
+over whole iterations (every pixel, every Gaussian) for about 10 seconds.
 
 Prints one JSON line.
 """
@@ -102,9 +105,13 @@ def kernel_bytes(name, st):
     if name.startswith("loss_kernel"):
         return P * 68
     if name.startswith("render_bwd_kernel"):
-        return st["loaded_bwd"] * 52 + P * 32 + st["touched"] * 40
+        # list entries and pixel state read, the 2D adjoint of touched records
+        # accumulated, and the dense gradient planes cleared (14 floats each)
+        return st["loaded_bwd"] * 52 + P * 32 + st["touched"] * 40 + N * 56
     if name.startswith("bwd_project_kernel"):
-        return st["touched"] * 124 + N * (56 + 1)
+        # per listed Gaussian: parameters, list entry and flag, the 2D adjoint
+        # copies read and cleared, the gradients written
+        return st["touched"] * (44 + 8 + 80 * st.get("copies", 1) + 56)
     return None
 
 
@@ -211,7 +218,7 @@ def main():
     st = dict(n=a.n, instances=n_inst, pixels=P, tiles=views.tile_count, records=views.rec_count,
               nlim=views.rec_count, cm=views.tile_count * ((views.rec_count + chunk - 1) // chunk),
               loaded_fwd=loaded_fwd, loaded_bwd=loaded_bwd, touched=touched, selected=selected, pairs=pairs,
-              fused_loss=True)
+              fused_loss=True, copies=ctx.get_param("bwd_copies"))
     log(f"[bench] instances {n_inst}, touched Gaussians {touched}, entries loaded fwd {loaded_fwd}, "
         f"binning LDS limit {ctx.get_param('lds_limit')}")
 
@@ -327,8 +334,9 @@ def main():
                    "composited_pairs": pairs, "parallelism": "single-gpu",
                    "timed": "hip graph replay" if graph is not None else "eager"},
         "roofline": roof,
-        "iteration_bytes_model": int(total_bytes),
-        "iteration_hbm_frac": round(iter_frac, 4),
+        "roofline_iteration": {"bound": "hbm", "achieved": round(total_bytes / (ms * 1e-3) / 1e9, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(iter_frac, 4),
+                               "algorithmic_bytes": int(total_bytes)},
         "eager_ms_per_step": round(eager_ms, 4),
         "kernel_us_per_step": {k: round(1000 * v, 2) for k, v in sorted(per_step.items(), key=lambda x: -x[1])},
         "step_ms_p10_p50_p90": [round(p10, 4), round(p50, 4), round(p90, 4)],
@@ -596,65 +604,25 @@ def uneven_batch(ctx):
 
 
 def learned_mp(ctx, a, g, cam, tc, td):
-    """The surrogate trained on plain-cue M_p of moving-box sequences; MP error
-    of plain and learned forms on held-out sequences, and the per-frame time
-    of the MP source at the headline size (plain: gs_mp_update; learned:
-    features + network + gs_mp_update with the network's M_p)."""
-    import torch
-    from paper_2602_21644_amd import gs, mp_learn, synth
-
-    def seq(seed, frames):
-        return synth.box_sequence(seed, 20000, 96, 72, frames, n_boxes=3, box_frac=0.2, zmin=3.0, zmax=6.0)
-
-    sur = mp_learn.MPSurrogate(ctx, seed=0)
-    for seed in (1000, 1001, 1002, 1003):
-        mp_learn.run_sequence(ctx, seq(seed, 12), surrogate=sur, train=True, steps_per_frame=8)
-    errs = []
-    for seed in (5000, 5001):
-        sq = seq(seed, 10)
-        mp_p, obs_p, _ = mp_learn.run_sequence(ctx, sq)
-        mp_l, obs_l, _ = mp_learn.run_sequence(ctx, sq, surrogate=sur)
-        ob = obs_p & obs_l
-        errs.append((mp_learn.mp_error(mp_p, sq["dynamic"], ob), mp_learn.mp_error(mp_l, sq["dynamic"], ob)))
-    e_plain = float(np.mean([e[0] for e in errs]))
-    e_learned = float(np.mean([e[1] for e in errs]))
-    # per-frame time at 1M Gaussians, 640x480
-    gd = gs.to_device(g)
-    mpf = mp_learn.MPFrame(ctx, gd, cam)
-    inst = torch.zeros(a.width * a.height, dtype=torch.int32, device="cuda")
-    prior, conf = mp_learn.instance_tables(0)
-    mpf.views.set_pose(0, cam["T_cw"])
-    mpf.pipe.forward(mpf.gst)
-    tgt = gs.Target(gs.ptr(tc), gs.ptr(td))
-
-    def plain():
-        fr = mpf._frame(inst, prior, conf, True)
-        gs.gs_mp_update(ctx, mpf.views.s, mpf.pipe.proj, mpf.pipe.img, tgt, fr, mpf.params, gd["mp"], mpf.out, mpf.ws)
-
-    def learned():
-        fr = mpf._frame(inst, prior, conf, True)
-        gs.gs_mlp_features(ctx, mpf.views.s, mpf.pipe.img, tgt, fr, mpf.x)
-        sur.predict(mpf.x, mpf.y)
-        fr = mpf._frame(inst, prior, conf, True, mpf.y)
-        gs.gs_mp_update(ctx, mpf.views.s, mpf.pipe.proj, mpf.pipe.img, tgt, fr, mpf.params, gd["mp"], mpf.out, mpf.ws)
-
-    t = {}
-    for name, fn in (("plain", plain), ("learned", learned)):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        t[name] = e0.elapsed_time(e1) / 10
-    log(f"[bench] MP error plain {e_plain:.4f} learned {e_learned:.4f}; per-frame ms plain {t['plain']:.3f} "
-        f"learned {t['learned']:.3f}")
-    return {"mp_abs_error_plain": round(e_plain, 4), "mp_abs_error_learned": round(e_learned, 4),
-            "equal_accuracy": bool(e_learned <= e_plain + 0.01), "ms_per_frame_plain": round(t["plain"], 4),
-            "ms_per_frame_learned": round(t["learned"], 4),
-            "eval": "2 held-out 10-frame sequences, 20k Gaussians at 96x72; timing at the headline size"}
+    """The learned-MP protocol at the headline size (1M Gaussians, 640x480):
+    the surrogate trained on the plain cue's M_p of 2,000 frames (sequences
+    1000-1019, 100 frames each, 1-5 moving boxes in front of a static layer),
+    then sequences 5000-5004 (100 frames each) tracked and MP-updated at the
+    tracked pose with the plain cue and with the surrogate under its fallback
+    rule. MP abs error, label error, pose error and the MP source's time per
+    frame for both forms."""
+    import time as _t
+    from paper_2602_21644_amd import mp_learn
+    t0 = _t.perf_counter()
+    sur, used, first, last = mp_learn.train_c5(ctx, n=a.n, width=a.width, height=a.height)
+    t_train = _t.perf_counter() - t0
+    res = mp_learn.evaluate_c5(ctx, sur, n=a.n, width=a.width, height=a.height)
+    log(f"[bench] learned MP: trained on {used} frames in {t_train:.1f} s (BCE {first:.4f} -> {last:.4f}); "
+        f"plain {res['plain']}; learned {res['learned']}")
+    return {"protocol": "train 1000-1019 x 100 frames, test 5000-5004 x 100 frames, 1M Gaussians at 640x480, "
+                        "tracking 10 iterations per frame from the previous estimate",
+            "train_frames": used, "train_s": round(t_train, 1), "bce_first_last": [round(first, 4), round(last, 4)],
+            **{f"{k}_{form}": v for form in ("plain", "learned") for k, v in res[form].items()}}
 
 
 def kernel_source_hash(kernel):

@@ -196,6 +196,10 @@ typedef struct gs_pixel_grads {
   float* ddepth; /* [P] */
   float* dmp;    /* [P] or NULL (treated as 0) */
   float* dT;     /* [P] or NULL (treated as 0) */
+  const float* view_weight; /* [V] or NULL, device, read by gs_render_bwd only:
+                               view v's pixel adjoints enter the backward
+                               multiplied by view_weight[v] (the incoming
+                               gradient of its loss); the planes are not changed */
 } gs_pixel_grads;
 
 /* Gradients w.r.t. gs_gaussians fields (same layout) and the pose twists. */
@@ -378,6 +382,12 @@ typedef struct gs_mp_out {
   float* M_p;        /* [P] nullable: fused per-pixel MP (Eq. 6) */
   float* e;          /* [P] nullable: residual cue */
   float* stats;      /* [8]: U_bar, tau, n_obs, n_dyn, n_prune, U_min, U_max, median */
+  float* judge;      /* [2] nullable: with a surrogate M_p (gs_mp_frame.mlp_mp), the
+                        sum of |M_p(surrogate) - M_p(plain cue)| over the pixels
+                        with observed depth, and their count (the plain cue is
+                        still formed, as the surrogate's error judge; the sum
+                        is accumulated with float atomics, so its last bits
+                        vary); 0 and 0 without a surrogate */
 } gs_mp_out;
 
 /* One frame of the temporal MP update for a single view (views->n_views = 1).

@@ -115,8 +115,12 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
 // One wave per region sums the per-wave partials (rows) in a fixed order.
 __global__ __launch_bounds__(MAXR * 64) void mp_region_final_kernel(const double* __restrict__ part, int nrows, int K,
                                                                     float lambda_e, float e_floor, float sigma_g,
-                                                                    MpScal* __restrict__ sc) {
+                                                                    MpScal* __restrict__ sc, float* __restrict__ judge) {
   const int r = threadIdx.x >> 6, lane = __lane_id();
+  if (judge && threadIdx.x == 0) {  // the surrogate judge accumulates in the pixel pass that follows
+    judge[0] = 0.f;
+    judge[1] = 0.f;
+  }
   if (r > K) return;
   double c = 0, s1 = 0, s2 = 0;
   // each lane has kRowUnroll rows' loads in flight before it adds them, in
@@ -161,30 +165,44 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_pixel_kernel(int64_t npix, int K,
                                                             const float* __restrict__ mlp, float sigma_small,
                                                             const MpScal* __restrict__ sc, float* __restrict__ Mp,
                                                             float* __restrict__ e_copy, const float* __restrict__ Dg,
-                                                            float2* __restrict__ pk) {
+                                                            float2* __restrict__ pk, float* __restrict__ judge) {
   const int64_t p = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
-  if (p >= npix) return;
-  const int r = min(max(inst[p], 0), K);
-  const float e = e_in[p];
-  if (e_copy) e_copy[p] = e;
-  if (mlp) {
-    const float m = mlp[p];
+  const bool live = p < npix;
+  float dev = 0.f, cnt = 0.f;
+  if (live) {
+    const int r = min(max(inst[p], 0), K);
+    const float e = e_in[p];
+    if (e_copy) e_copy[p] = e;
+    const float mu = sc->region[r][0], sd = sc->region[r][1], ub = sc->region[r][2], gg = sc->region[r][3];
+    const float et = sd < sigma_small ? mu : e;
+    const float geo = ub > 0.f ? fminf(fmaxf(et / ub, 0.f), 1.f) : 0.f;
+    const float gi = conf[r];
+    const float den = gi + gg;
+    const float Kp = den > 0.f ? gg / den : 0.5f;
+    const float plain = (1.f - Kp) * prior[r] + Kp * geo;
+    const bool seen = Dg[p] > 0.f;
+    float m = plain;
+    if (mlp) {
+      m = mlp[p];
+      if (seen) {
+        dev = fabsf(m - plain);
+        cnt = 1.f;
+      }
+    }
     Mp[p] = m;
-    pk[p] = make_float2(m, Dg[p] > 0.f ? e : -1.f);
-    return;
+    // (M_p, e) packed for the per-Gaussian windows, e = -1 where no depth was
+    // observed (e >= 0 elsewhere): 8 bytes per pixel, so a frame's pixels
+    // stay in one XCD's L2
+    pk[p] = make_float2(m, seen ? e : -1.f);
   }
-  const float mu = sc->region[r][0], sd = sc->region[r][1], ub = sc->region[r][2], gg = sc->region[r][3];
-  const float et = sd < sigma_small ? mu : e;
-  const float geo = ub > 0.f ? fminf(fmaxf(et / ub, 0.f), 1.f) : 0.f;
-  const float gi = conf[r];
-  const float den = gi + gg;
-  const float Kp = den > 0.f ? gg / den : 0.5f;
-  const float m = (1.f - Kp) * prior[r] + Kp * geo;
-  Mp[p] = m;
-  // (M_p, e) packed for the per-Gaussian windows, e = -1 where no depth was
-  // observed (e >= 0 elsewhere): 8 bytes per pixel, so a frame's pixels stay
-  // in one XCD's L2
-  pk[p] = make_float2(m, Dg[p] > 0.f ? e : -1.f);
+  if (judge && mlp) {  // uniform: one atomic pair per wave
+    dev = wave_sum_to_lane63(dev);
+    cnt = wave_sum_to_lane63(cnt);
+    if (__lane_id() == 63 && cnt > 0.f) {
+      atomicAdd(&judge[0], dev);
+      atomicAdd(&judge[1], cnt);
+    }
+  }
 }
 
 struct GaussOut {
@@ -612,11 +630,11 @@ gs_status launch_mp_update(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj,
     GS_LAUNCH(ctx, mp_region_kernel, dim3(nb), dim3(GS_BLOCK), 0, s, P, P, K, img->depth, tgt->depth, img->color,
               tgt->color, fr->instance_id, pp->beta_color, e, part, (int64_t)nb * (GS_BLOCK / 64));
   GS_LAUNCH(ctx, mp_region_final_kernel, dim3(1), dim3(MAXR * 64), 0, s, part, nb * (GS_BLOCK / 64), K,
-            pp->lambda_e, pp->e_floor, pp->sigma_g, sc);
+            pp->lambda_e, pp->e_floor, pp->sigma_g, sc, out->judge);
   if (P > 0)
     GS_LAUNCH(ctx, mp_pixel_kernel, dim3((unsigned)((P + GS_BLOCK - 1) / GS_BLOCK)), dim3(GS_BLOCK), 0, s, P, K,
               e, fr->instance_id, fr->inst_prior, fr->inst_conf, fr->mlp_mp, pp->sigma_small, sc, Mp, out->e,
-              tgt->depth, pk);
+              tgt->depth, pk, out->judge);
   const unsigned gb = (unsigned)((n + GS_BLOCK - 1) / GS_BLOCK);
   if (n > 0)
     GS_LAUNCH(ctx, mp_gauss_kernel, dim3(gb), dim3(GS_BLOCK), 0, s, tab, proj->mean2d, proj->depth_key, pk, mp,

@@ -403,8 +403,8 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) v
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
     const float* __restrict__ imgT, const uint32_t* __restrict__ nlast, const float* __restrict__ dC,
     const float* __restrict__ dD, const float* __restrict__ dM, const float* __restrict__ dT,
-    float* __restrict__ g2d, TouchArgs touch, const uint32_t* __restrict__ order, int copies, int cull,
-    GradZero zg) {
+    const float* __restrict__ vw, float* __restrict__ g2d, TouchArgs touch, const uint32_t* __restrict__ order,
+    int copies, int cull, GradZero zg) {
   __shared__ float4 s_a[BATCH], s_b[BATCH], s_c[BATCH];
   __shared__ uint8_t s_mask[BATCH];
   // per wave: the batch entries it walks (mask has its strip, inside its
@@ -447,12 +447,14 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) v
   if (tc.inside) {
     T = imgT[tc.pix];
     nl = nlast[tc.pix];
-    gc0 = dC[tc.pix];
-    gc1 = dC[P + tc.pix];
-    gc2 = dC[2 * P + tc.pix];
-    gd = dD[tc.pix];
-    gm = dM ? dM[tc.pix] : 0.f;
-    const float gt = dT ? dT[tc.pix] : 0.f;
+    // the view's loss weight scales all of its pixel adjoints
+    const float sw = vw ? vw[tc.v] : 1.f;
+    gc0 = dC[tc.pix] * sw;
+    gc1 = dC[P + tc.pix] * sw;
+    gc2 = dC[2 * P + tc.pix] * sw;
+    gd = dD[tc.pix] * sw;
+    gm = dM ? dM[tc.pix] * sw : 0.f;
+    const float gt = dT ? dT[tc.pix] * sw : 0.f;
     Tbar = gt + gc0 * bg0 + gc1 * bg1 + gc2 * bg2;
   }
   // longest list prefix any pixel of this wave composited
@@ -712,7 +714,7 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
 #define GS_BWD(BATCH)                                                                                        \
   GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,    \
             bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
-            g2d, touch, order, ctx->bwd_copies, ctx->wave_cull, zg)
+            pg->view_weight, g2d, touch, order, ctx->bwd_copies, ctx->wave_cull, zg)
   switch (ctx->bwd_batch) {
     case 32: GS_BWD(32); break;
     case 128: GS_BWD(128); break;

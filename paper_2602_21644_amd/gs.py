@@ -79,7 +79,7 @@ class LossParams(ctypes.Structure):
 
 
 class PixelGrads(ctypes.Structure):
-    _fields_ = [(k, c_void_p) for k in ("dcolor", "ddepth", "dmp", "dT")]
+    _fields_ = [(k, c_void_p) for k in ("dcolor", "ddepth", "dmp", "dT", "view_weight")]
 
 
 class Grads(ctypes.Structure):
@@ -102,7 +102,7 @@ class MPParams(ctypes.Structure):
 
 
 class MPOut(ctypes.Structure):
-    _fields_ = [(k, c_void_p) for k in ("U_tilde", "alpha", "dynamic", "prune", "M_p", "e", "stats")]
+    _fields_ = [(k, c_void_p) for k in ("U_tilde", "alpha", "dynamic", "prune", "M_p", "e", "stats", "judge")]
 
 
 class AdamGroup(ctypes.Structure):

@@ -13,6 +13,13 @@ observe      renders an observed frame (colour, depth with holes where the
              accumulated opacity is below 0.5, instance map of the moving
              boxes) with the library, as the synthetic stand-in for an RGB-D
              frame and its segmentation.
+train_c5 / evaluate_c5
+             the learned-MP protocol at scale: the surrogate trained on the
+             plain cue's M_p over 20 sequences of 100 frames, then five
+             held-out sequences tracked and MP-updated with the plain cue and
+             with the surrogate, which falls back to the plain cue for a few
+             frames whenever its mean disagreement with the plain cue (the
+             error judge gs_mp_update forms beside it) exceeds a bound.
 
 Every kernel runs in libgs.so; torch holds the buffers.
 """
@@ -22,7 +29,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import gs
+from . import gs, synth
 
 MLP_SHAPES = (("W1", (32, 8)), ("b1", (32,)), ("W2", (32, 32)), ("b2", (32,)), ("W3", (1, 32)), ("b3", (1,)))
 
@@ -121,8 +128,9 @@ class MPFrame:
         self.Mp = torch.zeros(P, device=dev)
         self.e = torch.zeros(P, device=dev)
         self.stats = torch.zeros(8, device=dev)
+        self.judge = torch.zeros(2, device=dev)
         self.out = gs.MPOut(gs.ptr(self.Ut), gs.ptr(self.alpha), gs.ptr(self.dyn), gs.ptr(self.prune),
-                            gs.ptr(self.Mp), gs.ptr(self.e), gs.ptr(self.stats))
+                            gs.ptr(self.Mp), gs.ptr(self.e), gs.ptr(self.stats), gs.ptr(self.judge))
         self.ws = torch.zeros(gs.gs_workspace_size(ctx, self.views.s, gs.GS_OP_MP_UPDATE), dtype=torch.uint8,
                               device=dev)
         self.x = torch.zeros(8 * P, device=dev)
@@ -195,3 +203,157 @@ def mp_error(mp, dynamic, observed=None):
     """Mean |MP - flag| against the ground-truth dynamic flags."""
     err = np.abs(mp - dynamic.astype(np.float64))
     return float(err[observed].mean()) if observed is not None else float(err.mean())
+
+
+class DeviceSequence:
+    """A box sequence (synth.box_sequence, materialize=False) on the device:
+    the map's parameters once, and frame states made by moving the box slices
+    of a mean plane in place."""
+
+    def __init__(self, seq, device="cuda"):
+        self.seq = seq
+        self.base = gs.to_device(seq["map"], device=device)
+        self.mean0 = self.base["mean"].clone()
+        self.deltas = [torch.tensor(np.stack(d).T if d else np.zeros((3, 0)), dtype=torch.float32,
+                                    device=self.mean0.device) for d in seq["deltas"]]
+
+    def frames(self):
+        return len(self.seq["cams"])
+
+    def set_state(self, mean, t):
+        """mean <- the scene's means at frame t (t < 0: the map as built)."""
+        mean.copy_(self.mean0)
+        if t >= 0:
+            for k, sl in enumerate(self.seq["slices"]):
+                mean[:, sl] += self.deltas[t][:, k:k + 1]
+
+    def view(self, mean=None, mp=None):
+        """A Gaussian dict sharing the map's planes, with its own mean/mp
+        tensors when given."""
+        g = dict(self.base)
+        if mean is not None:
+            g["mean"] = mean
+        if mp is not None:
+            g["mp"] = mp
+        return g
+
+
+def c5_sequence(seed, n, width, height, frames):
+    """A C5-protocol sequence: 1-5 moving boxes (5% of the Gaussians) in front
+    of a static layer 3-6 m away, so that the boxes are seen."""
+    return synth.box_sequence(seed, n, width, height, frames, n_boxes=1 + seed % 5, box_frac=0.05, zmin=3.0,
+                              zmax=6.0, materialize=False)
+
+
+def train_c5(ctx, seeds=range(1000, 1020), n=1_000_000, width=640, height=480, frames=100, steps_per_frame=2,
+             lr=3e-3, surrogate=None, log=None):
+    """Trains a surrogate on the plain cue's M_p of every frame of the
+    training sequences (true poses; the map holds each box where it was one
+    frame earlier). Returns (surrogate, frames used, mean BCE of the first and
+    the last 100 steps)."""
+    sur = surrogate or MPSurrogate(ctx, seed=0)
+    losses = []
+    used = 0
+    for seed in seeds:
+        ds = DeviceSequence(c5_sequence(seed, n, width, height, frames))
+        obs_mean = torch.empty_like(ds.mean0)
+        map_mean = torch.empty_like(ds.mean0)
+        mp = torch.full_like(ds.base["mp"], 0.5)
+        g_map = ds.view(map_mean, mp)
+        g_obs = ds.view(obs_mean)
+        mpf = MPFrame(ctx, g_map, ds.seq["cams"][0])
+        prior, conf = instance_tables(len(ds.seq["slices"]))
+        for t in range(ds.frames()):
+            ds.set_state(map_mean, t - 1)
+            ds.set_state(obs_mean, t)
+            cam = ds.seq["cams"][t]
+            tc, td, inst = observe(ctx, g_obs, cam, ds.seq["slices"])
+            mpf.step(cam["T_cw"], tc, td, inst, prior, conf)
+            label = mpf.Mp.clone()
+            for _ in range(steps_per_frame):
+                losses.append(sur.train_step(mpf.views, mpf.x, label, lr).clone())
+            used += 1
+        if log:
+            log(f"trained on sequence {seed}: {used} frames")
+        del mpf, ds
+        torch.cuda.empty_cache()
+    tl = torch.cat(losses).cpu().numpy()
+    k = min(100, tl.size)
+    return sur, used, float(tl[:k].mean()), float(tl[-k:].mean())
+
+
+def evaluate_c5(ctx, surrogate, seeds=range(5000, 5005), n=1_000_000, width=640, height=480, frames=100,
+                track_iters=10, judge_max=0.15, fallback_frames=5):
+    """Held-out sequences tracked from the first frame's true pose (pose-only
+    tracking of the MP-weighted loss, full lists) and MP-updated at the
+    tracked pose, once with the plain cue and once with the surrogate under
+    the fallback rule. Returns per form: MP abs error and label error over
+    the Gaussians observed at least once, camera-centre RMSE (cm), mean
+    rotation error (deg), the MP source's milliseconds per frame, and for the
+    surrogate the share of frames it served and its mean disagreement."""
+    from . import optim
+    res = {}
+    for form in ("plain", "learned"):
+        mp_err, lab_err, dists, angs, ms_src, served, dev = [], [], [], [], [], [], []
+        for seed in seeds:
+            ds = DeviceSequence(c5_sequence(seed, n, width, height, frames))
+            obs_mean = torch.empty_like(ds.mean0)
+            map_mean = torch.empty_like(ds.mean0)
+            mp = torch.full_like(ds.base["mp"], 0.5)
+            g_map = ds.view(map_mean, mp)
+            g_obs = ds.view(obs_mean)
+            cams = ds.seq["cams"]
+            ds.set_state(map_mean, -1)
+            mpf = MPFrame(ctx, g_map, cams[0])
+            trk = optim.Tracker(ctx, g_map, cams[0], max_rank=0, capacity=64 * n + (1 << 16), use_graph=True)
+            prior, conf = instance_tables(len(ds.seq["slices"]))
+            observed = torch.zeros(mpf.n, dtype=torch.bool, device=mp.device)
+            T_prev = np.asarray(cams[0]["T_cw"], np.float64)
+            cool = 0
+            for t in range(1, ds.frames()):
+                ds.set_state(map_mean, t - 1)
+                ds.set_state(obs_mean, t)
+                tc, td, inst = observe(ctx, g_obs, cams[t], ds.seq["slices"])
+                T, _, _ = trk.run(tc.reshape(-1).contiguous(), td, iters=track_iters, T_init=T_prev)
+                T_prev = T
+                use = form == "learned" and cool == 0
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                mpf.step(T, tc, td, inst, prior, conf, surrogate=surrogate if use else None)
+                e1.record()
+                e1.synchronize()
+                ms_src.append(e0.elapsed_time(e1))
+                observed |= mpf.alpha > 0
+                if form == "learned":
+                    served.append(use)
+                    if use:
+                        j = mpf.judge.cpu().numpy()
+                        d = float(j[0] / max(j[1], 1.0))
+                        dev.append(d)
+                        if d > judge_max:
+                            cool = fallback_frames
+                    elif cool > 0:
+                        cool -= 1
+                R_ref = np.asarray(cams[t]["T_cw"], np.float64)
+                dR = T[:, :3] @ R_ref[:, :3].T
+                angs.append(float(np.degrees(np.arccos(np.clip((np.trace(dR) - 1) / 2, -1, 1)))))
+                c = -T[:, :3].T @ T[:, 3]
+                c_ref = -R_ref[:, :3].T @ R_ref[:, 3]
+                dists.append(float(np.linalg.norm(c - c_ref)))
+            ob = observed.cpu().numpy()
+            dyn = ds.seq["dynamic"]
+            mpv = mp.cpu().numpy().astype(np.float64)
+            mp_err.append(mp_error(mpv, dyn, ob))
+            lab = mpf.dyn.cpu().numpy().astype(bool)
+            lab_err.append(float((lab[ob] != dyn[ob]).mean()))
+            del trk, mpf, ds
+            torch.cuda.empty_cache()
+        r = dict(mp_abs_error=round(float(np.mean(mp_err)), 4), label_error_pct=round(100 * float(np.mean(lab_err)), 3),
+                 ate_cm=round(100 * float(np.sqrt(np.mean(np.square(dists)))), 4),
+                 rot_err_deg=round(float(np.mean(angs)), 4), ms_per_frame_mp=round(float(np.median(ms_src)), 4))
+        if form == "learned":
+            r["surrogate_frames_pct"] = round(100 * float(np.mean(served)), 2)
+            r["mean_disagreement"] = round(float(np.mean(dev)), 4) if dev else None
+        res[form] = r
+    return res

@@ -27,18 +27,6 @@ from . import gs
 PARAMS = ("mean", "log_scale", "quat", "opacity_logit", "color")
 
 
-def _scale_pixel_grads(pipe, views, w):
-    """Multiplies view v's pixel adjoints by w[v] (the incoming gradient of
-    its loss)."""
-    sizes = [c["width"] * c["height"] for c in views.cams]
-    s = torch.repeat_interleave(w.to(torch.float32), torch.tensor(sizes, device=w.device))
-    P = pipe.P
-    pipe.dC.view(3, P).mul_(s)
-    pipe.dD.mul_(s)
-    pipe.dM.mul_(s)
-    pipe.dT.mul_(s)
-
-
 class RenderLoss(torch.autograd.Function):
     """loss[V] = RenderLoss.apply(pipe, mp, target_color, target_depth,
     mean, log_scale, quat, opacity_logit, color, pose)
@@ -69,11 +57,16 @@ class RenderLoss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gloss):
         pipe = ctx.pipe
-        if not bool(torch.all(gloss == 1.0)):
-            _scale_pixel_grads(pipe, pipe.views, gloss)
+        # each view's pixel adjoints enter the backward scaled by the incoming
+        # gradient of its loss
+        w = gloss.to(torch.float32).contiguous()
+        pipe.pg.view_weight = gs.ptr(w)
         grads = gs.alloc_grads(ctx.n)
         pose = torch.zeros(6 * pipe.views.V, dtype=torch.float32, device=gloss.device)
-        pipe.backward(ctx.gst, gs.grads_struct(grads, pose))
+        try:
+            pipe.backward(ctx.gst, gs.grads_struct(grads, pose))
+        finally:
+            pipe.pg.view_weight = None
         return (None, None, None, None, grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"],
                 grads["color"], pose.view(-1, 6))
 

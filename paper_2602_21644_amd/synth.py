@@ -208,14 +208,18 @@ def window_cameras(seed, n_views, width, height, spacing=5):
     return cams
 
 
-def box_sequence(seed, n, width, height, n_frames, n_boxes=3, box_frac=0.05, spacing=1, zmin=0.5, zmax=4.0):
+def box_sequence(seed, n, width, height, n_frames, n_boxes=3, box_frac=0.05, spacing=1, zmin=0.5, zmax=4.0,
+                 materialize=True):
     """A moving-box sequence: the map (the scene at frame 0, boxes at their
     first positions), and per frame the camera pose (a random walk of 1 cm /
     0.5 degree per frame) and the observed scene, whose boxes keep moving
     U[0.05, 0.20] m along a random signed axis per frame. Returns
     dict(map=gaussians, cams=[...], obs=[gaussians per frame], slices=[box
-    slices], dynamic=bool[n] ground-truth flags (box Gaussians)). Static
-    depths are drawn on [zmin, zmax]."""
+    slices], dynamic=bool[n] ground-truth flags (box Gaussians), deltas=[per
+    frame, the translation of each box from the map]). Static depths are
+    drawn on [zmin, zmax]. With materialize=False the observed Gaussians are
+    not built (obs is None): large sequences apply `deltas` to the map's box
+    slices instead."""
     rng = rng_for(seed)
     nb_total = int(round(n * box_frac)) if n_boxes > 0 else 0
     g_static = static_gaussians(rng, n - nb_total, width, height, zmin=zmin, zmax=zmax)
@@ -233,19 +237,21 @@ def box_sequence(seed, n, width, height, n_frames, n_boxes=3, box_frac=0.05, spa
     dynamic = np.zeros(n, bool)
     for sl in slices:
         dynamic[sl] = True
-    cams, obs = [], []
+    cams, obs, deltas = [], [], []
     pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
     cur = boxes
     for t in range(n_frames):
         for _ in range(spacing):
             pose = perturbed_pose(rng, deg=0.5, trans=0.01, base=pose)
             cur = move_boxes(rng, cur)
-        g_t = g0
-        for b0, b1, sl in zip(boxes, cur, slices):
-            g_t = translate_gaussians(g_t, sl, b1["centre"] - b0["centre"])
+        deltas.append([np.asarray(b1["centre"] - b0["centre"], np.float64) for b0, b1 in zip(boxes, cur)])
         cams.append(camera(width, height, pose))
-        obs.append(g_t)
-    return dict(map=g0, cams=cams, obs=obs, slices=slices, dynamic=dynamic)
+        if materialize:
+            g_t = g0
+            for d, sl in zip(deltas[-1], slices):
+                g_t = translate_gaussians(g_t, sl, d)
+            obs.append(g_t)
+    return dict(map=g0, cams=cams, obs=obs if materialize else None, slices=slices, dynamic=dynamic, deltas=deltas)
 
 
 # ---------------------------------------------------------------- MP-update inputs

@@ -54,3 +54,24 @@ def test_surrogate_trains_and_matches_plain(ctx):
     print("MP error plain / learned:", errs)
     for e_plain, e_learned in errs:
         assert e_learned <= e_plain + 0.05
+
+
+def test_c5_protocol_gain(ctx):
+    """The learned-MP protocol at 1M Gaussians / 640x480 (fewer sequences than
+    the full protocol): trained on the plain cue's M_p, the surrogate serving
+    the MP update inside the tracking loop gives a lower MP error than the
+    plain cue at the same pose accuracy; a tight bound on the judged
+    disagreement sends frames back to the plain cue."""
+    sur, used, first, last = mp_learn.train_c5(ctx, seeds=range(1000, 1004), frames=50)
+    assert used == 200 and last < first
+    res = mp_learn.evaluate_c5(ctx, sur, seeds=range(5000, 5002), frames=30)
+    print(f"\n[c5] {res}")
+    p, l = res["plain"], res["learned"]
+    assert l["surrogate_frames_pct"] == 100.0
+    assert l["mp_abs_error"] < p["mp_abs_error"] - 0.01
+    assert l["label_error_pct"] <= p["label_error_pct"] + 0.5
+    assert l["ate_cm"] <= p["ate_cm"] + 0.5
+    # the fallback rule: with a bound below the disagreement the surrogate
+    # serves one frame, then the plain cue the next five, and so on
+    tight = mp_learn.evaluate_c5(ctx, sur, seeds=[5000], frames=13, judge_max=1e-6, fallback_frames=5)
+    assert tight["learned"]["surrogate_frames_pct"] == pytest.approx(100.0 * 2 / 12, abs=0.01)
