@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch knobs")
     ap.add_argument("--knobs", default="",
                     help="comma-separated name=value context knobs set before tuning (e.g. bwd_batch=64)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle (C1, C2, the metric workload, one window view) on the host, "
+                         "on all threads and on one, and print the table as JSON")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-window, uneven-batch and learned-MP forms reported beside the step")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -117,6 +120,9 @@ def kernel_bytes(name, st):
 
 def main():
     a = parse()
+    if a.oracle_timing:
+        print(json.dumps(oracle_timing()), flush=True)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "mpsplat runs on one GPU; --gpus must be 1 (sharding the views over "
                                    "several GPUs is not implemented)"}))
@@ -127,6 +133,7 @@ def main():
 
     dev = "cuda"
     torch.cuda.set_device(0)
+    CLOCKS["start"] = rocm_smi_clocks()
     log(f"[bench] workload: {a.n} Gaussians, {a.width}x{a.height}")
     g, cam, tcam, g_t, sl = synth.moving_box_scene(a.seed, a.n, a.width, a.height)
     ctx = gs.Context(0)
@@ -311,6 +318,8 @@ def main():
             total_bytes += b * n_l / a.steps
     iter_frac = total_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
     copy_gbs = copy_bandwidth_gbs(torch)
+    cold_ms = cold_cache_ms(torch, graph, step, a.steps) if graph is not None else None
+    atomics = atomic_roofline(ctx, gs, torch, st, avg_launch_us)
 
     # per-frame MP update at the same scale (reported beside, not in the step)
     mp_ms, mp_graph_ms = mp_update_ms(ctx, gs, synth, torch, a, g, cam, pipe, tc, td)
@@ -340,6 +349,9 @@ def main():
         "eager_ms_per_step": round(eager_ms, 4),
         "kernel_us_per_step": {k: round(1000 * v, 2) for k, v in sorted(per_step.items(), key=lambda x: -x[1])},
         "step_ms_p10_p50_p90": [round(p10, 4), round(p50, 4), round(p90, 4)],
+        "cold_cache_ms_per_step": round(cold_ms, 5) if cold_ms else None,
+        "atomic_roofline": atomics,
+        "clocks": CLOCKS,
         "copy_gbs": round(copy_gbs, 1),
         "iteration_copy_frac": round(total_bytes / (ms * 1e-3) / (copy_gbs * 1e9), 4),
         "mp_update_ms": round(mp_ms, 4),
@@ -355,6 +367,7 @@ def main():
         out["tracking"] = tracking_run(ctx)
         out["epipolar"] = epipolar_run(ctx)
         out["ablation"] = ablation_run(ctx)
+    CLOCKS["end"] = rocm_smi_clocks()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, cam, tc.cpu().numpy().reshape(3, -1), td.cpu().numpy())
     print(json.dumps(out), flush=True)
@@ -644,6 +657,128 @@ def pmc_traffic(kernel):
     if not rec or rec["sha256"] != kernel_source_hash(kernel):
         return None
     return int(1024 * (rec["fetch_kib"] * PMC_SCALE["fetch"] + rec["write_kib"] * PMC_SCALE["write"]))
+
+
+def rocm_smi_clocks():
+    """Current clocks from rocm-smi (None when the tool is not there)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        d = json.loads(r.stdout)
+    except Exception as exc:  # no rocm-smi, or no JSON
+        return {"error": type(exc).__name__}
+    out = {}
+    for card, vals in d.items():
+        if isinstance(vals, dict):
+            out[card] = {k: v for k, v in vals.items() if "clock" in k.lower() or "freq" in k.lower()}
+    return out
+
+
+CLOCKS = {}
+
+
+def cold_cache_ms(torch, graph, step, steps, flush_bytes=512 << 20):
+    """Median ms of single graph replays, each after a 512 MiB device write
+    that evicts the working set from the L2s and the Infinity Cache (the
+    write itself is outside the timed events)."""
+    junk = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    ts = []
+    for i in range(min(steps, 50)):
+        junk.fill_(float(i))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del junk
+    return float(np.median(ts))
+
+
+def atomic_roofline(ctx, gs, torch, st, avg_launch_us):
+    """The backward's float atomics against gs_measure_atomics on the same
+    pattern: the touched records, ten components each, one atomic per staged
+    entry and component (an upper bound on the kernel's count), in the tuned
+    number of per-XCD copies."""
+    n_rec = max(int(st["touched"]), 1)
+    n_ops = int(st["loaded_bwd"]) * 10
+    copies = int(st.get("copies", 1))
+    acc = torch.zeros(copies * n_rec * 10, device="cuda")
+    gs.gs_measure_atomics(ctx, acc, n_rec, n_ops, copies)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gs.gs_measure_atomics(ctx, acc, n_rec, n_ops, copies)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    rate = n_ops / (ms * 1e-3)
+    bwd = [v for k, v in avg_launch_us.items() if k.startswith("render_bwd_kernel")]
+    return {"records": n_rec, "atomics": n_ops, "copies": copies, "ms": round(ms, 4), "atomics_per_s": round(rate, 1),
+            "backward_us": round(bwd[0], 2) if bwd else None,
+            "atomics_share_of_backward": round(1000.0 * ms / bwd[0], 4) if bwd else None}
+
+
+def oracle_timing():
+    """The FP64 oracle's forward + loss + backward of one iteration, median of
+    3 runs (1 run single-threaded at 1M Gaussians), on all host threads and on
+    one: C1 (2,000 Gaussians, 64x48), C2 (200k, 640x480, pose-only tracking
+    case), the metric workload (1M, 640x480) and one 640x480 view of the
+    8-keyframe window over the same 1M scene."""
+    import platform
+    import oracle
+    from paper_2602_21644_amd import synth
+
+    def one(g, cam, tc, td):
+        t0 = time.perf_counter()
+        pr = oracle.project(g, cam)
+        im = oracle.render(pr, g, cam)
+        L = oracle.loss(im, tc, td)
+        g2d = oracle.render_backward(pr, g, cam, L["dC"], L["dD"], L["dM"], L["dT"])
+        oracle.project_backward(g, cam, g2d)
+        return time.perf_counter() - t0
+
+    def target(g_t, tcam):
+        im = oracle.render(oracle.project(g_t, tcam), g_t, tcam)
+        return im["C"].astype(np.float32), np.where(1 - im["T"] >= 0.5, im["D"], 0.0).astype(np.float32)
+
+    cases = {}
+    g, cam, tcam = synth.tiny_scene(seed=1)
+    cases["C1"] = (g, cam) + target(g, tcam)
+    g, cam, tcam, g_t, _ = synth.moving_box_scene(2, 200_000, 640, 480)
+    cases["C2"] = (g, cam) + target(g_t, tcam)
+    g, cam, tcam, g_t, _ = synth.moving_box_scene(11, 1_000_000, 640, 480)
+    cases["metric"] = (g, cam) + target(g_t, tcam)
+    wc = synth.window_cameras(12, 8, 640, 480, spacing=5)
+    cases["C3_view"] = (g, wc[3]) + target(g_t, wc[3])
+    full = oracle.num_threads()
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    out = {"cpu_model": cpu, "nproc": os.cpu_count(), "omp_threads": full, "machine": platform.machine(),
+           "rows": {}}
+    for name, (gg, cc, tc, td) in cases.items():
+        row = {}
+        for threads in (full, 1):
+            oracle.set_threads(threads)
+            runs = 1 if threads == 1 and synth.n_gaussians(gg) >= 1_000_000 else 3
+            row[f"s_{threads}t"] = round(float(np.median([one(gg, cc, tc, td) for _ in range(runs)])), 4)
+            row[f"runs_{threads}t"] = runs
+        oracle.set_threads(full)
+        row["n_gaussians"] = synth.n_gaussians(gg)
+        row["pixels"] = cc["width"] * cc["height"]
+        out["rows"][name] = row
+        log(f"[oracle] {name}: {row}")
+    return out
 
 
 def copy_bandwidth_gbs(torch, nbytes=256 << 20, reps=10):

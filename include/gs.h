@@ -509,6 +509,16 @@ gs_status gs_sched_decide(const gs_sched_params* params, gs_sched_state* state /
                           const float* dbar /*[host] k*/, const uint8_t* epi_state /*[host] k*/, int64_t k,
                           int32_t* refresh /*[host] out*/);
 
+/* ---------------------------------------------------------------- measurement
+ * Not part of the method: the atomic roofline of gs_render_bwd's 2D-adjoint
+ * accumulation. n_ops float atomicAdds of 1.0 in groups of ten consecutive
+ * floats (one record's ten adjoint components, served by ten adjacent lanes)
+ * on records hash(group) % n_records of acc [copies][n_records][10] (device,
+ * the caller's; each workgroup uses the copy of the XCD it runs on, as the
+ * backward's "bwd_copies" do). Time it with events on `stream`. */
+gs_status gs_measure_atomics(gs_ctx* ctx, float* acc, int64_t n_records, int64_t n_ops, int32_t copies,
+                             void* stream);
+
 /* ---------------------------------------------------------------- pruning
  * The mapping window prunes Gaussians whose MP after gs_mp_update exceeds a
  * threshold (the config-3 option `prune_above` flags them; not in the paper,

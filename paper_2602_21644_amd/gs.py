@@ -195,6 +195,7 @@ def lib():
                                     POINTER(EpiParams), P, P, P, P, P], c_int32),
             "gs_sched_decide": ([POINTER(SchedParams), POINTER(SchedState), c_float, P, P, c_int64,
                                  POINTER(c_int32)], c_int32),
+            "gs_measure_atomics": ([P, P, c_int64, c_int64, c_int32, P], c_int32),
             "gs_compact": ([P, P, c_int64, c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int64), c_int32,
                             P, P, P, c_size_t, P], c_int32),
             "gs_mlp_features": ([P, POINTER(Views), POINTER(Image), POINTER(Target), POINTER(MPFrame), P, P],
@@ -219,7 +220,7 @@ EXPORTED = ("gs_status_str", "gs_ctx_create", "gs_ctx_destroy", "gs_last_error",
             "gs_workspace_size", "gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss", "gs_render_fwd_loss",
             "gs_render_fwd_loss_static",
             "gs_render_bwd", "gs_bins_check", "gs_mp_update", "gs_compact", "gs_mp_regularizer", "gs_edge_warp",
-            "gs_epipolar_verify", "gs_sched_decide", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
+            "gs_epipolar_verify", "gs_sched_decide", "gs_measure_atomics", "gs_mlp_features", "gs_mlp_sync", "gs_mlp_fwd", "gs_mlp_train_step",
             "gs_adam_step", "gs_pose_update")
 
 
@@ -396,6 +397,15 @@ def gs_sched_decide(params, state, U_bar, dbar=None, epi_state=None):
     if st != 0:
         raise GSError(st, "gs_sched_decide: invalid parameters")
     return bool(out.value)
+
+
+def gs_measure_atomics(ctx, acc, n_records, n_ops, copies=1, stream=None):
+    """Atomic-throughput probe on the backward's accumulation pattern (see the
+    header); acc: float32 device tensor of at least copies * n_records * 10."""
+    if acc.numel() < copies * n_records * 10:
+        raise ValueError("acc too small")
+    ctx.check(lib().gs_measure_atomics(ctx.h, ptr(acc), int(n_records), int(n_ops), int(copies), _stream(stream)),
+              "gs_measure_atomics")
 
 
 def sched_params(**kw):
