@@ -42,10 +42,10 @@ FLOPS_PER_PAIR = {"render_fwd_kernel": 28, "render_bwd_kernel": 54}
 # the counters are scaled by what they read for a 256 MiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0)
 PMC_TRAFFIC = {
-    "render_bwd_kernel<64>": {"fetch_kib": 9970.6, "write_kib": 5587.2,
-                              "sha256": "129740ded556107967e2092c6fc7fca9526e79ed8e20b745479c3b7eb1f12873"},
-    "render_bwd_kernel<32>": {"fetch_kib": 9934.8, "write_kib": 5588.2,
-                              "sha256": "129740ded556107967e2092c6fc7fca9526e79ed8e20b745479c3b7eb1f12873"},
+    "render_bwd_kernel<64>": {"fetch_kib": 10419.3, "write_kib": 60459.0,
+                              "sha256": "593a1c28027cbed038463c034a5e25f2ee38dd2a0f5894c3b74aa4d1898e15ce"},
+    "render_bwd_kernel<32>": {"fetch_kib": 10452.3, "write_kib": 60467.3,
+                              "sha256": "593a1c28027cbed038463c034a5e25f2ee38dd2a0f5894c3b74aa4d1898e15ce"},
 }
 PMC_SCALE = {"fetch": 2.0, "write": 1.0}
 
@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch knobs")
     ap.add_argument("--knobs", default="",
                     help="comma-separated name=value context knobs set before tuning (e.g. bwd_batch=64)")
+    ap.add_argument("--profile-tracking", type=int, default=0,
+                    help="only run the tracking configuration for this many graph-replayed iterations (after the "
+                         "capture's two), for a profiler")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 oracle (C1, C2, the metric workload, one window view) on the host, "
                          "on all threads and on one, and print the table as JSON")
@@ -122,6 +125,10 @@ def main():
     a = parse()
     if a.oracle_timing:
         print(json.dumps(oracle_timing()), flush=True)
+        return
+    if a.profile_tracking > 0:
+        from paper_2602_21644_amd import gs
+        tracking_run(gs.Context(0), iters=a.profile_tracking)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "mpsplat runs on one GPU; --gpus must be 1 (sharding the views over "
