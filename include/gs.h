@@ -77,7 +77,10 @@ typedef struct gs_camera {
 typedef struct gs_views {
   int32_t n_views;              /* 1 .. GS_MAX_VIEWS */
   int32_t n_scenes;             /* >= 1 */
-  int64_t n_gaussians;          /* total Gaussians of all scenes (= gs_gaussians.n) */
+  int64_t n_gaussians;          /* total Gaussians of all scenes (= gs_gaussians.n);
+                                   0 is allowed: the array pointers of every call
+                                   sized by it (m = 0 records included) may be
+                                   NULL, and the image is the background */
   const gs_camera* cams_host;   /* [host] V cameras: sizes (and values) */
   const gs_camera* cams_dev;    /* V cameras read by the kernels; poses may be
                                    updated in place between graph replays */
@@ -97,7 +100,7 @@ typedef struct gs_gaussians {
 } gs_gaussians;
 
 /* Projection output, m = gs_rec_count records. `rec`, `rect` and `depth_key`
- * are required; the planar fields are optional (NULL skips them). */
+ * are required when m > 0; the planar fields are optional (NULL skips them). */
 typedef struct gs_proj {
   int64_t m;
   float* rec;        /* [m][12] compositing record: ux, uy, depth, opacity,
@@ -150,11 +153,17 @@ typedef struct gs_bins {
   int64_t max_rank;       /* > 0 with proj->key_hist set: bin only the records in
                              front of the first key-histogram boundary that has at
                              least max_rank records in front of it. Every tile list
-                             is then an exact prefix of its full list; tiles that
-                             run out of it with unsaturated pixels raise
-                             `incomplete`. A view with more selected records than
+                             is then an exact prefix of its full list; tiles of a
+                             view whose lists leave out a visible record that run
+                             out of their list with unsaturated pixels raise
+                             `incomplete` (a view with at most max_rank visible
+                             records keeps all of them and never does). A view
+                             with more selected records than
                              gs_ctx_get_param("prefix_cap") gets empty lists and
                              raises `incomplete` at once. <= 0: full lists. */
+  int32_t* truncated;     /* [1] required when max_rank > 0, owned by the library:
+                             bit v is set by gs_bin_sort when view v's lists leave
+                             out a visible record, and read by gs_render_fwd. */
 } gs_bins;
 
 /* Rendered maps (planar, see layouts). */
@@ -335,7 +344,10 @@ gs_status gs_render_fwd_loss_static(gs_ctx* ctx, const gs_views* views, const gs
  * gs_workspace_size(GS_OP_RENDER_BWD), zero-filled before first use; each
  * call leaves it zero-filled. With img->tile_work set (and "tile_order" on)
  * the tiles run in the order the forward dealt, heaviest first; the gradients
- * differ only in the order of their float atomics. */
+ * differ only in the order of their float atomics. When the lists overflowed
+ * (the overflow flag is set) or no Gaussian is listed, every gradient and the
+ * pose twists are written as zeros; with grads->accumulate set the outputs
+ * are then left as they were. */
 gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, const gs_proj* proj,
                         const gs_bins* bins, const gs_image* img, const gs_pixel_grads* pg, const float* bg,
                         gs_grads* grads, void* ws, size_t ws_bytes, void* stream);

@@ -328,7 +328,8 @@ gs_status gs_project(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g, 
   if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
   if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->color || !g->mp))
     return gs_fail(ctx, GS_E_ARG, "gaussian arrays are NULL");
-  if (!proj->rec || !proj->rect || !proj->depth_key) return gs_fail(ctx, GS_E_ARG, "proj.rec/rect/depth_key NULL");
+  if (tab.nrec > 0 && (!proj->rec || !proj->rect || !proj->depth_key))
+    return gs_fail(ctx, GS_E_ARG, "proj.rec/rect/depth_key NULL");
   if (proj->m < tab.nrec) return gs_fail(ctx, GS_E_ARG, "proj.m %lld < %lld records", (long long)proj->m,
                                          (long long)tab.nrec);
   return launch_project(ctx, tab, views->cams_dev, g, proj, (hipStream_t)stream);
@@ -339,14 +340,16 @@ gs_status gs_bin_sort(gs_ctx* ctx, const gs_views* views, const gs_gaussians* g,
   if (!ctx || !proj || !bins) return gs_fail(ctx, GS_E_ARG, "null argument");
   ViewTab tab;
   GS_TRY(make_tab(ctx, views, tab));
-  if (!bins->gauss_id || !bins->tile_start || !bins->sorted_ids || !bins->n_instances || !bins->overflow ||
-      !bins->incomplete)
+  if (!bins->gauss_id || !bins->tile_start || (tab.nrec > 0 && !bins->sorted_ids) || !bins->n_instances ||
+      !bins->overflow || !bins->incomplete)
     return gs_fail(ctx, GS_E_ARG, "bins arrays NULL");
   if (bins->capacity < 0 || bins->capacity > ((int64_t)1 << 32)) return gs_fail(ctx, GS_E_ARG, "bad capacity");
+  if (bins->max_rank > 0 && !bins->truncated) return gs_fail(ctx, GS_E_ARG, "bins.truncated NULL with max_rank > 0");
   if (bins->max_rank > 0 && proj->key_hist) {
     const size_t need = bin_prefix_ws_bytes(ctx, tab, bins->capacity);
     if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "bin_sort workspace %zu < %zu bytes", ws_bytes, need);
-    if (!g || g->n != tab.ng || !proj->rec) return gs_fail(ctx, GS_E_ARG, "prefix binning needs the gaussians and proj.rec");
+    if (!g || g->n != tab.ng || (tab.nrec > 0 && !proj->rec))
+      return gs_fail(ctx, GS_E_ARG, "prefix binning needs the gaussians and proj.rec");
     return launch_bin_prefix(ctx, tab, views->cams_dev, g, proj, bins, (char*)ws, (hipStream_t)stream);
   }
   // the full lists read the rect and record of every Gaussian, which
@@ -371,11 +374,8 @@ gs_status gs_render_fwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   GS_TRY(make_tab(ctx, views, tab));
   if (!img->color || !img->depth || !img->mp || !img->T || !img->n_last) return gs_fail(ctx, GS_E_ARG, "image NULL");
   if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
-  BinTab bt;
-  bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
-  int bits = 0;
-  for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
-  return launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, (hipStream_t)stream);
+  if (bins->max_rank > 0 && !bins->truncated) return gs_fail(ctx, GS_E_ARG, "bins.truncated NULL with max_rank > 0");
+  return launch_render_fwd(ctx, tab, proj, bins, bg, img, (hipStream_t)stream);
 }
 
 gs_status gs_loss(gs_ctx* ctx, const gs_views* views, const gs_image* img, const gs_target* tgt,
@@ -406,12 +406,9 @@ gs_status gs_render_fwd_loss(gs_ctx* ctx, const gs_views* views, const gs_gaussi
   if (lp->weight_mode != 0 && lp->weight_mode != 1) return gs_fail(ctx, GS_E_ARG, "weight_mode 0|1");
   const size_t need = loss_ws_bytes(tab);
   if (!ws || ws_bytes < need) return gs_fail(ctx, GS_E_ARG, "loss workspace %zu < %zu", ws_bytes, need);
-  BinTab bt;
-  bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
-  int bits = 0;
-  for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
+  if (bins->max_rank > 0 && !bins->truncated) return gs_fail(ctx, GS_E_ARG, "bins.truncated NULL with max_rank > 0");
   const LossArgs la = loss_args(tgt, lp, pg, (double*)ws, loss);
-  return launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, (hipStream_t)stream, &la);
+  return launch_render_fwd(ctx, tab, proj, bins, bg, img, (hipStream_t)stream, &la);
 }
 
 }  // extern "C"
@@ -469,13 +466,10 @@ gs_status gs_render_fwd_loss_static(gs_ctx* ctx, const gs_views* views, const gs
                    (long long)tab.ntiles, (long long)kStaticLossTiles);
   double* part = nullptr;
   GS_TRY(static_scratch(ctx, &part));
-  BinTab bt;
-  bin_tab_fill(tab, ctx->bin_chunk, bins->max_rank, bt);
-  int bits = 0;
-  for (int v = 0; v < tab.nv; ++v) bits |= bt.truncated[v] << v;
+  if (bins->max_rank > 0 && !bins->truncated) return gs_fail(ctx, GS_E_ARG, "bins.truncated NULL with max_rank > 0");
   const LossArgs la = loss_args(tgt, lp, pg, part, loss);
   ctx->no_alloc = 1;
-  const gs_status st = launch_render_fwd(ctx, tab, proj, bins, bg, bits, img, (hipStream_t)stream, &la);
+  const gs_status st = launch_render_fwd(ctx, tab, proj, bins, bg, img, (hipStream_t)stream, &la);
   ctx->no_alloc = 0;
   return st;
 }
@@ -487,7 +481,7 @@ gs_status gs_render_bwd(gs_ctx* ctx, const gs_views* views, const gs_gaussians* 
   ViewTab tab;
   GS_TRY(make_tab(ctx, views, tab));
   if (g->n != tab.ng) return gs_fail(ctx, GS_E_ARG, "gaussians.n != views.n_gaussians");
-  if (!gr->pose_only && (!gr->mean || !gr->log_scale || !gr->quat || !gr->opacity_logit || !gr->color))
+  if (!gr->pose_only && tab.ng > 0 && (!gr->mean || !gr->log_scale || !gr->quat || !gr->opacity_logit || !gr->color))
     return gs_fail(ctx, GS_E_ARG, "gradient arrays NULL");
   const BwdWs L = bwd_ws_layout(ctx, tab);
   if (!ws || ws_bytes < L.bytes) return gs_fail(ctx, GS_E_ARG, "render_bwd workspace %zu < %zu", ws_bytes, L.bytes);

@@ -117,8 +117,9 @@ __device__ __forceinline__ void wave_sum10(const float v[10], float k[3]) {
   for (int i = 0; i < 3; ++i) k[i] += dpp_mov<0x118>(k[i]);
 }
 
-__device__ __forceinline__ double wave_sum_to_lane63_d(double x) {
-  // exact-order-independent enough for FP64 partials: butterfly via shuffles
+// Sum of x over the 64 lanes of a wave, returned in every lane (an xor
+// butterfly of shuffles: a fixed order per lane, so repeat calls agree).
+__device__ __forceinline__ double wave_sum_all_d(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
@@ -250,7 +251,7 @@ BinWs bin_ws_layout(const ViewTab&, const BinTab&);
 gs_status launch_bin_sort(gs_ctx*, const ViewTab&, const BinTab&, const gs_proj*, gs_bins*, char*, hipStream_t);
 // with `loss` set, the loss of Eq. (20)-(22) is fused into the forward's
 // epilogue: the pixel adjoints and one float64 partial per tile
-gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const float*, int, gs_image*,
+gs_status launch_render_fwd(gs_ctx*, const ViewTab&, const gs_proj*, const gs_bins*, const float*, gs_image*,
                             hipStream_t, const LossArgs* loss = nullptr);
 // The Gaussians the backward's tile pass gave a gradient: flag[N] (0 or 1,
 // zero on entry, cleared again by the projection adjoint), the list of

@@ -204,7 +204,10 @@ __global__ __launch_bounds__(GS_BLOCK) void bin_ranges_kernel(ViewTab tab, BinTa
                                                               int64_t capacity, uint32_t* __restrict__ tile_start,
                                                               int64_t* __restrict__ n_inst,
                                                               int32_t* __restrict__ overflow,
-                                                              int32_t* __restrict__ incomplete) {
+                                                              int32_t* __restrict__ incomplete,
+                                                              const uint32_t* __restrict__ sorted,
+                                                              const uint32_t* __restrict__ key,
+                                                              int32_t* __restrict__ trunc) {
   const int t = blockIdx.x * GS_BLOCK + threadIdx.x;
   if (t < tab.ntiles) {
     const int v = view_of_tile(tab, t);
@@ -217,6 +220,18 @@ __global__ __launch_bounds__(GS_BLOCK) void bin_ranges_kernel(ViewTab tab, BinTa
     *n_inst = tot;
     *overflow = tot > capacity ? 1 : 0;
     if (incomplete) *incomplete = 0;
+    if (trunc) {
+      // a view binned only its first nlim sorted records leaves out a visible
+      // one when the first record past the limit is visible (culled records
+      // sort last)
+      int32_t bits = 0;
+      for (int v = 0; v < tab.nv; ++v) {
+        if (!bt.truncated[v]) continue;
+        const int64_t roff = tab.r_off[v];
+        if (key[roff + sorted[roff + bt.nlim[v]]] != 0xFFFFFFFFu) bits |= 1 << v;
+      }
+      *trunc = bits;
+    }
   }
 }
 
@@ -409,7 +424,8 @@ gs_status launch_bin_sort(gs_ctx* ctx, const ViewTab& tab, const BinTab& bt, con
   gs_status st = exclusive_scan(ctx, cm, L.cm_n, part, total, s);
   if (st != GS_OK) return st;
   GS_LAUNCH(ctx, bin_ranges_kernel, dim3((tab.ntiles + GS_BLOCK) / GS_BLOCK), dim3(GS_BLOCK), 0, s, tab, bt, cm,
-                     total, bins->capacity, bins->tile_start, bins->n_instances, bins->overflow, bins->incomplete);
+                     total, bins->capacity, bins->tile_start, bins->n_instances, bins->overflow, bins->incomplete,
+                     bins->sorted_ids, proj->depth_key, bins->max_rank > 0 ? bins->truncated : nullptr);
   GS_LAUNCH(ctx, bin_scatter_kernel, dim3(maxchunk, tab.nv), dim3(GS_BLOCK), lds, s, tab, bt,
                      bins->sorted_ids, (const int2*)proj->rect, proj->depth_key, cm, bins->overflow,
                      bins->gauss_id);

@@ -85,7 +85,8 @@ __global__ __launch_bounds__(GS_BLOCK) void psel_kernel(ViewTab tab, const uint3
                                                         float4* __restrict__ rec, uint32_t* __restrict__ seg_key,
                                                         uint32_t* __restrict__ seg_id, int2* __restrict__ seg_rect,
                                                         uint32_t* __restrict__ cnt, int32_t* __restrict__ overflow,
-                                                        int32_t* __restrict__ incomplete, int keys_only) {
+                                                        int32_t* __restrict__ incomplete, int32_t* __restrict__ trunc,
+                                                        int keys_only) {
   __shared__ uint32_t s_wave[4];
   __shared__ uint32_t s_n;
   __shared__ uint32_t s_sel[SEL_TILE];
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(GS_BLOCK) void psel_kernel(ViewTab tab, const uint3
   if (v == 0 && b == 0 && threadIdx.x == 0) {
     *overflow = 0;
     *incomplete = 0;
+    *trunc = 0;
   }
   const int64_t npad = tab.npad[v];
   if (b >= sel_blocks(npad)) return;  // uniform per workgroup
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     ViewTab tab, int nb_max, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ seg_key,
     const uint32_t* __restrict__ seg_id, const int2* __restrict__ seg_rect, uint32_t* __restrict__ hist,
     uint32_t* __restrict__ sorted_ids, int2* __restrict__ srect, uint32_t* __restrict__ view_total,
-    uint32_t* __restrict__ nsel_out, int32_t* __restrict__ incomplete) {
+    uint32_t* __restrict__ nsel_out, int32_t* __restrict__ incomplete, int32_t* __restrict__ trunc) {
   extern __shared__ uint32_t s_dyn[];
   uint32_t* gk = s_dyn;              // [PS_CAP] keys grouped by bucket; later the difference array
   uint32_t* gi = gk + PS_CAP;        // [PS_CAP] ids
@@ -217,17 +219,27 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     s_max = 0u;
     s_area = 0u;
   }
-  for (int i = tid; i < HB; i += PS_THREADS) hist[(int64_t)v * HB + i] = 0;  // consumed
-  __syncthreads();
+  // the histogram counts the view's visible records; it is consumed here
+  uint32_t vis = 0;
+  for (int i = tid; i < HB; i += PS_THREADS) {
+    vis += hist[(int64_t)v * HB + i];
+    hist[(int64_t)v * HB + i] = 0;
+  }
+  uint32_t n_vis;
+  (void)block1024_excl(vis, s_w, n_vis);
   if (n > (uint32_t)PS_CAP) {
     // too many records in front of the threshold for this path: empty lists
     if (tid == 0) {
       view_total[v] = 0;
       nsel_out[v] = 0;
       *incomplete = 1;
+      atomicOr(trunc, 1 << v);
     }
     return;
   }
+  // the lists leave out a visible record: a tile that runs out of its list
+  // with light still passing is not exact
+  if (tid == 0 && n < n_vis) atomicOr(trunc, 1 << v);
   // 2. gather into registers: record e lives in the segment of block b with
   //    bst[b] <= e < bst[b + 1]
   uint32_t kr[PS_PER], ir[PS_PER];
@@ -579,9 +591,9 @@ gs_status launch_bin_prefix(gs_ctx* ctx, const ViewTab& tab, const gs_camera* ca
   uint32_t* nsel = (uint32_t*)(ws + L.nsel);
   GS_LAUNCH(ctx, psel_kernel, dim3(L.nb_max, tab.nv), dim3(GS_BLOCK), 0, s, tab, proj->depth_key, proj->key_hist,
             (const int2*)proj->rect, bins->max_rank, L.nb_max, cams, gsrc, (float4*)proj->rec, seg_key, seg_id,
-            seg_rect, cnt, bins->overflow, bins->incomplete, proj->keys_only ? 1 : 0);
+            seg_rect, cnt, bins->overflow, bins->incomplete, bins->truncated, proj->keys_only ? 1 : 0);
   GS_LAUNCH(ctx, psort_kernel, dim3(tab.nv), dim3(PS_THREADS), PS_LDS, s, tab, L.nb_max, cnt, seg_key, seg_id,
-            seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete);
+            seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete, bins->truncated);
   int nblk = 1;
   for (int v = 0; v < tab.nv; ++v) nblk = max(nblk, ((tab.gx[v] + 1) >> 1) * ((tab.gy[v] + 1) >> 1));
   GS_LAUNCH(ctx, ptiles_kernel, dim3(nblk, tab.nv), dim3(PT_THREADS), 0, s, tab, vtot, nsel, bins->sorted_ids, srect, bins->capacity, bins->tile_start, bins->gauss_id, bins->n_instances,

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(GS_BLOCK) void bwd_project_kernel(
       t += (double)pose_part[(int64_t)b * nvp + i];
       pose_part[(int64_t)b * nvp + i] = 0.f;
     }
-    t = wave_sum_to_lane63_d(t);
+    t = wave_sum_all_d(t);
     if (lane == 0 && pose) pose[i] = (float)(accumulate ? (double)pose[i] + t : t);
   }
   if (threadIdx.x == 0) {

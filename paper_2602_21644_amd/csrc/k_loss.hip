@@ -19,7 +19,7 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_kernel(ViewTab tab, const float
     acc = pixel_loss(la, P, p, C[p], C[P + p], C[2 * P + p], D[p], Mm[p], T[p], la.Cg[p], la.Cg[P + p],
                      la.Cg[2 * P + p], la.Dg[p]);
   }
-  acc = wave_sum_to_lane63_d(acc);
+  acc = wave_sum_all_d(acc);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) la.part[(int64_t)v * gridDim.x + blockIdx.x] = s[0] + s[1] + s[2] + s[3];
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(GS_BLOCK) void loss_final_kernel(const double* __re
 #pragma unroll
     for (int u = 0; u < kLossUnroll; ++u) t += x[u];
   }
-  t = wave_sum_to_lane63_d(t);
+  t = wave_sum_all_d(t);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = t;
   __syncthreads();
   if (threadIdx.x == 0) loss[v] = (float)(s[0] + s[1] + s[2] + s[3]);

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(GS_BLOCK) void mlp_grad_kernel(const float* __restr
     const int idx = threadIdx.x + q * GS_BLOCK;
     if (idx < NP) part[(int64_t)blockIdx.x * NP + idx] = acc[q];
   }
-  lsum = wave_sum_to_lane63_d(lsum);
+  lsum = wave_sum_all_d(lsum);
   if (__lane_id() == 63) s_l[threadIdx.x >> 6] = lsum;
   __syncthreads();
   if (threadIdx.x == 0) lpart[blockIdx.x] = s_l[0] + s_l[1] + s_l[2] + s_l[3];

@@ -48,7 +48,7 @@ __device__ __forceinline__ float ord2f(uint32_t u) {
 }
 
 __device__ __forceinline__ double block_sum_d(double x, double* s) {
-  x = wave_sum_to_lane63_d(x);
+  x = wave_sum_all_d(x);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = x;
   __syncthreads();
   const double r = s[0] + s[1] + s[2] + s[3];
@@ -100,9 +100,9 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_region_kernel(int64_t npix, int64
         s1 += (double)ev[i];
         s2 += (double)ev[i] * (double)ev[i];
       }
-    c = wave_sum_to_lane63_d(c);
-    s1 = wave_sum_to_lane63_d(s1);
-    s2 = wave_sum_to_lane63_d(s2);
+    c = wave_sum_all_d(c);
+    s1 = wave_sum_all_d(s1);
+    s2 = wave_sum_all_d(s2);
     if (__lane_id() == 0) {
       double* o = part + (int64_t)r * 3 * nrows + row;
       o[0] = c;
@@ -142,9 +142,9 @@ __global__ __launch_bounds__(MAXR * 64) void mp_region_final_kernel(const double
       s2 += x[u][2];
     }
   }
-  c = wave_sum_to_lane63_d(c);
-  s1 = wave_sum_to_lane63_d(s1);
-  s2 = wave_sum_to_lane63_d(s2);
+  c = wave_sum_all_d(c);
+  s1 = wave_sum_all_d(s1);
+  s2 = wave_sum_all_d(s2);
   if (lane != 0) return;
   double mu = 0, sd = 0;
   if (c > 0) {

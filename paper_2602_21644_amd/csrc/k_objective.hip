@@ -56,7 +56,7 @@ __global__ __launch_bounds__(GS_BLOCK) void mp_reg_kernel(int64_t n, const float
     dmean[n + k] += g * d1;
     dmean[2 * n + k] += g * d2;
   }
-  acc = wave_sum_to_lane63_d(acc);
+  acc = wave_sum_all_d(acc);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (double)lam * (s[0] + s[1] + s[2] + s[3]);
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(GS_BLOCK) void sum_partials_kernel(const double* __
   __shared__ double s[GS_BLOCK / 64];
   double t = 0.0;
   for (int64_t b = threadIdx.x; b < nb; b += GS_BLOCK) t += part[b];
-  t = wave_sum_to_lane63_d(t);
+  t = wave_sum_all_d(t);
   if (__lane_id() == 63) s[threadIdx.x >> 6] = t;
   __syncthreads();
   if (threadIdx.x == 0) *out = (float)(s[0] + s[1] + s[2] + s[3]);
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(GS_BLOCK) void edge_warp_kernel(ViewTab tab, PairTa
   const int w = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < EW_PART; ++c) {
-    const double t = wave_sum_to_lane63_d(acc[c]);
+    const double t = wave_sum_all_d(acc[c]);
     if (__lane_id() == 63) s_red[c][w] = t;
   }
   __syncthreads();
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(GS_BLOCK) void edge_warp_final_kernel(PairTab pt, c
     }
 #pragma unroll
     for (int c = 0; c < EW_PART; ++c) {
-      const double t = wave_sum_to_lane63_d(acc[c]);
+      const double t = wave_sum_all_d(acc[c]);
       if (__lane_id() == 63) s[c][threadIdx.x >> 6] = t;
     }
     __syncthreads();

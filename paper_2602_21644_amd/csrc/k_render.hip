@@ -80,7 +80,7 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, const int32_t* __restrict__ trunc,
     float bg0, float bg1, float bg2, float* __restrict__ outC, float* __restrict__ outD, float* __restrict__ outM,
     float* __restrict__ outT, uint32_t* __restrict__ nlast, uint32_t* __restrict__ tile_work,
-    int32_t* __restrict__ incomplete, int truncated_bits, int cull, LossArgs la) {
+    int32_t* __restrict__ incomplete, int cull, LossArgs la) {
   // slot BATCH is a zero-opacity entry that pads a wave's last group of four
   __shared__ float4 s_a[BATCH + 1], s_b[BATCH + 1], s_c[BATCH + 1];
   __shared__ uint8_t s_mask[BATCH];
@@ -229,8 +229,9 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
       walked += (uint32_t)k;
     }
   }
-  // a truncated list ran out while some pixel still lets light through
-  if ((truncated_bits >> tc.v) & 1) {
+  // a list that leaves out visible records ran out while some pixel still
+  // lets light through
+  if (trunc && ((*trunc >> tc.v) & 1)) {
     const int active = __syncthreads_count(!done);
     if (exhausted && active > 0 && threadIdx.x == 0) atomicOr(incomplete, 1);
   }
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
   if (tile_work || la.Cg) {
     // the tile's work: the entries its four waves evaluated; the tile's loss
     // partial
-    if (la.Cg) lsum = wave_sum_to_lane63_d(lsum);
+    if (la.Cg) lsum = wave_sum_all_d(lsum);
     if (lane == 0) s_wmax[w] = walked;
     if (lane == 63) s_loss[w] = lsum;
     __syncthreads();
@@ -262,7 +263,6 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
       if (la.Cg) la.part[t] = s_loss[0] + s_loss[1] + s_loss[2] + s_loss[3];
     }
   }
-  (void)trunc;
 }
 
 // Launch order of the backward's tiles, heaviest first by tile_work: a
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kOrderThreads) void fwd_finish_kernel(ViewTab tab, 
 #pragma unroll
     for (int u = 0; u < kU; ++u) acc += x[u];
   }
-  acc = wave_sum_to_lane63_d(acc);
+  acc = wave_sum_all_d(acc);
   if (__lane_id() == 63) s_sum[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -655,7 +655,7 @@ static gs_status query_n_cu(gs_ctx* ctx) {
 }
 
 gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj, const gs_bins* bins,
-                            const float* bg, int truncated_bits, gs_image* img, hipStream_t s, const LossArgs* loss) {
+                            const float* bg, gs_image* img, hipStream_t s, const LossArgs* loss) {
   if (tab.ntiles == 0) return GS_OK;
   const dim3 grid(tab.ntiles), block(GS_BLOCK);
   const float4* rec = (const float4*)proj->rec;
@@ -663,8 +663,9 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
   if (loss) la = *loss;
 #define GS_FWD(BATCH)                                                                                         \
   GS_LAUNCH(ctx, render_fwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
-                     bins->overflow, nullptr, bg[0], bg[1], bg[2], img->color, img->depth, img->mp, img->T,   \
-                     img->n_last, img->tile_work, bins->incomplete, truncated_bits, ctx->wave_cull, la)
+                     bins->overflow, bins->max_rank > 0 ? bins->truncated : nullptr, bg[0], bg[1], bg[2],       \
+                     img->color, img->depth, img->mp, img->T, img->n_last, img->tile_work, bins->incomplete,   \
+                     ctx->wave_cull, la)
   switch (ctx->render_batch) {
     case 64: GS_FWD(64); break;
     case 128: GS_FWD(128); break;

@@ -62,7 +62,7 @@ class Proj(ctypes.Structure):
 class Bins(ctypes.Structure):
     _fields_ = [("capacity", c_int64)] + [(k, c_void_p) for k in ("gauss_id", "tile_start", "sorted_ids",
                                                                  "n_instances", "overflow", "incomplete")] + [
-        ("max_rank", c_int64)]
+        ("max_rank", c_int64), ("truncated", c_void_p)]
 
 
 class Image(ctypes.Structure):
@@ -602,7 +602,8 @@ class Pipeline:
         self.ids = torch.empty(max(1, self.capacity), dtype=i32, device=dev)
         self.tile_start = torch.empty(T + 1, dtype=i32, device=dev)
         self.sorted_ids = torch.empty(M, dtype=i32, device=dev)
-        self.counters = torch.zeros(4, dtype=torch.int64, device=dev)  # n_inst, overflow|incomplete
+        # n_instances, overflow, incomplete, the per-view truncation bits
+        self.counters = torch.zeros(4, dtype=torch.int64, device=dev)
         self.bins = Bins()
         self.bins.capacity = self.capacity
         self.bins.gauss_id, self.bins.tile_start, self.bins.sorted_ids = ptr(self.ids), ptr(self.tile_start), ptr(
@@ -611,6 +612,7 @@ class Pipeline:
         self.bins.n_instances = c_void_p(base)
         self.bins.overflow = c_void_p(base + 8)
         self.bins.incomplete = c_void_p(base + 16)
+        self.bins.truncated = c_void_p(base + 24)
         self.set_max_rank(max_rank)
         self.img_color = torch.empty(3 * P, dtype=f32, device=dev)
         self.img_depth = torch.empty(P, dtype=f32, device=dev)

@@ -88,6 +88,29 @@ def test_layout_helpers():
     assert e.value.status == gs.GS_E_UNSUPPORTED
 
 
+def test_view_count_and_empty_scene_limits():
+    """1 .. GS_MAX_VIEWS views per batch; a batch with no Gaussians is valid
+    (no records, tiles and workspaces as usual), a negative count is not."""
+    from paper_2602_21644_amd import gs, synth
+    L = gs.lib()
+    ctx = gs.Context(0)
+    for V, ok in ((gs.GS_MAX_VIEWS, True), (gs.GS_MAX_VIEWS + 1, False)):
+        host = (gs.Camera * V)(*[gs.camera_struct(synth.camera(40, 30)) for _ in range(V)])
+        v = gs.Views()
+        v.n_views, v.n_scenes, v.n_gaussians = V, 1, 0
+        v.cams_host = ctypes.cast(host, ctypes.POINTER(gs.Camera))
+        v.cams_dev = ctypes.c_void_p(1)
+        if ok:
+            assert L.gs_rec_count(ctypes.byref(v)) == 0
+            assert L.gs_tile_count(ctypes.byref(v)) == V * 3 * 2
+            for op in (gs.GS_OP_BIN_SORT, gs.GS_OP_RENDER_BWD, gs.GS_OP_LOSS):
+                assert gs.gs_workspace_size(ctx, v, op) > 0
+            v.n_gaussians = -1
+        assert L.gs_rec_count(ctypes.byref(v)) == -1
+        with pytest.raises(gs.GSError):
+            gs.gs_workspace_size(ctx, v, gs.GS_OP_LOSS)
+
+
 def test_structs_keep_their_tensors_alive():
     """The C structs hold raw addresses: they keep the tensors they point to
     alive, so a captured graph replayed later never writes freed memory."""

@@ -87,6 +87,8 @@ def _batch_case(ctx, orc, scenes, views, max_rank=0, bg=(0.1, 0.1, 0.1)):
             ref[key][..., begin[s]:begin[s + 1]] += rg[key]
         ref_pose[v] = rg["pose"]
     for s in range(len(scenes)):
+        if begin[s + 1] == begin[s]:
+            continue  # an empty scene has no gradient
         for key in KEYS:
             assert_grads_close(torch_np(grads[key])[..., begin[s]:begin[s + 1]], ref[key][..., begin[s]:begin[s + 1]],
                                name=f"{key}[scene {s}]")
@@ -123,6 +125,23 @@ def test_uneven_scene_batch_parity(ctx, orc, max_rank):
         g, vv = _window(seed, n, W, H, V)
         scenes.append(g)
         views += [(i, c, tc) for _, c, tc in vv]
+    _batch_case(ctx, orc, scenes, views, max_rank=max_rank)
+
+
+@pytest.mark.parametrize("max_rank", [0, 16384])
+def test_max_views_batch_parity(ctx, orc, max_rank):
+    """The largest batch one call takes (GS_MAX_VIEWS = 32 views) over four
+    scenes, one of them empty: every view's image and loss, every scene's
+    gradients and every view's pose twist against the oracle."""
+    empty = synth.static_gaussians(synth.rng_for(40), 0, 48, 32)
+    scenes, views = [empty], [(0, c, c) for c in synth.window_cameras(40, 2, 48, 32)]
+    specs = [(41, 3000, 64, 48, 10), (42, 5000, 96, 72, 10), (43, 2000, 40, 30, 10)]
+    for i, (seed, n, W, H, V) in enumerate(specs):
+        g, vv = _window(seed, n, W, H, V)
+        scenes.append(g)
+        views += [(i + 1, c, tc) for _, c, tc in vv]
+    assert len(views) == 32
+    print(f"\n[batch] 32 views, max_rank={max_rank}", flush=True)
     _batch_case(ctx, orc, scenes, views, max_rank=max_rank)
 
 

@@ -1,0 +1,150 @@
+"""GPU edge cases of the render + loss + backward path (Sec. IV-D, Eq.
+(20)-(22)) against the FP64 oracle: a scene with no Gaussians (full and
+prefix lists, the separate and the fused loss, the backward), and the
+backward when every Gaussian is culled and when the list capacity overflows
+(the gradients and pose twists are written as zeros; with accumulation the
+outputs are left as they were)."""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_21644_amd import gs, synth
+from tests.gpu_util import bwd_zero_part, image_view, make_pipeline, torch_np
+
+pytestmark = pytest.mark.gpu
+
+NAN = float("nan")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return gs.Context(0)
+
+
+def _targets(seed, W, H):
+    rng = np.random.default_rng(seed)
+    tc = rng.random((3, W * H)).astype(np.float32)
+    td = np.where(rng.random(W * H) < 0.8, rng.uniform(0.5, 3.0, W * H), 0.0).astype(np.float32)
+    return tc, td, torch.from_numpy(tc.reshape(-1)).cuda(), torch.from_numpy(td).cuda()
+
+
+def _nan_grads(n):
+    return {k: torch.full_like(v, NAN) for k, v in gs.alloc_grads(n).items()}
+
+
+@pytest.mark.parametrize("weight_mode", [0, 1])
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("max_rank", [0, 64])
+def test_zero_gaussians(ctx, orc, max_rank, fused, weight_mode):
+    """n = 0: no records, empty lists, the background image with T = 1, the
+    oracle's loss (zero: no pixel has coverage) and zero pose twists."""
+    W, H = 72, 40  # partial edge tiles
+    g = synth.static_gaussians(synth.rng_for(5), 0, W, H)
+    cam = synth.camera(W, H)
+    bg = (0.2, 0.5, 0.9)
+    print(f"\n[edge] zero gaussians max_rank={max_rank} fused={fused} weight_mode={weight_mode}", flush=True)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], max_rank=max_rank, full_proj=max_rank == 0, bg=bg)
+    assert pipe.M == 0
+    pipe.set_loss_params(weight_mode=weight_mode)
+    tc, td, tcd, tdd = _targets(1, W, H)
+    pipe.loss.fill_(NAN)
+    if fused:
+        pipe.forward_loss(gst, tcd, tdd)
+    else:
+        pipe.forward(gst)
+        pipe.loss_and_grads(tcd, tdd)
+    over, n_inst, inc = pipe.check()
+    assert not over and n_inst == 0 and inc == 0
+    ref = orc.render(orc.project(g, cam), g, cam, bg=bg)
+    got = image_view(pipe, views, 0)
+    for k in ("C", "D", "M", "T"):
+        np.testing.assert_allclose(got[k], ref[k], rtol=0, atol=1e-7, err_msg=k)
+    assert np.all(got["n_last"] == 0)
+    L = orc.loss(ref, tc, td, weight_mode=weight_mode)
+    assert float(pipe.loss[0]) == L["loss"] == 0.0
+    grads = gs.alloc_grads(0)
+    pose = torch.full((6,), NAN, device="cuda")
+    pipe.backward(gst, gs.grads_struct(grads, pose))
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(pose) == 0
+    assert torch.count_nonzero(bwd_zero_part(pipe, views)) == 0
+
+
+def _assert_zero_backward(pipe, views, gst, n):
+    """A backward with nothing listed writes zeros over NaN-filled outputs;
+    with accumulation it leaves the outputs alone."""
+    grads = _nan_grads(n)
+    pose = torch.full((6,), NAN, device="cuda")
+    pipe.backward(gst, gs.grads_struct(grads, pose))
+    torch.cuda.synchronize()
+    for k, v in grads.items():
+        assert torch.count_nonzero(v) == 0, k  # NaN counts as nonzero
+    assert torch.count_nonzero(pose) == 0
+    grads = {k: torch.full_like(v, 1.5) for k, v in gs.alloc_grads(n).items()}
+    pose = torch.full((6,), 1.5, device="cuda")
+    pipe.backward(gst, gs.grads_struct(grads, pose, accumulate=True))
+    torch.cuda.synchronize()
+    for k, v in grads.items():
+        assert torch.all(v == 1.5), k
+    assert torch.all(pose == 1.5)
+    assert torch.count_nonzero(bwd_zero_part(pipe, views)) == 0
+
+
+@pytest.mark.parametrize("max_rank", [0, 64])
+def test_backward_all_culled(ctx, orc, max_rank):
+    """Every Gaussian behind the camera: an empty image, a zero loss, and zero
+    gradients, as the oracle gives."""
+    W, H = 64, 48
+    g = synth.static_gaussians(synth.rng_for(9), 500, W, H)
+    g["mean"][2] = -1.0
+    cam = synth.camera(W, H)
+    print(f"\n[edge] all culled max_rank={max_rank}", flush=True)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], capacity=16, max_rank=max_rank, full_proj=max_rank == 0)
+    tc, td, tcd, tdd = _targets(2, W, H)
+    pipe.forward_loss(gst, tcd, tdd)
+    over, n_inst, inc = pipe.check()
+    assert not over and n_inst == 0 and inc == 0
+    pr = orc.project(g, cam)
+    im = orc.render(pr, g, cam)
+    L = orc.loss(im, tc, td)
+    assert float(pipe.loss[0]) == L["loss"] == 0.0
+    rg = orc.project_backward(g, cam, orc.render_backward(pr, g, cam, L["dC"], L["dD"], L["dM"], L["dT"]))
+    assert all(np.all(np.asarray(v) == 0) for v in rg.values())
+    _assert_zero_backward(pipe, views, gst, 500)
+
+
+@pytest.mark.parametrize("max_rank", [0, 64])
+def test_backward_after_overflow(ctx, max_rank):
+    """Lists beyond the capacity: the forward leaves the image alone, the loss
+    is a defined zero and the backward writes zero gradients (none of them
+    would be exact)."""
+    g, cam, tcam = synth.tiny_scene()
+    n = synth.n_gaussians(g)
+    print(f"\n[edge] overflow max_rank={max_rank}", flush=True)
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam], capacity=100, max_rank=max_rank, full_proj=max_rank == 0)
+    tc, td, tcd, tdd = _targets(3, cam["width"], cam["height"])
+    pipe.loss.fill_(NAN)
+    pipe.img_T.fill_(7.0)
+    pipe.forward_loss(gst, tcd, tdd)
+    over, n_inst, _ = pipe.check()
+    assert over and n_inst > 100
+    assert float(pipe.loss[0]) == 0.0
+    assert torch.all(pipe.img_T == 7.0)
+    _assert_zero_backward(pipe, views, gst, n)
+    # pose-only under overflow: zero twist, no gradient array touched
+    pose = torch.full((6,), NAN, device="cuda")
+    pipe.backward(gst, gs.grads_struct(None, pose, pose_only=True))
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(pose) == 0
+    # the same views bin in full once the capacity (and the rank) suffice
+    big = gs.Pipeline(ctx, views, 64 * n, max_rank=max_rank and 4096, full_proj=max_rank == 0)
+    big.forward_loss(gst, tcd, tdd)
+    over, _, inc = big.check()
+    assert not over and inc == 0 and float(big.loss[0]) > 0
+    grads = gs.alloc_grads(n)
+    pose = torch.zeros(6, device="cuda")
+    big.backward(gst, gs.grads_struct(grads, pose))
+    torch.cuda.synchronize()
+    assert float(torch_np(grads["mean"]).__abs__().max()) > 0

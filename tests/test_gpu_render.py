@@ -131,7 +131,10 @@ def test_bin_sort_prefix_bitexact(ctx, orc, seed, m, W, H, R):
         over, n_inst, inc = pipe.check()
         assert not over
         assert int(pipe.key_hist.abs().sum()) == 0
-        if sel.sum() > ctx.get_param("prefix_cap"):
+        # the view's truncation bit: some visible record was left out
+        cap = ctx.get_param("prefix_cap")
+        assert int(pipe.counters[3]) == int(sel.sum() < (key != 0xFFFFFFFF).sum() or sel.sum() > cap)
+        if sel.sum() > cap:
             assert inc == 1 and n_inst == 0
             continue
         assert inc == 0
@@ -437,6 +440,37 @@ def test_max_rank_prefix_lists(ctx, orc):
             assert_image_close(image_view(pipe2, views2, 0), ref, ref["margin"])
         elif R_exact > 256:
             assert inc == 1  # R_exact is the smallest exact power of two from 256
+
+
+@pytest.mark.parametrize("prefix", [True, False])
+def test_rank_above_visible_count_is_exact(ctx, orc, prefix):
+    """max_rank below the record count but above the visible count: the
+    lists keep every visible record, so they are the full lists and no tile
+    raises `incomplete`, though most pixels are unsaturated; a rank below the
+    visible count does raise it. Both on the prefix path and on the
+    rank-limited full path (key_hist NULL)."""
+    g, cam, _ = synth.tiny_scene(seed=6)
+    n = synth.n_gaussians(g)
+    g["mean"][2, 500:] = -1.0  # 500 of 2000 in front of the camera
+    views, pipe, gt, gst = make_pipeline(ctx, g, [cam])
+    pipe.forward(gst)
+    full = [t.clone() for t in (pipe.img_color, pipe.img_depth, pipe.img_mp, pipe.img_T, pipe.img_nlast)]
+    n_full = pipe.check()[1]
+    assert float((pipe.img_T > 0.5).float().mean()) > 0.1  # unsaturated pixels
+    ref = orc.render(orc.project(g, cam), g, cam)
+    for R, inc_want in ((1024, 0), (64, 1)):
+        print(f"\n[rank] prefix={prefix} R={R} (n={n})", flush=True)
+        views2, pipe2, gt2, gst2 = make_pipeline(ctx, g, [cam], max_rank=R, full_proj=not prefix)
+        if not prefix:
+            pipe2.proj.key_hist = None  # rank-limited full lists
+        pipe2.forward(gst2)
+        over, n_inst, inc = pipe2.check()
+        assert not over and inc == inc_want, (R, inc)
+        if inc_want == 0:
+            assert n_inst == n_full
+            for a, b in zip(full, (pipe2.img_color, pipe2.img_depth, pipe2.img_mp, pipe2.img_T, pipe2.img_nlast)):
+                assert torch.equal(a, b)
+            assert_image_close(image_view(pipe2, views2, 0), ref, ref["margin"])
 
 
 def test_full_size_full_lists(ctx, orc):
