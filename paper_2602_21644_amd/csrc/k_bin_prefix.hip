@@ -52,7 +52,7 @@ static_assert(PS_BUCKETS == 4 * PS_THREADS && PS_MAXBLK == 4 * PS_THREADS, "4 en
 __device__ __forceinline__ int sel_blocks(int64_t npad) { return (int)((npad + SEL_TILE - 1) / SEL_TILE); }
 
 // Threshold from the coarse histogram of one view: keys < theta are selected.
-__device__ uint32_t theta_of(const uint32_t* __restrict__ hist, int64_t R, uint32_t* s_wave) {
+__device__ uint32_t theta_of(const uint32_t* __restrict__ hist, int64_t R, uint32_t* s_wave, uint32_t& total) {
   __shared__ uint32_t s_theta;
   constexpr int PER = HB / GS_BLOCK;
   uint32_t loc[PER];
@@ -62,7 +62,6 @@ __device__ uint32_t theta_of(const uint32_t* __restrict__ hist, int64_t R, uint3
     loc[i] = hist[threadIdx.x * PER + i];
     sum += loc[i];
   }
-  uint32_t total;
   const uint32_t ex = block_excl_scan(sum, s_wave, total);
   if (threadIdx.x == 0) s_theta = 0xFFFFFFFFu;
   __syncthreads();
@@ -86,7 +85,7 @@ __global__ __launch_bounds__(GS_BLOCK) void psel_kernel(ViewTab tab, const uint3
                                                         uint32_t* __restrict__ seg_id, int2* __restrict__ seg_rect,
                                                         uint32_t* __restrict__ cnt, int32_t* __restrict__ overflow,
                                                         int32_t* __restrict__ incomplete, int32_t* __restrict__ trunc,
-                                                        int keys_only) {
+                                                        uint32_t* __restrict__ nvis, int keys_only) {
   __shared__ uint32_t s_wave[4];
   __shared__ uint32_t s_n;
   __shared__ uint32_t s_sel[SEL_TILE];
@@ -106,8 +105,12 @@ __global__ __launch_bounds__(GS_BLOCK) void psel_kernel(ViewTab tab, const uint3
     const int64_t j = (int64_t)b * SEL_TILE + i * GS_BLOCK + threadIdx.x;
     kk[i] = j < npad ? key[roff + j] : 0xFFFFFFFFu;
   }
-  const uint32_t theta = theta_of(hist + (int64_t)v * HB, R, s_wave);
-  if (threadIdx.x == 0) s_n = 0;
+  uint32_t visible;
+  const uint32_t theta = theta_of(hist + (int64_t)v * HB, R, s_wave, visible);
+  if (threadIdx.x == 0) {
+    s_n = 0;
+    if (b == 0) nvis[v] = visible;  // the view's visible records
+  }
   __syncthreads();
   const uint64_t lt = lanemask_lt();
   const int64_t sbase = roff + (int64_t)b * SEL_TILE;
@@ -185,7 +188,8 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     ViewTab tab, int nb_max, const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ seg_key,
     const uint32_t* __restrict__ seg_id, const int2* __restrict__ seg_rect, uint32_t* __restrict__ hist,
     uint32_t* __restrict__ sorted_ids, int2* __restrict__ srect, uint32_t* __restrict__ view_total,
-    uint32_t* __restrict__ nsel_out, int32_t* __restrict__ incomplete, int32_t* __restrict__ trunc) {
+    uint32_t* __restrict__ nsel_out, int32_t* __restrict__ incomplete, int32_t* __restrict__ trunc,
+    const uint32_t* __restrict__ nvis) {
   extern __shared__ uint32_t s_dyn[];
   uint32_t* gk = s_dyn;              // [PS_CAP] keys grouped by bucket; later the difference array
   uint32_t* gi = gk + PS_CAP;        // [PS_CAP] ids
@@ -219,14 +223,8 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     s_max = 0u;
     s_area = 0u;
   }
-  // the histogram counts the view's visible records; it is consumed here
-  uint32_t vis = 0;
-  for (int i = tid; i < HB; i += PS_THREADS) {
-    vis += hist[(int64_t)v * HB + i];
-    hist[(int64_t)v * HB + i] = 0;
-  }
-  uint32_t n_vis;
-  (void)block1024_excl(vis, s_w, n_vis);
+  for (int i = tid; i < HB; i += PS_THREADS) hist[(int64_t)v * HB + i] = 0;  // consumed
+  __syncthreads();
   if (n > (uint32_t)PS_CAP) {
     // too many records in front of the threshold for this path: empty lists
     if (tid == 0) {
@@ -238,8 +236,9 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     return;
   }
   // the lists leave out a visible record: a tile that runs out of its list
-  // with light still passing is not exact
-  if (tid == 0 && n < n_vis) atomicOr(trunc, 1 << v);
+  // with light still passing is not exact (psel counted the visible records
+  // of every view with records)
+  if (tid == 0 && nb > 0 && n < nvis[v]) atomicOr(trunc, 1 << v);
   // 2. gather into registers: record e lives in the segment of block b with
   //    bst[b] <= e < bst[b + 1]
   uint32_t kr[PS_PER], ir[PS_PER];
@@ -517,7 +516,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ host side
 struct PrefWs {
-  size_t cnt, seg_key, seg_id, seg_rect, srect, vtot, nsel, bytes;
+  size_t cnt, seg_key, seg_id, seg_rect, srect, vtot, nsel, nvis, bytes;
   int nb_max;
 };
 
@@ -535,6 +534,7 @@ static PrefWs pref_layout(const ViewTab& tab) {
   L.srect = o; o += al256(M * 8);
   L.vtot = o; o += al256(4 * GS_MAX_VIEWS);
   L.nsel = o; o += al256(4 * GS_MAX_VIEWS);
+  L.nvis = o; o += al256(4 * GS_MAX_VIEWS);
   L.bytes = o;
   return L;
 }
@@ -589,11 +589,12 @@ gs_status launch_bin_prefix(gs_ctx* ctx, const ViewTab& tab, const gs_camera* ca
   int2* srect = (int2*)(ws + L.srect);
   uint32_t* vtot = (uint32_t*)(ws + L.vtot);
   uint32_t* nsel = (uint32_t*)(ws + L.nsel);
+  uint32_t* nvis = (uint32_t*)(ws + L.nvis);
   GS_LAUNCH(ctx, psel_kernel, dim3(L.nb_max, tab.nv), dim3(GS_BLOCK), 0, s, tab, proj->depth_key, proj->key_hist,
             (const int2*)proj->rect, bins->max_rank, L.nb_max, cams, gsrc, (float4*)proj->rec, seg_key, seg_id,
-            seg_rect, cnt, bins->overflow, bins->incomplete, bins->truncated, proj->keys_only ? 1 : 0);
+            seg_rect, cnt, bins->overflow, bins->incomplete, bins->truncated, nvis, proj->keys_only ? 1 : 0);
   GS_LAUNCH(ctx, psort_kernel, dim3(tab.nv), dim3(PS_THREADS), PS_LDS, s, tab, L.nb_max, cnt, seg_key, seg_id,
-            seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete, bins->truncated);
+            seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete, bins->truncated, nvis);
   int nblk = 1;
   for (int v = 0; v < tab.nv; ++v) nblk = max(nblk, ((tab.gx[v] + 1) >> 1) * ((tab.gy[v] + 1) >> 1));
   GS_LAUNCH(ctx, ptiles_kernel, dim3(nblk, tab.nv), dim3(PT_THREADS), 0, s, tab, vtot, nsel, bins->sorted_ids, srect, bins->capacity, bins->tile_start, bins->gauss_id, bins->n_instances,
