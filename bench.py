@@ -128,7 +128,11 @@ def main():
         return
     if a.profile_tracking > 0:
         from paper_2602_21644_amd import gs
-        tracking_run(gs.Context(0), iters=a.profile_tracking)
+        ctx = gs.Context(0)
+        for kv in filter(None, a.knobs.split(",")):
+            name, val = kv.split("=")
+            ctx.set_param(name.strip(), int(val))
+        tracking_run(ctx, iters=a.profile_tracking)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "mpsplat runs on one GPU; --gpus must be 1 (sharding the views over "

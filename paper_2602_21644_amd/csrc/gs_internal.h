@@ -117,6 +117,35 @@ __device__ __forceinline__ void wave_sum10(const float v[10], float k[3]) {
   for (int i = 0; i < 3; ++i) k[i] += dpp_mov<0x118>(k[i]);
 }
 
+// The same transposed reduction for six values (the terms a pose-only
+// backward needs). Totals in lane 15 of every row r as k[0..1]:
+//   row 0: (v0, v2)   row 1: (v1, 0)   row 2: (v3, v5)   row 3: (v4, 0)
+__device__ __forceinline__ void wave_sum6(const float v[6], float k[2]) {
+  float h[4];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    // lanes 0-31 end up with v[i] folded over lanes +32, lanes 32-63 with v[i+3]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 3]), false, false);
+    h[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  h[3] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    // rows 0 and 2 take h[2i] folded over rows +1, rows 1 and 3 take h[2i+1]
+    const auto r =
+        __builtin_amdgcn_permlane16_swap(__float_as_uint(h[2 * i]), __float_as_uint(h[2 * i + 1]), false, false);
+    k[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) k[i] += dpp_mov<0x111>(k[i]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) k[i] += dpp_mov<0x112>(k[i]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) k[i] += dpp_mov<0x114>(k[i]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) k[i] += dpp_mov<0x118>(k[i]);
+}
+
 // Sum of x over the 64 lanes of a wave, returned in every lane (an xor
 // butterfly of shuffles: a fixed order per lane, so repeat calls agree).
 __device__ __forceinline__ double wave_sum_all_d(double x) {
@@ -214,8 +243,11 @@ struct gs_ctx {
 };
 
 // Kernel launch; with ctx->timing set, records a start and a stop event on the
-// launch stream around it (measurement only: not for graph capture).
-#define GS_LAUNCH(ctx, kern, grid, block, shm, strm, ...)                   \
+// launch stream around it (measurement only: not for graph capture), under
+// the kernel's name or the given one.
+#define GS_LAUNCH(ctx, kern, grid, block, shm, strm, ...) \
+  GS_LAUNCH_NAMED(ctx, #kern, kern, grid, block, shm, strm, __VA_ARGS__)
+#define GS_LAUNCH_NAMED(ctx, name, kern, grid, block, shm, strm, ...)      \
   do {                                                                      \
     hipEvent_t e0_ = nullptr, e1_ = nullptr;                                \
     const bool t_ = (ctx) && (ctx)->timing && !(ctx)->no_alloc;             \
@@ -227,7 +259,7 @@ struct gs_ctx {
     hipLaunchKernelGGL(kern, grid, block, shm, strm, __VA_ARGS__);          \
     if (t_) {                                                               \
       (void)hipEventRecord(e1_, strm);                                      \
-      gs_note_timer(ctx, #kern, e0_, e1_);                                  \
+      gs_note_timer(ctx, name, e0_, e1_);                                   \
     }                                                                       \
   } while (0)
 

@@ -397,7 +397,7 @@ __device__ __forceinline__ void zero_grad_slice(const GradZero& z, int blk) {
   }
 }
 
-template <int BATCH>
+template <int BATCH, bool POSE>
 __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void render_bwd_kernel(
     ViewTab tab, const float4* __restrict__ rec, const uint32_t* __restrict__ ids,
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, float bg0, float bg1, float bg2,
@@ -528,18 +528,30 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) v
           const float h = (valid && araw < GS_ALPHA_MAX) ? abar * G : 0.f;
           Tbar = vdot * a + Tbar * one_m;
           T = Tj;
-          float v[10];
-          v[0] = h * dx;
-          v[1] = h * dy;
-          v[2] = v[0] * dx;
-          v[3] = v[0] * dy;
-          v[4] = v[1] * dy;
-          v[5] = h;
-          v[6] = wgt * gc0;
-          v[7] = wgt * gc1;
-          v[8] = wgt * gc2;
-          v[9] = wgt * gd;
-          wave_sum10(v, k);
+          if constexpr (POSE) {
+            // the pose moves the mean, the conic and the depth only
+            float v[6];
+            v[0] = h * dx;
+            v[1] = h * dy;
+            v[2] = v[0] * dx;
+            v[3] = v[0] * dy;
+            v[4] = v[1] * dy;
+            v[5] = wgt * gd;
+            wave_sum6(v, k);
+          } else {
+            float v[10];
+            v[0] = h * dx;
+            v[1] = h * dy;
+            v[2] = v[0] * dx;
+            v[3] = v[0] * dy;
+            v[4] = v[1] * dy;
+            v[5] = h;
+            v[6] = wgt * gc0;
+            v[7] = wgt * gc1;
+            v[8] = wgt * gc2;
+            v[9] = wgt * gd;
+            wave_sum10(v, k);
+          }
         }
       }
       if ((lane & 15) == 15) s_red[jj][w * 4 + (lane >> 4)] = make_float4(k[0], k[1], k[2], 0.f);
@@ -598,9 +610,17 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) v
         t2.x += rw[ww][2].x; t2.y += rw[ww][2].y; t2.z += rw[ww][2].z;
         t3.x += rw[ww][3].x; t3.y += rw[ww][3].y;
       }
-      // wave_sum10's rows: (m0, m2, m4), (m1, m3, -), (m5, m7, m9), (m6, m8, -)
-      const float m0 = t0.x, m2 = t0.y, m4 = t0.z, m1 = t1.x, m3 = t1.y;
-      const float m5 = t2.x, m7 = t2.y, m9 = t2.z, m6 = t3.x, m8 = t3.y;
+      float m0, m1, m2, m3, m4, m5, m6, m7, m8, m9;
+      if constexpr (POSE) {
+        // wave_sum6's rows: (m0, m2), (m1, -), (m3, m9), (m4, -); the opacity
+        // and colour sums are not formed
+        m0 = t0.x; m2 = t0.y; m1 = t1.x; m3 = t2.x; m9 = t2.y; m4 = t3.x;
+        m5 = m6 = m7 = m8 = 0.f;
+      } else {
+        // wave_sum10's rows: (m0, m2, m4), (m1, m3, -), (m5, m7, m9), (m6, m8, -)
+        m0 = t0.x; m2 = t0.y; m4 = t0.z; m1 = t1.x; m3 = t1.y;
+        m5 = t2.x; m7 = t2.y; m9 = t2.z; m6 = t3.x; m8 = t3.y;
+      }
       const float o = s_a[jj].w;
       const float4 B = s_b[jj];
       // back from base-2 exponent units to the conic
@@ -712,14 +732,17 @@ gs_status launch_render_bwd_tiles(gs_ctx* ctx, const ViewTab& tab, const gs_proj
   const float4* rec = (const float4*)proj->rec;
   // the order the last forward dealt (second half of the scheduling state)
   const uint32_t* order = img->tile_work && ctx->tile_order ? img->tile_work + tab.ntiles : nullptr;
-#define GS_BWD(BATCH)                                                                                        \
-  GS_LAUNCH(ctx, render_bwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,    \
-            bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor, pg->ddepth, pg->dmp, pg->dT,  \
-            pg->view_weight, g2d, touch, order, ctx->bwd_copies, ctx->wave_cull, zg)
+#define GS_BWD(BATCH, POSE)                                                                                   \
+  GS_LAUNCH_NAMED(ctx, POSE ? "render_bwd_pose_kernel<" #BATCH ">" : "render_bwd_kernel<" #BATCH ">",          \
+                  (render_bwd_kernel<BATCH, POSE>), grid, block, 0, s, tab, rec, bins->gauss_id,               \
+                  bins->tile_start, bins->overflow, bg[0], bg[1], bg[2], img->T, img->n_last, pg->dcolor,      \
+                  pg->ddepth, pg->dmp, pg->dT, pg->view_weight, g2d, touch, order, ctx->bwd_copies,            \
+                  ctx->wave_cull, zg)
+  const bool pose = gr->pose_only != 0;
   switch (ctx->bwd_batch) {
-    case 32: GS_BWD(32); break;
-    case 128: GS_BWD(128); break;
-    default: GS_BWD(64); break;
+    case 32: if (pose) GS_BWD(32, true); else GS_BWD(32, false); break;
+    case 128: if (pose) GS_BWD(128, true); else GS_BWD(128, false); break;
+    default: if (pose) GS_BWD(64, true); else GS_BWD(64, false); break;
   }
 #undef GS_BWD
   return gs_check_launch(ctx, "render_bwd");
