@@ -42,10 +42,10 @@ FLOPS_PER_PAIR = {"render_fwd_kernel": 28, "render_bwd_kernel": 54}
 # the counters are scaled by what they read for a 256 MiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0)
 PMC_TRAFFIC = {
-    "render_bwd_kernel<64>": {"fetch_kib": 10433.6, "write_kib": 60459.4,
-                              "sha256": "492acb8eea150f2985ac2c382773727688da33345134163984ae882aafbc697c"},
-    "render_bwd_kernel<32>": {"fetch_kib": 10417.2, "write_kib": 60460.0,
-                              "sha256": "492acb8eea150f2985ac2c382773727688da33345134163984ae882aafbc697c"},
+    "render_bwd_kernel<64>": {"fetch_kib": 10446.8, "write_kib": 60457.6,
+                              "sha256": "cc6fb4f9e9a4a98254a0b77c2fdade0d61edaf9dcb9132499e1b85f3777bfa99"},
+    "render_bwd_kernel<32>": {"fetch_kib": 10447.5, "write_kib": 60467.4,
+                              "sha256": "cc6fb4f9e9a4a98254a0b77c2fdade0d61edaf9dcb9132499e1b85f3777bfa99"},
 }
 PMC_SCALE = {"fetch": 2.0, "write": 1.0}
 
