@@ -110,17 +110,22 @@ def tune(ctx, views, gaussians, target_color, target_depth, cache=None, iters=10
     if R == 0:
         space.update(FULL_KNOBS)
     names = list(space)
-    # the current knobs first; another candidate wins only when it is at
-    # least `margin` faster, so timing noise does not flip the choice
     cur = tuple(ctx.get_param(k) for k in names)
     combos = [cur] + [c for c in itertools.product(*[space[k] for k in names]) if c != cur]
-    best = None
-    for combo in combos:
+
+    def measure(combo, rounds):
         for k, v in zip(names, combo):
             ctx.set_param(k, v)
-        ms = _time(step, iters)
-        if best is None or ms < (1.0 - margin) * best[0]:
-            best = (ms, dict(zip(names, combo)))
+        return _time(step, iters, rounds)
+
+    # every candidate once, then the three fastest and the current knobs again;
+    # a candidate replaces the current knobs only when it is at least `margin`
+    # faster, so timing noise does not flip the choice
+    first = sorted((measure(c, 3), c) for c in combos)
+    finals = {c: measure(c, 5) for c in dict.fromkeys([cur] + [c for _, c in first[:3]])}
+    fast = min(finals, key=finals.get)
+    pick = fast if finals[fast] < (1.0 - margin) * finals[cur] else cur
+    best = (finals[pick], dict(zip(names, pick)))
     over, _, inc = pipe.check()
     if over:
         raise RuntimeError("binning capacity exceeded while tuning")
