@@ -40,6 +40,14 @@ constexpr int PS_THREADS = 1024;
 constexpr int PS_CAP = 12288;                   // selected records per view
 constexpr int PS_PER = PS_CAP / PS_THREADS;
 constexpr int PS_BUCKETS = 4096;
+// buckets larger than this are sorted by a network instead of being ranked
+// record by record (at most PS_CAP / (PS_BIG + 1) of them). A network stage
+// with its workgroup barrier costs ~1000 cycles, so the network only pays
+// for buckets of several thousand records: one of 561 took 58k cycles
+// sorted, 63k ranked.
+constexpr int PS_BIG = 4096;
+constexpr int PS_MAXBIG = PS_CAP / (PS_BIG + 1) + 1;
+static_assert(PS_CAP < 0xFFFF, "0xFFFF marks a slot outside the sorted buckets");
 constexpr int PS_MAXBLK = 4096;                 // selection blocks per view (8.4M records)
 // dynamic LDS of psort: keys and ids grouped by bucket, bucket cursors, the
 // block offsets (later the bucket starts), and the final position of each
@@ -198,6 +206,8 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
   uint16_t* fpos = reinterpret_cast<uint16_t*>(bst + PS_MAXBLK + 1);  // [PS_CAP] final position per slot
   __shared__ uint32_t s_w[PS_THREADS / 64];
   __shared__ uint32_t s_min, s_max, s_area;
+  __shared__ uint32_t s_nbig, s_big[PS_MAXBIG];
+  __shared__ uint32_t s_bb0[PS_MAXBIG], s_bbn[PS_MAXBIG], s_blp[PS_MAXBIG], s_boff[PS_MAXBIG + 1], s_lmax;
   const int v = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t roff = tab.r_off[v];
@@ -219,6 +229,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
   }
   if (tid == 0) {
     bst[PS_MAXBLK] = n;
+    s_nbig = 0u;
     s_min = 0xFFFFFFFFu;
     s_max = 0u;
     s_area = 0u;
@@ -311,6 +322,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     cur[tid * 4 + q] = run;
     bst[tid * 4 + q] = run;
     run += c4[q];
+    if (c4[q] > (uint32_t)PS_BIG) s_big[atomicAdd(&s_nbig, 1u)] = (uint32_t)(tid * 4 + q);
   }
   __syncthreads();
   uint32_t pos[PS_PER];  // each record's slot in bucket order, then its final position
@@ -324,6 +336,94 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     }
   }
   __syncthreads();
+  // 4a. Buckets of more than PS_BIG records (many records at nearly one
+  //     depth, such as a large surface facing the camera) are sorted in place on
+  //     (key, id) by one segmented bitonic network: every bucket's merges
+  //     run ascending (the first stage of each compares mirrored positions),
+  //     so the positions past a bucket's end act as +inf and their pairs are
+  //     skipped, and all such buckets advance through the same stages.
+  //     Ranking inside them record by record would take time quadratic in
+  //     their size. fpos carries each record's scatter slot through the
+  //     network and then maps the slot to its final position.
+  const uint32_t nbig = s_nbig;
+  if (nbig > 0) {  // uniform
+    if (tid == 0) {
+      uint32_t off = 0, lmax = 0;
+      for (uint32_t bb = 0; bb < nbig; ++bb) {
+        const uint32_t d = s_big[bb];
+        const uint32_t b0 = bst[d], B = cur[d] - b0;
+        uint32_t lp = 0;
+        while ((1u << lp) < B) ++lp;
+        s_bb0[bb] = b0;
+        s_bbn[bb] = B;
+        s_blp[bb] = lp;
+        s_boff[bb] = off;
+        off += 1u << (lp - 1);  // pairs per stage
+        lmax = lp > lmax ? lp : lmax;
+      }
+      s_boff[nbig] = off;
+      s_lmax = lmax;
+    }
+#pragma unroll
+    for (int q = 0; q < PS_PER; ++q) {
+      const uint32_t i = (uint32_t)(q * PS_THREADS + tid);
+      if (i < n) fpos[i] = (uint16_t)i;
+    }
+    __syncthreads();
+    const uint32_t npairs = s_boff[nbig], lmax = s_lmax;
+    for (uint32_t lk = 1; lk <= lmax; ++lk) {
+      const uint32_t k = 1u << lk;
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll 1
+        for (uint32_t f = tid; f < npairs; f += PS_THREADS) {
+          uint32_t bb = 0;
+          while (bb + 1 < nbig && s_boff[bb + 1] <= f) ++bb;  // at most PS_MAXBIG steps
+          if (lk > s_blp[bb]) continue;                       // this bucket's network is done
+          const uint32_t i = f - s_boff[bb], b0 = s_bb0[bb], B = s_bbn[bb];
+          uint32_t lo, hi;
+          if (j == (k >> 1)) {
+            const uint32_t blk = i >> (lk - 1), ps = i & ((k >> 1) - 1u);
+            lo = blk * k + ps;
+            hi = blk * k + k - 1u - ps;
+          } else {
+            lo = 2u * i - (i & (j - 1u));
+            hi = lo + j;
+          }
+          if (hi < B) {
+            const uint32_t ka = gk[b0 + lo], kb = gk[b0 + hi], ia = gi[b0 + lo], ib = gi[b0 + hi];
+            if (ka > kb || (ka == kb && ia > ib)) {
+              gk[b0 + lo] = kb;
+              gk[b0 + hi] = ka;
+              gi[b0 + lo] = ib;
+              gi[b0 + hi] = ia;
+              const uint16_t t = fpos[b0 + lo];
+              fpos[b0 + lo] = fpos[b0 + hi];
+              fpos[b0 + hi] = t;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // in a sorted bucket, slot fpos[x] now sits at x: invert the map there
+    uint16_t from[PS_PER];
+#pragma unroll
+    for (int q = 0; q < PS_PER; ++q) {
+      const uint32_t x = (uint32_t)(q * PS_THREADS + tid);
+      from[q] = 0xFFFFu;
+      if (x < n) {
+        const uint32_t d = (gk[x] - kmin) >> sh;
+        if (cur[d] - bst[d] > (uint32_t)PS_BIG) from[q] = fpos[x];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PS_PER; ++q) {
+      const uint32_t x = (uint32_t)(q * PS_THREADS + tid);
+      if (from[q] != 0xFFFFu) fpos[from[q]] = (uint16_t)x;
+    }
+    __syncthreads();
+  }
   // 4. rank inside the bucket on (key, id) gives the final position. Slot p
   //    is ranked by thread p mod 1024, so neighbouring lanes walk the same
   //    bucket in step (broadcast reads): a bucket can hold hundreds of
@@ -334,6 +434,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     const uint32_t kp = gk[p], ip = gi[p];
     const uint32_t d = (kp - kmin) >> sh;
     const uint32_t b0 = bst[d], b1 = cur[d];
+    if (b1 - b0 > (uint32_t)PS_BIG) continue;  // sorted by the network above
     uint32_t rank = 0, i = b0;
     for (; i + 4 <= b1; i += 4) {  // four entries' loads in flight per step
       uint32_t k2[4], i2[4];
@@ -352,14 +453,13 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     fpos[p] = (uint16_t)(b0 + rank);
   }
   __syncthreads();
-  // each record's id moves from its bucket slot (gi) to its final position
-  // in gk (the keys are no longer needed)
+  // each record's id moves to its final position in gk (the keys are no
+  // longer needed)
 #pragma unroll
   for (int q = 0; q < PS_PER; ++q) {
     if ((uint32_t)(q * PS_THREADS + tid) < n) {
-      const uint32_t slot = pos[q];
-      pos[q] = fpos[slot];
-      gk[pos[q]] = gi[slot];
+      pos[q] = fpos[pos[q]];
+      gk[pos[q]] = ir[q];
     }
   }
   __syncthreads();

@@ -111,6 +111,35 @@ def test_bin_sort_prefix_bitexact(ctx, orc, seed, m, W, H, R):
     z = np.cbrt(0.125 + rng.random(m) * (64 - 0.125)).astype(np.float32)
     z[rng.random(m) < 0.05] = np.float32(1.0)  # exact ties
     key = np.where(key == 0xFFFFFFFF, key, z.view(np.uint32)).astype(np.uint32)
+    _prefix_case(ctx, orc, seed, m, W, H, R, rect, key)
+
+
+@pytest.mark.parametrize("sizes", [(30, 400, 700, 1500), (385, 2000, 4500), (4200, 4300), (9000,)])
+def test_bin_sort_prefix_tie_clusters(ctx, orc, sizes):
+    """Records at exactly one depth (a surface facing the camera) fill one
+    sort bucket: clusters of assorted sizes, below and above the 4096 records
+    from which psort sorts a bucket with a network (two such buckets at once
+    included), among spread keys and nearly equal ones; the lists must still
+    be the stable sort bit for bit."""
+    seed, W, H = 31, 320, 240
+    m = 20000
+    rect, key = synth.bin_inputs(seed, m, W, H, max_tiles=4)
+    rng = np.random.default_rng(seed)
+    z = np.cbrt(0.125 + rng.random(m) * (64 - 0.125)).astype(np.float32)
+    perm = rng.permutation(np.nonzero(key != 0xFFFFFFFF)[0])  # clusters of visible records only
+    o = 0
+    for c, size in enumerate(sizes):
+        zc = np.float32(0.6 + 0.05 * c)
+        z[perm[o:o + size]] = zc
+        # a few keys one ulp around the cluster
+        z[perm[o + size:o + size + 8]] = np.nextafter(zc, np.float32(9), dtype=np.float32)
+        o += size + 8
+    key = np.where(key == 0xFFFFFFFF, key, z.view(np.uint32)).astype(np.uint32)
+    R = int(sum(sizes)) + 600
+    _prefix_case(ctx, orc, seed, m, W, H, R, rect, key)
+
+
+def _prefix_case(ctx, orc, seed, m, W, H, R, rect, key):
     sel, hist = _prefix_selection(key, R)
     g = synth.static_gaussians(synth.rng_for(seed), m, W, H)
     views, pipe, gt, gst = make_pipeline(ctx, g, [synth.camera(W, H)], capacity=m * 36 + 1024, max_rank=R)
