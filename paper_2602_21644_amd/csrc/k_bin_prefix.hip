@@ -18,7 +18,8 @@
 //   psort:  one 1024-thread workgroup per view gathers the segments into
 //           registers, sorts them on (key, id) in LDS (counting pass on the top
 //           12 bits of the key range, then each record's rank inside its
-//           bucket), writes the sorted ids and rects and the view's instance
+//           bucket, or a bitonic network for a bucket of thousands of
+//           records), writes the sorted ids and rects and the view's instance
 //           total (the sum of the rect areas);
 //   ptiles: a workgroup per 2x2 block of tiles keeps, in order, the sorted
 //           records that meet the block (in LDS) and finds where each of its
@@ -336,15 +337,15 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     }
   }
   __syncthreads();
-  // 4a. Buckets of more than PS_BIG records (many records at nearly one
-  //     depth, such as a large surface facing the camera) are sorted in place on
-  //     (key, id) by one segmented bitonic network: every bucket's merges
-  //     run ascending (the first stage of each compares mirrored positions),
-  //     so the positions past a bucket's end act as +inf and their pairs are
-  //     skipped, and all such buckets advance through the same stages.
-  //     Ranking inside them record by record would take time quadratic in
-  //     their size. fpos carries each record's scatter slot through the
-  //     network and then maps the slot to its final position.
+  // 4. Buckets of more than PS_BIG records (many records at nearly one
+  //    depth, such as a large surface facing the camera) are sorted in place
+  //    on (key, id) by one segmented bitonic network: every bucket's merges
+  //    run ascending (the first stage of each compares mirrored positions),
+  //    so the positions past a bucket's end act as +inf and their pairs are
+  //    skipped, and all such buckets advance through the same stages.
+  //    Ranking inside them record by record would take time quadratic in
+  //    their size. fpos carries each record's scatter slot through the
+  //    network and then maps the slot to its final position.
   const uint32_t nbig = s_nbig;
   if (nbig > 0) {  // uniform
     if (tid == 0) {
@@ -424,7 +425,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     }
     __syncthreads();
   }
-  // 4. rank inside the bucket on (key, id) gives the final position. Slot p
+  // 5. In the other buckets the rank on (key, id) gives the final position. Slot p
   //    is ranked by thread p mod 1024, so neighbouring lanes walk the same
   //    bucket in step (broadcast reads): a bucket can hold hundreds of
   //    entries (a surface facing the camera puts many Gaussians at one
