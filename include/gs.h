@@ -78,9 +78,10 @@ typedef struct gs_views {
   int32_t n_views;              /* 1 .. GS_MAX_VIEWS */
   int32_t n_scenes;             /* >= 1 */
   int64_t n_gaussians;          /* total Gaussians of all scenes (= gs_gaussians.n);
-                                   0 is allowed: the array pointers of every call
-                                   sized by it (m = 0 records included) may be
-                                   NULL, and the image is the background */
+                                   0 is allowed in gs_project, gs_bin_sort, the
+                                   render and loss calls and gs_render_bwd: their
+                                   arrays sized by it (m = 0 records included)
+                                   may be NULL, and the image is the background */
   const gs_camera* cams_host;   /* [host] V cameras: sizes (and values) */
   const gs_camera* cams_dev;    /* V cameras read by the kernels; poses may be
                                    updated in place between graph replays */
