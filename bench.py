@@ -42,10 +42,10 @@ FLOPS_PER_PAIR = {"render_fwd_kernel": 28, "render_bwd_kernel": 54}
 # the counters are scaled by what they read for a 256 MiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0)
 PMC_TRAFFIC = {
-    "render_bwd_kernel<64>": {"fetch_kib": 10446.8, "write_kib": 60457.6,
-                              "sha256": "cc6fb4f9e9a4a98254a0b77c2fdade0d61edaf9dcb9132499e1b85f3777bfa99"},
-    "render_bwd_kernel<32>": {"fetch_kib": 10447.5, "write_kib": 60467.4,
-                              "sha256": "cc6fb4f9e9a4a98254a0b77c2fdade0d61edaf9dcb9132499e1b85f3777bfa99"},
+    "render_bwd_kernel<64>": {"fetch_kib": 10424.3, "write_kib": 60458.2,
+                              "sha256": "84df235f5b401b14f8f7c6a538a2265db34bf945b90f94389e674129150004c9"},
+    "render_bwd_kernel<32>": {"fetch_kib": 10374.1, "write_kib": 60464.9,
+                              "sha256": "84df235f5b401b14f8f7c6a538a2265db34bf945b90f94389e674129150004c9"},
 }
 PMC_SCALE = {"fetch": 2.0, "write": 1.0}
 

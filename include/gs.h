@@ -165,6 +165,12 @@ typedef struct gs_bins {
   int32_t* truncated;     /* [1] required when max_rank > 0, owned by the library:
                              bit v is set by gs_bin_sort when view v's lists leave
                              out a visible record, and read by gs_render_fwd. */
+  int32_t* sticky;        /* [2] optional (NULL skips): gs_bin_sort sets [0] to 1 when
+                             the lists overflow, gs_bin_sort and gs_render_fwd set
+                             [1] to 1 when `incomplete` is raised; the library
+                             never clears them, so across the replays of a
+                             captured loop they record whether any iteration
+                             was not exact (the caller clears them) */
 } gs_bins;
 
 /* Rendered maps (planar, see layouts). */
@@ -597,9 +603,13 @@ typedef struct gs_adam_group {
 typedef struct gs_adam_params {
   float beta1, beta2, eps;
   int32_t step;            /* 1-based step count of the bias correction */
-  const int32_t* step_dev; /* nullable, device: when set the step count is read
+  int32_t* step_dev;       /* nullable, device: when set the step count is read
                               from here at run time (a captured graph replays
-                              with the caller advancing it); `step` is ignored */
+                              with it advancing); `step` is ignored */
+  int32_t advance;         /* with step_dev: 1 adds one to *step_dev before the
+                              step (inside the Adam kernel when it is a single
+                              workgroup), so a replayed graph advances its own
+                              count; 0 reads it as it is */
 } gs_adam_params;
 #define GS_ADAM_MAX_GROUPS 8
 /* Adam (Kingma and Ba 2015) on up to GS_ADAM_MAX_GROUPS device arrays in one

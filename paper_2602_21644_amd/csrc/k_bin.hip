@@ -207,7 +207,8 @@ __global__ __launch_bounds__(GS_BLOCK) void bin_ranges_kernel(ViewTab tab, BinTa
                                                               int32_t* __restrict__ incomplete,
                                                               const uint32_t* __restrict__ sorted,
                                                               const uint32_t* __restrict__ key,
-                                                              int32_t* __restrict__ trunc) {
+                                                              int32_t* __restrict__ trunc,
+                                                              int32_t* __restrict__ sticky) {
   const int t = blockIdx.x * GS_BLOCK + threadIdx.x;
   if (t < tab.ntiles) {
     const int v = view_of_tile(tab, t);
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(GS_BLOCK) void bin_ranges_kernel(ViewTab tab, BinTa
     tile_start[tab.ntiles] = (uint32_t)tot;
     *n_inst = tot;
     *overflow = tot > capacity ? 1 : 0;
+    if (sticky && tot > capacity) atomicOr(&sticky[0], 1);
     if (incomplete) *incomplete = 0;
     if (trunc) {
       // a view binned only its first nlim sorted records leaves out a visible
@@ -425,7 +427,8 @@ gs_status launch_bin_sort(gs_ctx* ctx, const ViewTab& tab, const BinTab& bt, con
   if (st != GS_OK) return st;
   GS_LAUNCH(ctx, bin_ranges_kernel, dim3((tab.ntiles + GS_BLOCK) / GS_BLOCK), dim3(GS_BLOCK), 0, s, tab, bt, cm,
                      total, bins->capacity, bins->tile_start, bins->n_instances, bins->overflow, bins->incomplete,
-                     bins->sorted_ids, proj->depth_key, bins->max_rank > 0 ? bins->truncated : nullptr);
+                     bins->sorted_ids, proj->depth_key, bins->max_rank > 0 ? bins->truncated : nullptr,
+                     bins->sticky);
   GS_LAUNCH(ctx, bin_scatter_kernel, dim3(maxchunk, tab.nv), dim3(GS_BLOCK), lds, s, tab, bt,
                      bins->sorted_ids, (const int2*)proj->rect, proj->depth_key, cm, bins->overflow,
                      bins->gauss_id);

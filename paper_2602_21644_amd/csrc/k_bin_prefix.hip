@@ -198,7 +198,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
     const uint32_t* __restrict__ seg_id, const int2* __restrict__ seg_rect, uint32_t* __restrict__ hist,
     uint32_t* __restrict__ sorted_ids, int2* __restrict__ srect, uint32_t* __restrict__ view_total,
     uint32_t* __restrict__ nsel_out, int32_t* __restrict__ incomplete, int32_t* __restrict__ trunc,
-    const uint32_t* __restrict__ nvis) {
+    const uint32_t* __restrict__ nvis, int32_t* __restrict__ sticky) {
   extern __shared__ uint32_t s_dyn[];
   uint32_t* gk = s_dyn;              // [PS_CAP] keys grouped by bucket; later the difference array
   uint32_t* gi = gk + PS_CAP;        // [PS_CAP] ids
@@ -244,6 +244,7 @@ __global__ __launch_bounds__(PS_THREADS) void psort_kernel(
       nsel_out[v] = 0;
       *incomplete = 1;
       atomicOr(trunc, 1 << v);
+      if (sticky) atomicOr(&sticky[1], 1);
     }
     return;
   }
@@ -507,7 +508,8 @@ __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const u
                                                             uint32_t* __restrict__ tile_start,
                                                             uint32_t* __restrict__ out_ids,
                                                             int64_t* __restrict__ n_inst,
-                                                            int32_t* __restrict__ overflow) {
+                                                            int32_t* __restrict__ overflow,
+                                                            int32_t* __restrict__ sticky) {
   __shared__ uint32_t s_keep[PS_CAP];
   __shared__ uint32_t s_cnt[4];
   __shared__ uint32_t s_front[4][4];  // [wave][tile of the block]
@@ -585,6 +587,7 @@ __global__ __launch_bounds__(PT_THREADS) void ptiles_kernel(ViewTab tab, const u
     tile_start[tab.ntiles] = all;
     *n_inst = all;
     *overflow = ovf ? 1 : 0;
+    if (sticky && ovf) atomicOr(&sticky[0], 1);
   }
   if (ovf) return;
   uint32_t* out = out_ids + start;
@@ -695,10 +698,11 @@ gs_status launch_bin_prefix(gs_ctx* ctx, const ViewTab& tab, const gs_camera* ca
             (const int2*)proj->rect, bins->max_rank, L.nb_max, cams, gsrc, (float4*)proj->rec, seg_key, seg_id,
             seg_rect, cnt, bins->overflow, bins->incomplete, bins->truncated, nvis, proj->keys_only ? 1 : 0);
   GS_LAUNCH(ctx, psort_kernel, dim3(tab.nv), dim3(PS_THREADS), PS_LDS, s, tab, L.nb_max, cnt, seg_key, seg_id,
-            seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete, bins->truncated, nvis);
+            seg_rect, proj->key_hist, bins->sorted_ids, srect, vtot, nsel, bins->incomplete, bins->truncated, nvis,
+            bins->sticky);
   int nblk = 1;
   for (int v = 0; v < tab.nv; ++v) nblk = max(nblk, ((tab.gx[v] + 1) >> 1) * ((tab.gy[v] + 1) >> 1));
   GS_LAUNCH(ctx, ptiles_kernel, dim3(nblk, tab.nv), dim3(PT_THREADS), 0, s, tab, vtot, nsel, bins->sorted_ids, srect, bins->capacity, bins->tile_start, bins->gauss_id, bins->n_instances,
-            bins->overflow);
+            bins->overflow, bins->sticky);
   return gs_check_launch(ctx, "bin_sort (prefix)");
 }

@@ -21,7 +21,9 @@ struct AdamTab {
   float lr[GS_ADAM_MAX_GROUPS];
   int ng;
   float b1, b2, eps, c1, c2;  // c1 = 1 / (1 - b1^step), c2 = 1 / (1 - b2^step)
-  const int32_t* step_dev;    // when set, c1 and c2 come from the device step count
+  int32_t* step_dev;          // when set, c1 and c2 come from the device step count
+  int bump;                   // one-workgroup launch: advance *step_dev by one first
+  int small;                  // every group fits one tile: one workgroup does them all
 };
 
 constexpr int ADAM_PER = 4;
@@ -35,17 +37,11 @@ __device__ __forceinline__ void adam_one(const AdamTab& t, float c1, float c2, f
   p -= lr * mh / (sqrtf(vh) + t.eps);
 }
 
-__global__ __launch_bounds__(GS_BLOCK) void adam_kernel(AdamTab t) {
-  float c1 = t.c1, c2 = t.c2;
-  if (t.step_dev) {
-    const double s = (double)max(1, *t.step_dev);
-    c1 = (float)(1.0 / (1.0 - pow((double)t.b1, s)));
-    c2 = (float)(1.0 / (1.0 - pow((double)t.b2, s)));
-  }
-  const int64_t blk = blockIdx.x;
-  int gi = 0;
-  while (gi + 1 < t.ng && blk >= t.blk0[gi + 1]) ++gi;
-  const int64_t i0 = (blk - t.blk0[gi]) * ADAM_TILE + (int64_t)threadIdx.x * ADAM_PER;
+// Advances the device step count of a multi-workgroup Adam launch.
+__global__ void step_advance_kernel(int32_t* step) { *step += 1; }
+
+// One tile of group gi: ADAM_PER elements per thread from element i0.
+__device__ __forceinline__ void adam_tile(const AdamTab& t, float c1, float c2, int gi, int64_t i0) {
   const int64_t n = t.n[gi];
   if (i0 >= n) return;
   float* P = t.param[gi];
@@ -73,6 +69,30 @@ __global__ __launch_bounds__(GS_BLOCK) void adam_kernel(AdamTab t) {
       Vv[i] = v;
     }
   }
+}
+
+__global__ __launch_bounds__(GS_BLOCK) void adam_kernel(AdamTab t) {
+  float c1 = t.c1, c2 = t.c2;
+  if (t.step_dev) {
+    const int32_t s0 = *t.step_dev + t.bump;
+    const double s = (double)max(1, s0);
+    c1 = (float)(1.0 / (1.0 - pow((double)t.b1, s)));
+    c2 = (float)(1.0 / (1.0 - pow((double)t.b2, s)));
+    if (t.bump) {
+      // the only workgroup: every thread has read the count before it moves
+      __syncthreads();
+      if (threadIdx.x == 0) *t.step_dev = s0;
+    }
+  }
+  if (t.small) {
+    // every group fits one tile: this single workgroup walks them in turn
+    for (int gi = 0; gi < t.ng; ++gi) adam_tile(t, c1, c2, gi, (int64_t)threadIdx.x * ADAM_PER);
+    return;
+  }
+  const int64_t blk = blockIdx.x;
+  int gi = 0;
+  while (gi + 1 < t.ng && blk >= t.blk0[gi + 1]) ++gi;
+  adam_tile(t, c1, c2, gi, (blk - t.blk0[gi]) * ADAM_TILE + (int64_t)threadIdx.x * ADAM_PER);
 }
 
 // T <- Exp(delta) T for view v; delta zeroed.
@@ -159,6 +179,8 @@ gs_status gs_adam_step(gs_ctx* ctx, const gs_adam_group* groups, int32_t n_group
   t.c1 = (float)(1.0 / (1.0 - pow((double)params->beta1, st)));
   t.c2 = (float)(1.0 / (1.0 - pow((double)params->beta2, st)));
   t.step_dev = params->step_dev;
+  t.bump = 0;
+  t.small = 0;
   int64_t blocks = 0;
   for (int i = 0; i < n_groups; ++i) {
     const gs_adam_group& g = groups[i];
@@ -174,7 +196,18 @@ gs_status gs_adam_step(gs_ctx* ctx, const gs_adam_group* groups, int32_t n_group
     blocks += (g.n + ADAM_TILE - 1) / ADAM_TILE;
   }
   t.blk0[n_groups] = blocks;
-  if (blocks == 0) return GS_OK;
+  if (blocks > 1 && blocks == n_groups) {
+    // small groups (a pose twist): one workgroup walks all of them
+    t.small = 1;
+    blocks = 1;
+  }
+  if (params->advance && params->step_dev) {
+    if (blocks == 1)
+      t.bump = 1;  // the kernel advances the count itself
+    else
+      GS_LAUNCH(ctx, step_advance_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, params->step_dev);
+  }
+  if (blocks == 0) return gs_check_launch(ctx, "adam_step");
   GS_LAUNCH(ctx, adam_kernel, dim3((unsigned)blocks), dim3(GS_BLOCK), 0, (hipStream_t)stream, t);
   return gs_check_launch(ctx, "adam_step");
 }

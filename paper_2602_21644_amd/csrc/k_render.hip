@@ -80,7 +80,7 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
     const uint32_t* __restrict__ tile_start, const int32_t* __restrict__ overflow, const int32_t* __restrict__ trunc,
     float bg0, float bg1, float bg2, float* __restrict__ outC, float* __restrict__ outD, float* __restrict__ outM,
     float* __restrict__ outT, uint32_t* __restrict__ nlast, uint32_t* __restrict__ tile_work,
-    int32_t* __restrict__ incomplete, int cull, LossArgs la) {
+    int32_t* __restrict__ incomplete, int32_t* __restrict__ sticky, int cull, LossArgs la) {
   // slot BATCH is a zero-opacity entry that pads a wave's last group of four
   __shared__ float4 s_a[BATCH + 1], s_b[BATCH + 1], s_c[BATCH + 1];
   __shared__ uint8_t s_mask[BATCH];
@@ -233,7 +233,10 @@ __global__ __launch_bounds__(GS_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) v
   // lets light through
   if (trunc && ((*trunc >> tc.v) & 1)) {
     const int active = __syncthreads_count(!done);
-    if (exhausted && active > 0 && threadIdx.x == 0) atomicOr(incomplete, 1);
+    if (exhausted && active > 0 && threadIdx.x == 0) {
+      atomicOr(incomplete, 1);
+      if (sticky) atomicOr(&sticky[1], 1);
+    }
   }
   double lsum = 0.0;
   if (tc.inside) {
@@ -685,7 +688,7 @@ gs_status launch_render_fwd(gs_ctx* ctx, const ViewTab& tab, const gs_proj* proj
   GS_LAUNCH(ctx, render_fwd_kernel<BATCH>, grid, block, 0, s, tab, rec, bins->gauss_id, bins->tile_start,      \
                      bins->overflow, bins->max_rank > 0 ? bins->truncated : nullptr, bg[0], bg[1], bg[2],       \
                      img->color, img->depth, img->mp, img->T, img->n_last, img->tile_work, bins->incomplete,   \
-                     ctx->wave_cull, la)
+                     bins->sticky, ctx->wave_cull, la)
   switch (ctx->render_batch) {
     case 64: GS_FWD(64); break;
     case 128: GS_FWD(128); break;

@@ -62,7 +62,7 @@ class Proj(ctypes.Structure):
 class Bins(ctypes.Structure):
     _fields_ = [("capacity", c_int64)] + [(k, c_void_p) for k in ("gauss_id", "tile_start", "sorted_ids",
                                                                  "n_instances", "overflow", "incomplete")] + [
-        ("max_rank", c_int64), ("truncated", c_void_p)]
+        ("max_rank", c_int64), ("truncated", c_void_p), ("sticky", c_void_p)]
 
 
 class Image(ctypes.Structure):
@@ -111,7 +111,8 @@ class AdamGroup(ctypes.Structure):
 
 
 class AdamParams(ctypes.Structure):
-    _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("step", c_int32), ("step_dev", c_void_p)]
+    _fields_ = [("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("step", c_int32), ("step_dev", c_void_p),
+                ("advance", c_int32)]
 
 
 class EdgePair(ctypes.Structure):
@@ -456,16 +457,17 @@ def gs_mlp_fwd(ctx, mlp, x, y, P, stream=None):
 ADAM_MAX_GROUPS = 8
 
 
-def gs_adam_step(ctx, groups, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+def gs_adam_step(ctx, groups, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None, advance=False):
     """groups: list of (param, grad, m, v, lr) float32 device tensors of equal
-    size; step: the 1-based step count, or an int32 device tensor holding it."""
+    size; step: the 1-based step count, or an int32 device tensor holding it
+    (with advance, the call adds one to it before the step)."""
     arr = (AdamGroup * len(groups))()
     for i, (p_, g_, m_, v_, lr) in enumerate(groups):
         arr[i] = AdamGroup(ptr(p_), ptr(g_), ptr(m_), ptr(v_), p_.numel(), float(lr))
     if isinstance(step, torch.Tensor):
-        prm = AdamParams(beta1, beta2, eps, 0, ptr(step))
+        prm = AdamParams(beta1, beta2, eps, 0, ptr(step), int(bool(advance)))
     else:
-        prm = AdamParams(beta1, beta2, eps, int(step), None)
+        prm = AdamParams(beta1, beta2, eps, int(step), None, 0)
     ctx.check(lib().gs_adam_step(ctx.h, arr, len(groups), ctypes.byref(prm), _stream(stream)), "gs_adam_step")
 
 
@@ -635,15 +637,20 @@ class Pipeline:
         self.ws_bwd = torch.zeros(gs_workspace_size(ctx, views.s, GS_OP_RENDER_BWD), dtype=torch.uint8, device=dev)
         self.ws_loss = torch.zeros(gs_workspace_size(ctx, views.s, GS_OP_LOSS), dtype=torch.uint8, device=dev)
         self.lp = LossParams(0.9, 0.1, 1e-6, 0, 0)
-        # sticky copies of the overflow and incomplete flags, kept across
-        # iterations when `sticky` is set (the library resets its own flags
-        # in every gs_bin_sort)
+        # sticky overflow and incomplete flags (gs_bins.sticky), which the
+        # library sets and never clears, kept across iterations while
+        # `sticky` is set (the library resets its own flags in every
+        # gs_bin_sort)
+        self.flags = torch.zeros(2, dtype=torch.int32, device=dev)
         self.sticky = False
-        self.flags = torch.zeros(2, dtype=torch.int64, device=dev)
 
-    def _note_flags(self):
-        if self.sticky:
-            torch.maximum(self.flags, self.counters[1:3], out=self.flags)
+    @property
+    def sticky(self):
+        return self.bins.sticky is not None
+
+    @sticky.setter
+    def sticky(self, on):
+        self.bins.sticky = ptr(self.flags) if on else None
 
     def raise_if_failed(self, stream=None):
         """Synchronises and raises GSError when an iteration since the last
@@ -675,7 +682,6 @@ class Pipeline:
         gs_project(self.ctx, self.views.s, g, self.proj, stream)
         gs_bin_sort(self.ctx, self.views.s, g, self.proj, self.bins, self.ws_bin, stream)
         gs_render_fwd(self.ctx, self.views.s, g, self.proj, self.bins, self.bg, self.img, stream)
-        self._note_flags()
 
     def loss_and_grads(self, target_color, target_depth, stream=None):
         self._tgt_keep = (target_color, target_depth)
@@ -691,7 +697,6 @@ class Pipeline:
         gs_bin_sort(self.ctx, self.views.s, g, self.proj, self.bins, self.ws_bin, stream)
         gs_render_fwd_loss(self.ctx, self.views.s, g, self.proj, self.bins, self.bg, self.img, tgt, self.lp,
                            self.loss, self.pg, self.ws_loss, stream)
-        self._note_flags()
 
     def backward(self, g: Gaussians, grads: Grads, stream=None):
         gs_render_bwd(self.ctx, self.views.s, g, self.proj, self.bins, self.img, self.pg, self.bg, grads,

@@ -91,11 +91,11 @@ class Adam:
 
     def step(self, grads, stream=None):
         """Graph-capturable: the step count advances on the device."""
-        self.count.add_(1)
         groups = [(p, g, m, v, lr) for (p, lr), g, m, v in zip(self.params, grads, self.m, self.v)]
         for i in range(0, len(groups), gs.ADAM_MAX_GROUPS):
+            # the first call advances the count, the rest read the advanced one
             gs.gs_adam_step(self.ctx, groups[i:i + gs.ADAM_MAX_GROUPS], self.count, self.betas[0], self.betas[1],
-                            self.eps, stream)
+                            self.eps, stream, advance=i == 0)
 
 
 def choose_rank(ctx, views, gst, n, start=256):
@@ -149,7 +149,8 @@ class Tracker:
         self.dpose = torch.zeros(6, dtype=torch.float32, device=dev)
         self.adam = Adam(ctx, [(self.delta[:3], lr_rho), (self.delta[3:], lr_phi)])
         self.grs = gs.grads_struct(None, self.dpose, pose_only=True)
-        self.flags = torch.zeros(2, dtype=torch.int64, device=dev)  # sticky overflow, incomplete
+        self.pipe.sticky = True  # the library records overflow / incomplete across the replays
+        self.flags = self.pipe.flags
         self.use_graph = use_graph
         self.graph = None
         self.tc = self.td = None
@@ -157,7 +158,6 @@ class Tracker:
     def _iteration(self):
         p = self.pipe
         p.forward_loss(self.gst, self.tc, self.td)
-        torch.maximum(self.flags, p.counters[1:3], out=self.flags)
         p.backward(self.gst, self.grs)
         self.adam.step([self.dpose[:3], self.dpose[3:]])
         gs.gs_pose_update(self.ctx, self.views, self.delta)
@@ -200,7 +200,6 @@ class Tracker:
                 self._iteration()
         # loss at the final pose
         self.pipe.forward_loss(self.gst, self.tc, self.td)
-        torch.maximum(self.flags, self.pipe.counters[1:3], out=self.flags)
         torch.cuda.synchronize()
         exact = int(self.flags.sum()) == 0
         return self.views.pose(0), float(self.pipe.loss[0]), exact

@@ -47,6 +47,49 @@ def test_adam_step_parity(ctx):
     assert float(base[4096]) == float(torch.from_numpy(np.random.default_rng(0).normal(size=5003).astype(np.float32))[4096])
 
 
+@pytest.mark.parametrize("sizes", [(6,), (3, 3), (3000,), (1000, 1100)])
+def test_adam_step_advances_its_count(ctx, sizes):
+    """advance=True adds one to the device step count before each step: in
+    the Adam kernel itself when one workgroup does the whole step (one small
+    group; or several one-tile groups, as the pose twist's two halves with
+    their two learning rates), in a separate launch otherwise. The same
+    results as host counts 1..4, and the count ends at 4, also when replayed
+    from a captured graph."""
+    rng = np.random.default_rng(1)
+    lrs = [1e-2, 3e-2]
+    p0 = [rng.normal(size=n).astype(np.float32) for n in sizes]
+    grads = [[torch.from_numpy(rng.normal(size=n).astype(np.float32)).cuda() for n in sizes] for _ in range(4)]
+    ref = [(p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)) for p in p0]
+    for k in range(1, 5):
+        ref = [oopt.adam_step(r[0], torch_np(grads[k - 1][i]), r[1], r[2], lrs[i], k) for i, r in enumerate(ref)]
+    for graph in (False, True):
+        ps = [torch.from_numpy(p).cuda() for p in p0]
+        ms, vs = [torch.zeros_like(p) for p in ps], [torch.zeros_like(p) for p in ps]
+        gs_ = [torch.zeros_like(p) for p in ps]
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        step = lambda: gs.gs_adam_step(ctx, [(ps[i], gs_[i], ms[i], vs[i], lrs[i]) for i in range(len(sizes))], count,
+                                       advance=True)
+        if graph:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            cg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cg, stream=s):
+                step()
+            torch.cuda.synchronize()
+        for k in range(4):
+            for i in range(len(sizes)):
+                gs_[i].copy_(grads[k][i])
+            if graph:
+                cg.replay()
+            else:
+                step()
+            torch.cuda.synchronize()
+        assert int(count[0]) == 4, (sizes, graph)
+        for i in range(len(sizes)):
+            np.testing.assert_allclose(torch_np(ps[i]), ref[i][0], rtol=1e-5, atol=1e-6)
+
+
 def test_pose_update_parity(ctx):
     """Exp(delta) T for twists from zero to one radian; delta is cleared."""
     rng = np.random.default_rng(1)
