@@ -127,11 +127,16 @@ def test_backward_after_overflow(ctx, max_rank):
     tc, td, tcd, tdd = _targets(3, cam["width"], cam["height"])
     pipe.loss.fill_(NAN)
     pipe.img_T.fill_(7.0)
+    pipe.sticky = True  # gs_bins.sticky records the overflow
+    pipe.clear_flags()
     pipe.forward_loss(gst, tcd, tdd)
     over, n_inst, _ = pipe.check()
     assert over and n_inst > 100
     assert float(pipe.loss[0]) == 0.0
     assert torch.all(pipe.img_T == 7.0)
+    assert pipe.flags.tolist() == [1, 0]
+    with pytest.raises(gs.GSError, match="capacity"):
+        pipe.raise_if_failed()
     _assert_zero_backward(pipe, views, gst, n)
     # pose-only under overflow: zero twist, no gradient array touched
     pose = torch.full((6,), NAN, device="cuda")
